@@ -1,0 +1,242 @@
+/*
+ * FP64 CPU oracle for one GPU's slice of the two-particle Green's function
+ * (G4, the paper's G_t) accumulation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the package smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code, header
+ * or table with the HIP library; it is the plain definition written out, entry
+ * by entry, in double precision, with every index computed from cluster
+ * coordinates and integer Matsubara labels (no lookup tables).
+ *
+ * What it computes (per measurement b with weight s_b, for every entry of the
+ * slice):
+ *
+ *   G4_ch(K1, K2, Q) += s_b * T_ch(K1, K2, Q)
+ *
+ *   PH magnetic  T = (Gu-Gd)(K1+Q,K1) (Gu-Gd)(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q)
+ *   PH charge    T = (Gu+Gd)(K1+Q,K1) (Gu+Gd)(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q)
+ *   PP up-down   T = sum_s G_s(Q-K2,Q-K1) G_{-s}(K2,K1)
+ *
+ * The PP term is the paper's Eq. (1) (Background section, "Memory-Bound Issue
+ * in DCA++") with K3 read as the transfer Q.  The particle-hole terms are the
+ * direct-minus-exchange Wick contractions of c+_{K1+Q,s1} c_{K1,s1}
+ * c+_{K2,s2} c_{K2+Q,s2}, weighted by s1*s2 (magnetic) or 1 (charge); the
+ * paper prints only Eq. (1), so these are a reading, pinned by the brute-force
+ * Wick test.  The slice is the paper's distributed G^d_t (Implementation
+ * section, "Distributed G_t in QMC Solver"): a contiguous range of transfer
+ * planes out of the full array.
+ *
+ * Conventions:
+ *   cluster Lx x Ly, momentum index k = ix + Lx*iy, k+q and q-k taken
+ *     coordinate-wise modulo the cluster;
+ *   fermionic n in [-Nw/2, Nw/2-1] (w_n = (2n+1) pi/beta), bosonic m in
+ *     [0, Nwex-1] (nu_m = 2 pi m/beta), so w_n + nu_m = w_{n+m} and
+ *     nu_m - w_n = w_{m-n-1};
+ *   G4 combined index K = k*Nw + (n + Nw/2);
+ *   G window n in [-Nw/2, Nw/2+Nwex-2], Nwg = Nw+Nwex-1, G row/column index
+ *     k*Nwg + (n + Nw/2), G stored row-major, complex interleaved (re, im);
+ *   transfer plane iQ = iq*Nwex + m, q = q_list[iq];
+ *   slice entry ((iQ - q_begin)*N + K2)*N + K1 with N = Nc*Nw.
+ *
+ * Compile: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
+ * No FMA contraction: each product is a plain complex multiply, each sum is
+ * taken in measurement order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int lx, ly;          /* cluster extent */
+    int nw;              /* G4 fermionic frequencies (even, total count) */
+    int nwex;            /* bosonic transfers m = 0..nwex-1 */
+    int nq;              /* number of momentum transfers */
+    const int *q_list;   /* nq momentum indices */
+    long q_begin, q_end; /* slice: planes [q_begin, q_end) of nq*nwex */
+} oracle_shape;
+
+enum { ORACLE_PH_MAGNETIC = 1, ORACLE_PH_CHARGE = 2, ORACLE_PP_UPDOWN = 4 };
+
+typedef struct { double re, im; } cplx;
+
+static cplx c_mul(cplx a, cplx b) {
+    cplx r;
+    r.re = a.re * b.re - a.im * b.im;
+    r.im = a.re * b.im + a.im * b.re;
+    return r;
+}
+static cplx c_add(cplx a, cplx b) { cplx r = {a.re + b.re, a.im + b.im}; return r; }
+static cplx c_sub(cplx a, cplx b) { cplx r = {a.re - b.re, a.im - b.im}; return r; }
+
+static int wrap(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
+
+/* momentum k + q: add the lattice coordinates, wrap around the cluster */
+static int mom_add(const oracle_shape *s, int k, int q) {
+    int ix = k % s->lx, iy = k / s->lx;
+    int jx = q % s->lx, jy = q / s->lx;
+    return wrap(ix + jx, s->lx) + s->lx * wrap(iy + jy, s->ly);
+}
+
+/* momentum q - k */
+static int mom_sub(const oracle_shape *s, int q, int k) {
+    int ix = k % s->lx, iy = k / s->lx;
+    int jx = q % s->lx, jy = q / s->lx;
+    return wrap(jx - ix, s->lx) + s->lx * wrap(jy - iy, s->ly);
+}
+
+/* G row/column index of (momentum k, fermionic Matsubara label n) */
+static long g_index(const oracle_shape *s, int k, int n) {
+    int nwg = s->nw + s->nwex - 1;
+    int loc = n + s->nw / 2;
+    if (loc < 0 || loc >= nwg) {
+        fprintf(stderr, "oracle: frequency n=%d outside the G window\n", n);
+        abort();
+    }
+    return (long)k * nwg + loc;
+}
+
+static cplx g_at(const double *g, long ng, long r, long c) {
+    const double *p = g + 2 * (r * ng + c);
+    cplx v = {p[0], p[1]};
+    return v;
+}
+
+/* T_ch for one measurement (G_up, G_dn of that measurement) and one entry */
+static cplx entry_term(const oracle_shape *s, int channel, const double *gu, const double *gd,
+                       long ng, long iQ, long K2, long K1) {
+    int nw = s->nw;
+    int iq = (int)(iQ / s->nwex), m = (int)(iQ % s->nwex);
+    int q = s->q_list[iq];
+    int k1 = (int)(K1 / nw), n1 = (int)(K1 % nw) - nw / 2;
+    int k2 = (int)(K2 / nw), n2 = (int)(K2 % nw) - nw / 2;
+    long r_k1 = g_index(s, k1, n1), r_k2 = g_index(s, k2, n2);
+    cplx t = {0.0, 0.0};
+    if (channel == ORACLE_PH_MAGNETIC || channel == ORACLE_PH_CHARGE) {
+        long r_k1q = g_index(s, mom_add(s, k1, q), n1 + m);   /* K1 + Q */
+        long r_k2q = g_index(s, mom_add(s, k2, q), n2 + m);   /* K2 + Q */
+        cplx u1 = g_at(gu, ng, r_k1q, r_k1), d1 = g_at(gd, ng, r_k1q, r_k1);
+        cplx u2 = g_at(gu, ng, r_k2, r_k2q), d2 = g_at(gd, ng, r_k2, r_k2q);
+        cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);
+        cplx b = channel == ORACLE_PH_MAGNETIC ? c_sub(u2, d2) : c_add(u2, d2);
+        cplx direct = c_mul(a, b);
+        cplx ex_u = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));
+        cplx ex_d = c_mul(g_at(gd, ng, r_k2, r_k1), g_at(gd, ng, r_k1q, r_k2q));
+        t = c_sub(direct, c_add(ex_u, ex_d));
+    } else if (channel == ORACLE_PP_UPDOWN) {
+        long r_qk1 = g_index(s, mom_sub(s, q, k1), m - n1 - 1); /* Q - K1 */
+        long r_qk2 = g_index(s, mom_sub(s, q, k2), m - n2 - 1); /* Q - K2 */
+        cplx up = c_mul(g_at(gu, ng, r_qk2, r_qk1), g_at(gd, ng, r_k2, r_k1));
+        cplx dn = c_mul(g_at(gd, ng, r_qk2, r_qk1), g_at(gu, ng, r_k2, r_k1));
+        t = c_add(up, dn);
+    }
+    return t;
+}
+
+static int check_shape(const oracle_shape *s, int channel) {
+    if (!s || s->lx < 1 || s->ly < 1 || s->nw < 2 || (s->nw & 1) || s->nwex < 1 || s->nq < 1)
+        return -1;
+    if (!s->q_list || s->q_begin < 0 || s->q_end > (long)s->nq * s->nwex || s->q_begin >= s->q_end)
+        return -1;
+    for (int i = 0; i < s->nq; ++i)
+        if (s->q_list[i] < 0 || s->q_list[i] >= s->lx * s->ly) return -1;
+    if (channel != ORACLE_PH_MAGNETIC && channel != ORACLE_PH_CHARGE && channel != ORACLE_PP_UPDOWN)
+        return -1;
+    return 0;
+}
+
+/*
+ * Accumulate `batch` measurements into the slice g4 (complex interleaved,
+ * (q_end-q_begin)*N*N values).  g_up/g_dn hold batch matrices of Ng x Ng.
+ * If comp is non-NULL the sums are Neumaier-compensated per real component and
+ * comp (same size as g4) holds the running compensation; value = g4 + comp.
+ * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on a bad shape.
+ */
+int oracle_accumulate(const oracle_shape *s, int channel, const double *g_up, const double *g_dn,
+                      const double *sign, int batch, double *g4, double *comp, int nthreads) {
+    if (check_shape(s, channel) || batch < 0 || !g_up || !g_dn || !sign || !g4) return -1;
+    long nc = (long)s->lx * s->ly;
+    long ng = nc * (s->nw + s->nwex - 1);
+    long n = nc * s->nw;
+    long planes = s->q_end - s->q_begin;
+    long rows = planes * n;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    for (int b = 0; b < batch; ++b) {
+        const double *gu = g_up + 2 * (size_t)b * ng * ng;
+        const double *gd = g_dn + 2 * (size_t)b * ng * ng;
+        double sb = sign[b];
+#pragma omp parallel for schedule(dynamic, 4)
+        for (long row = 0; row < rows; ++row) {
+            long iQ = s->q_begin + row / n;
+            long K2 = row % n;
+            for (long K1 = 0; K1 < n; ++K1) {
+                cplx t = entry_term(s, channel, gu, gd, ng, iQ, K2, K1);
+                double x[2] = {sb * t.re, sb * t.im};
+                double *acc = g4 + 2 * (row * n + K1);
+                if (!comp) {
+                    acc[0] += x[0];
+                    acc[1] += x[1];
+                } else {
+                    double *cc = comp + 2 * (row * n + K1);
+                    for (int j = 0; j < 2; ++j) {
+                        double sum = acc[j], tt = sum + x[j];
+                        if (fabs(sum) >= fabs(x[j]))
+                            cc[j] += (sum - tt) + x[j];
+                        else
+                            cc[j] += (x[j] - tt) + sum;
+                        acc[j] = tt;
+                    }
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * Sum over the batch, in measurement order, of s_b * T_ch at `count` slice
+ * entries given by their flattened slice index.  out: count complex values.
+ */
+int oracle_entries(const oracle_shape *s, int channel, const double *g_up, const double *g_dn,
+                   const double *sign, int batch, const int64_t *idx, long count, double *out) {
+    if (check_shape(s, channel) || batch < 0 || !g_up || !g_dn || !sign || (!idx && count) || (!out && count))
+        return -1;
+    long nc = (long)s->lx * s->ly;
+    long ng = nc * (s->nw + s->nwex - 1);
+    long n = nc * s->nw;
+    long total = (s->q_end - s->q_begin) * n * n;
+    for (long j = 0; j < count; ++j)
+        if (idx[j] < 0 || idx[j] >= total) return -1;
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < count; ++j) {
+        long e = idx[j];
+        long K1 = e % n, K2 = (e / n) % n, iQ = s->q_begin + e / (n * n);
+        double re = 0.0, im = 0.0;
+        for (int b = 0; b < batch; ++b) {
+            cplx t = entry_term(s, channel, g_up + 2 * (size_t)b * ng * ng,
+                                g_dn + 2 * (size_t)b * ng * ng, ng, iQ, K2, K1);
+            re += sign[b] * t.re;
+            im += sign[b] * t.im;
+        }
+        out[2 * j] = re;
+        out[2 * j + 1] = im;
+    }
+    return 0;
+}
+
+/* Threads OpenMP would use (for reporting the CPU-baseline core count). */
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,103 @@
+"""ctypes wrapper of the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+PH_MAGNETIC = 1
+PH_CHARGE = 2
+PP_UPDOWN = 4
+
+
+class _Shape(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int), ("ly", ctypes.c_int), ("nw", ctypes.c_int),
+                ("nwex", ctypes.c_int), ("nq", ctypes.c_int),
+                ("q_list", ctypes.POINTER(ctypes.c_int)),
+                ("q_begin", ctypes.c_long), ("q_end", ctypes.c_long)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_accumulate.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, dp, dp, dp,
+                                        ctypes.c_int, dp, dp, ctypes.c_int]
+        L.oracle_accumulate.restype = ctypes.c_int
+        L.oracle_entries.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, dp, dp, dp,
+                                     ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.c_long, dp]
+        L.oracle_entries.restype = ctypes.c_int
+        L.oracle_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _shape(w):
+    q = np.ascontiguousarray(np.asarray(w.qs, dtype=np.int32))
+    s = _Shape(w.lx, w.ly, w.nw, w.nwex, w.nq,
+               q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), w.q0, w.q1)
+    return s, q
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c128(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    assert a.shape == shape, (a.shape, shape)
+    return a
+
+
+def accumulate(w, channel: int, g_up: np.ndarray, g_dn: np.ndarray, sign: np.ndarray,
+               g4: Optional[np.ndarray] = None, comp: Optional[np.ndarray] = None,
+               nthreads: int = 0) -> np.ndarray:
+    """G4 slice (complex128 [planes, N, N]) += sum_b s_b T_channel, in place if given."""
+    sign = np.ascontiguousarray(sign, dtype=np.float64)
+    batch = sign.shape[0]
+    g_up = _c128(g_up, (batch, w.ng, w.ng))
+    g_dn = _c128(g_dn, (batch, w.ng, w.ng))
+    if g4 is None:
+        g4 = np.zeros((w.planes, w.n, w.n), dtype=np.complex128)
+    assert g4.dtype == np.complex128 and g4.flags.c_contiguous and g4.shape == (w.planes, w.n, w.n)
+    if comp is not None:
+        assert comp.dtype == np.complex128 and comp.shape == g4.shape and comp.flags.c_contiguous
+    s, q = _shape(w)
+    rc = lib().oracle_accumulate(ctypes.byref(s), channel, _dp(g_up), _dp(g_dn), _dp(sign), batch,
+                                 _dp(g4), _dp(comp) if comp is not None else None, nthreads)
+    if rc:
+        raise ValueError("oracle_accumulate rejected the shape or arguments")
+    return g4
+
+
+def entries(w, channel: int, g_up: np.ndarray, g_dn: np.ndarray, sign: np.ndarray,
+            idx: np.ndarray) -> np.ndarray:
+    """sum_b s_b T_channel at flattened slice entries idx (complex128 array)."""
+    sign = np.ascontiguousarray(sign, dtype=np.float64)
+    batch = sign.shape[0]
+    g_up = _c128(g_up, (batch, w.ng, w.ng))
+    g_dn = _c128(g_dn, (batch, w.ng, w.ng))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(idx.shape[0], dtype=np.complex128)
+    s, q = _shape(w)
+    rc = lib().oracle_entries(ctypes.byref(s), channel, _dp(g_up), _dp(g_dn), _dp(sign), batch,
+                              idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.shape[0],
+                              _dp(out))
+    if rc:
+        raise ValueError("oracle_entries rejected the shape or arguments")
+    return out
+
+
+def max_threads() -> int:
+    return lib().oracle_max_threads()
