@@ -1,0 +1,230 @@
+/*
+ * g4.h -- C ABI of the MI355X (gfx950) library that accumulates one GPU's
+ * slice of the two-particle Green's function G4 (the paper's G_t) from
+ * streamed single-particle Green's functions G_sigma.
+ *
+ * Paper: "Memory Reduction using a Ring Abstraction over GPU RDMA for
+ * Distributed Quantum Monte Carlo Solver" (arXiv 2105.00027).
+ *   - The update: Background section, "Memory-Bound Issue in DCA++", Eq. (1)
+ *     (particle-particle channel), and its particle-hole counterparts
+ *     (direct minus exchange Wick products; the paper prints only Eq. (1)).
+ *   - The slice: Implementation section, "Distributed G_t in QMC Solver":
+ *     each rank owns an even 1/p part of G_t and must see every G_sigma.
+ *   - The stream of G_sigma buffers: Implementation section, "Pipeline Ring
+ *     Algorithm" (Algorithm 1): a rank updates its part with its own G_sigma,
+ *     then with each buffer received from its left neighbour.
+ *   - Lifetime: G_t is allocated before the measurements and lives until the
+ *     end of the run (Background section, the solver workflow).
+ *
+ * Conventions (all integer maps are exact):
+ *   Cluster lx x ly, Nc = lx*ly momenta, k = ix + lx*iy.  k+q and q-k are
+ *     taken coordinate-wise modulo the cluster.
+ *   Fermionic Matsubara n in [-nw/2, nw/2-1] (nw even), w_n = (2n+1)pi/beta.
+ *   Bosonic transfer m in [0, nwex-1], nu_m = 2 pi m/beta; so
+ *     w_n + nu_m = w_{n+m} and nu_m - w_n = w_{m-n-1}.
+ *   G4 combined index K = k*nw + (n + nw/2), N = Nc*nw.
+ *   G frequency window n in [-nw/2, nw/2+nwex-2], Nwg = nw+nwex-1;
+ *     G row/column index k*Nwg + (n + nw/2), Ng = Nc*Nwg.
+ *   Transfer plane Q = (q, m), flattened iQ = iq*nwex + m, q = q_list[iq],
+ *     NQ = nq*nwex planes in the full G4.
+ *   The slice holds planes [q_begin, q_end); entry ((iQ-q_begin)*N + K2)*N + K1
+ *     of each channel, K1 fastest.
+ *
+ * Per measurement b with weight s_b (the QMC sign, normally +-1):
+ *   PH magnetic  G4 += s_b [ (Gu-Gd)(K1+Q,K1) (Gu-Gd)(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q) ]
+ *   PH charge    G4 += s_b [ (Gu+Gd)(K1+Q,K1) (Gu+Gd)(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q) ]
+ *   PP up-down   G4 += s_b   sum_s G_s(Q-K2,Q-K1) G_{-s}(K2,K1)          (Eq. (1), K3 -> Q)
+ * The values kept are raw signed sums; g4_stats gives the measurement count
+ * and the sum of weights for normalisation.
+ *
+ * Errors: every call returns G4_OK or a negative status, and leaves a
+ * message for g4_last_error() (thread-local).  G4_E_ARG, G4_E_OOM and
+ * G4_E_UNSUPPORTED change nothing.  G4_E_HIP poisons the handle: every
+ * later call on it except g4_destroy returns G4_E_STATE.  Arguments are
+ * validated before any HIP call.
+ *
+ * Threading: a handle is used by one host thread at a time.  Work is
+ * enqueued on the handle's stream; calls return before the GPU finishes
+ * unless documented as synchronous.
+ */
+#ifndef G4_H
+#define G4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define G4_ABI_VERSION 1u
+
+enum {
+    G4_OK = 0,
+    G4_E_ARG = -1,          /* invalid argument or configuration */
+    G4_E_OOM = -2,          /* the slice and its work buffers do not fit */
+    G4_E_HIP = -3,          /* a HIP runtime call failed; handle poisoned */
+    G4_E_STATE = -4,        /* poisoned handle, or call out of order */
+    G4_E_UNSUPPORTED = -5   /* valid request this build does not implement */
+};
+
+/* channels (bitmask) */
+enum { G4_PH_MAGNETIC = 1, G4_PH_CHARGE = 2, G4_PP_UPDOWN = 4 };
+
+/* element type of the G_up / G_dn buffers passed to g4_accumulate */
+enum {
+    G4_IN_C128 = 0,  /* complex double, interleaved (re, im): 16 bytes */
+    G4_IN_C64 = 1    /* complex float, interleaved: 8 bytes */
+};
+
+/* precision of the products */
+enum {
+    G4_PROD_F64 = 0,     /* every product in FP64 */
+    G4_PROD_F32 = 1,     /* G rounded to FP32, products and batch sums in FP32 */
+    G4_PROD_BF16X2 = 2,  /* direct term on MFMA from bf16 hi+lo split operands, exchange FP32 */
+    G4_PROD_F16X2 = 3    /* direct term on MFMA from scaled fp16 hi+lo split operands, exchange FP32 */
+};
+
+/* accumulator held in device memory for every slice entry */
+enum {
+    G4_ACC_C128 = 0,        /* complex double */
+    G4_ACC_C64_KAHAN = 1,   /* complex float value + complex float Kahan compensation */
+    G4_ACC_C64 = 2          /* complex float, uncompensated (a control for drift studies) */
+};
+
+/* how measurements are applied */
+enum {
+    G4_MODE_PLAIN = 0,    /* one kernel pass over the slice per measurement */
+    G4_MODE_BATCHED = 1   /* up to max_batch measurements fused in one pass */
+};
+
+/* flags */
+enum {
+    G4_F_CHECK_FINITE = 1u,   /* g4_accumulate rejects signs that are not finite */
+    G4_F_KERNEL_TIMING = 2u,  /* time every slice-update kernel with HIP events (see g4_stats) */
+    G4_F_GRAPH = 4u,          /* replay each batched step as a captured HIP graph */
+    G4_F_MFMA = 8u            /* batched FP32: direct term on MFMA (otherwise VALU) */
+};
+
+typedef struct g4_config {
+    uint32_t abi_version;     /* G4_ABI_VERSION */
+    int32_t lx, ly;           /* cluster extent, >= 1 each */
+    int32_t nw;               /* G4 fermionic frequencies, even, >= 2 */
+    int32_t nwex;             /* bosonic transfers, >= 1 */
+    int32_t nq;               /* momentum transfers, 1..Nc */
+    const int32_t *q_list;    /* host array of nq distinct momenta in [0,Nc), or NULL for 0..nq-1;
+                                 copied by g4_init_slice */
+    int64_t q_begin, q_end;   /* slice planes, 0 <= q_begin < q_end <= nq*nwex */
+    uint32_t channels;        /* nonzero bitmask of G4_PH_MAGNETIC | G4_PH_CHARGE | G4_PP_UPDOWN */
+    int32_t g_in;             /* G4_IN_* */
+    int32_t prod;             /* G4_PROD_* ; G4_MODE_PLAIN requires G4_PROD_F64 */
+    int32_t acc;              /* G4_ACC_* */
+    int32_t mode;             /* G4_MODE_* */
+    int32_t max_batch;        /* batched: measurements per pass, 1..256 (plain: ignored) */
+    int32_t device;           /* HIP device ordinal */
+    void *stream;             /* hipStream_t to enqueue on, or NULL for a library-owned stream */
+    uint32_t flags;           /* G4_F_* */
+    int32_t tile;             /* rows of K2 frequencies per work tile; 0 = default */
+    double beta;              /* inverse temperature; metadata only */
+} g4_config;
+
+typedef struct g4_slice g4_slice;   /* opaque; owned by the library */
+
+typedef struct g4_stats_t {
+    uint64_t measurements;     /* measurements accumulated since init/reset/load */
+    double sign_sum;           /* sum of their weights */
+    uint64_t launches;         /* slice-update kernel launches */
+    double kernel_ms;          /* summed HIP-event time of those launches (G4_F_KERNEL_TIMING) */
+    uint64_t timed_launches;   /* launches included in kernel_ms */
+    uint64_t entries;          /* entries per channel in the slice */
+    uint32_t channels;         /* channel bitmask */
+    int32_t batch;             /* measurements per pass in use */
+    int32_t tile;              /* K2 rows per tile in use */
+    int32_t variant;           /* kernel variant in use (0 VALU, 1 MFMA direct) */
+} g4_stats_t;
+
+/* Fill *cfg with defaults (magnetic channel, c128, FP64, plain, whole
+ * slice of a 1x1 cluster).  Returns G4_E_ARG for NULL. */
+int g4_config_init(g4_config *cfg);
+
+/* Validate cfg and report entries per channel and the device bytes that
+ * g4_init_slice would allocate.  No HIP call.  Either output may be NULL. */
+int g4_slice_size(const g4_config *cfg, uint64_t *entries_per_channel, uint64_t *device_bytes);
+
+/* Create a slice: validate, check device memory (also against the optional
+ * cap G4_TEST_DEVICE_MEM_LIMIT, in bytes, from the environment), build and
+ * upload the index tables, allocate and zero the accumulators.  Synchronous.
+ * On success *out owns all device memory until g4_destroy. */
+int g4_init_slice(const g4_config *cfg, g4_slice **out);
+
+/* Enqueue the accumulation of `batch` measurements.
+ * G_up, G_dn: DEVICE pointers to batch consecutive Ng x Ng row-major matrices
+ *   of element type cfg.g_in (Ng = lx*ly*(nw+nwex-1)), one per spin.
+ *   Borrowed: they must stay alive and unchanged until g4_sync returns (or
+ *   until later work on the same stream has run).
+ * sign: HOST array of batch weights s_b, copied before return.
+ * batch >= 0 (0 is a no-op).  In batched mode the measurements are processed
+ * in passes of at most max_batch; in plain mode one pass per measurement.
+ * Asynchronous on the handle's stream. */
+int g4_accumulate(g4_slice *h, const void *G_up, const void *G_dn, const double *sign,
+                  int32_t batch);
+
+/* Wait for all enqueued work on the handle's stream; folds event timings
+ * into the statistics. */
+int g4_sync(g4_slice *h);
+
+/* Synchronous copy of entries [first, first+count) of one channel (a single
+ * G4_* bit present in cfg.channels) into out_c128 (HOST, 2*count doubles,
+ * interleaved).  Compensated accumulators are returned as value +
+ * compensation in double. */
+int g4_readback(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, double *out_c128);
+
+/* Synchronous overwrite of entries [first, first+count) of one channel from
+ * in_c128 (HOST).  For float accumulators each value is split into a rounded
+ * value and its rounding remainder (compensated) or rounded (plain float). */
+int g4_load(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, const double *in_c128);
+
+/* Set the measurement count and weight sum (restoring a checkpoint). */
+int g4_set_counts(g4_slice *h, uint64_t measurements, double sign_sum);
+
+/* Zero every accumulator and the statistics.  Enqueued. */
+int g4_reset(g4_slice *h);
+
+/* Current statistics (synchronous: waits for the stream first). */
+int g4_stats(g4_slice *h, g4_stats_t *st);
+
+/* Override the work tile (K2 rows) and, in batched mode, the pass size and
+ * kernel variant (0 VALU, 1 MFMA direct).  0 keeps the current value.
+ * G4_E_UNSUPPORTED if the combination cannot run for this slice. */
+int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant);
+
+/* Release everything owned by h (waits for its stream).  NULL is a no-op. */
+void g4_destroy(g4_slice *h);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char *g4_last_error(void);
+
+/* ---- synthetic inputs (not part of the method) -------------------------
+ * Fill a DEVICE buffer with `count` seeded Hubbard-shaped G matrices for
+ * measurements b0..b0+count-1 of one spin (0 up, 1 down):
+ *   G(r,c) = delta_rc / (i w_n + mu + s h - eps_k) + noise (x + i y),
+ *   eps_k = -2t(cos kx + cos ky),  x, y ~ N(0,1) from Philox4x32-10 with
+ *   key (seed, wid) and counter (r*Ng + c, b, spin, 0), Box-Muller in double.
+ * dtype: G4_IN_C128 or G4_IN_C64 (rounded).  stream: hipStream_t or NULL
+ * (the null stream).  Asynchronous. */
+int g4_synth_fill(void *out, int32_t dtype, int32_t lx, int32_t ly, int32_t nw, int32_t nwex,
+                  double beta, double t, double mu, double h, double noise, uint32_t seed,
+                  uint32_t wid, int64_t b0, int32_t count, int32_t spin, void *stream);
+
+/* ---- debug export of the integer index maps (no HIP call) --------------
+ * kadd[k*Nc+q] = k+q, ksub[q*Nc+k] = q-k (Nc*Nc int32 each, HOST).
+ * plane_q[i], plane_m[i] for the slice's planes i = 0..q_end-q_begin-1.
+ * Any output may be NULL. */
+int g4_index_maps(const g4_config *cfg, int32_t *kadd, int32_t *ksub, int32_t *plane_q,
+                  int32_t *plane_m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* G4_H */

@@ -1,0 +1,65 @@
+"""Build the HIP C-ABI library paper_2105_00027_amd/libg4.so for gfx950.
+
+Every source is compiled by hipcc (objects under _build/, kept out of the
+repository history), then linked into one shared library next to this file.
+All device code is built with packed FP32 instructions disabled.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(ROOT, "_build", "g4")
+LIB = os.path.join(HERE, "libg4.so")
+# (source, object name, extra defines); the update kernel is instantiated once
+# per (precision, K2 rows per thread) pair
+SOURCES = [("g4_abi.cpp", "g4_abi", []), ("g4_kernels.hip", "g4_kernels", []),
+           ("g4_synth.hip", "g4_synth", [])] + [
+    ("g4_update_inst.hip", "g4_update_p%d_e%d" % (p, e), ["-DG4_PREC=%d" % p, "-DG4_EPT=%d" % e])
+    for p in (0, 1) for e in (1, 2, 4, 8)]
+ARCH = os.environ.get("G4_OFFLOAD_ARCH", "gfx950")
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+          "-I", os.path.join(ROOT, "include")]
+DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _compile(spec, verbose: bool) -> str:
+    src, name, defs = spec
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = ["hipcc", *COMMON, *DEVICE, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = ["hipcc", *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on " + src)
+    warn = "\n".join(l for l in (r.stderr or "").splitlines()
+                     if "packed-fp32-ops" not in l and "not a recognized feature" not in l)
+    if verbose and warn.strip():
+        sys.stderr.write(warn + "\n")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 4, 16, len(SOURCES))) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,735 @@
+// C ABI of the G4 slice library: validation, index tables, device memory,
+// the per-call pass schedule and the synchronous copies.  See include/g4.h
+// for the contract of each entry point.
+#include "../../include/g4.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "g4_internal.hpp"
+
+using namespace g4;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+constexpr int kMaxNw = 256;      // one K1 row per lane group of a 256-thread block
+constexpr int kMaxBatch = 256;
+constexpr int kSignSlots = 8;
+constexpr uint64_t kScratchEntries = 4u << 20;   // readback/load staging, complex128
+
+int acc_entry_bytes(int acc) { return acc == G4_ACC_C64 ? 8 : 16; }
+
+int popcount3(uint32_t c) { return (c & 1) + ((c >> 1) & 1) + ((c >> 2) & 1); }
+
+// Everything derived from a configuration, computed without touching HIP.
+struct Plan {
+    Dims d;
+    int prec;          // 0 FP64 products, 1 FP32
+    int batch;         // measurements per pass
+    int mgroup;        // transfer planes per work tile (compile-time bound)
+    int tile;          // K2 rows per work tile
+    int ept;           // K2 rows per thread
+    int slots;         // direct-vector slots (bit 0 magnetic, bit 1 charge)
+    int nslots;
+    uint64_t entries;  // per channel
+    uint64_t acc_bytes, dir_bytes, stage_bytes, sign_bytes, scratch_bytes, table_bytes;
+    uint64_t total_bytes;
+    std::vector<int32_t> qlist;
+};
+
+int choose_mgroup(int nwex) { return nwex == 1 ? 1 : (nwex <= 4 ? 4 : 8); }
+
+// Largest K2-rows-per-thread count keeping the register accumulators and the
+// LDS tiles modest; tile = ept * (256 / nw).
+int choose_ept(int prec, int nch, int mgroup, int nw) {
+    const int rp = 256 / nw;
+    const int budget = prec == 0 ? 8 : 16;    // complex accumulators per thread
+    int ept = 8;
+    while (ept > 1 && (nch * ept * mgroup > budget || ept * rp > nw)) ept >>= 1;
+    return ept;
+}
+
+int validate(const g4_config *c, Plan *p) {
+    if (!c) return fail(G4_E_ARG, "config is NULL");
+    if (c->abi_version != G4_ABI_VERSION)
+        return fail(G4_E_ARG, "abi_version %u, library speaks %u", c->abi_version, G4_ABI_VERSION);
+    if (c->lx < 1 || c->ly < 1 || (int64_t)c->lx * c->ly > 4096)
+        return fail(G4_E_ARG, "cluster %d x %d out of range", c->lx, c->ly);
+    const int nc = c->lx * c->ly;
+    if (c->nw < 2 || (c->nw & 1)) return fail(G4_E_ARG, "nw=%d must be even and >= 2", c->nw);
+    if (c->nwex < 1) return fail(G4_E_ARG, "nwex=%d must be >= 1", c->nwex);
+    if (c->nq < 1 || c->nq > nc) return fail(G4_E_ARG, "nq=%d outside [1, %d]", c->nq, nc);
+    std::vector<int32_t> ql(c->nq);
+    std::vector<char> seen(nc, 0);
+    for (int i = 0; i < c->nq; ++i) {
+        const int32_t q = c->q_list ? c->q_list[i] : i;
+        if (q < 0 || q >= nc) return fail(G4_E_ARG, "q_list[%d]=%d outside [0, %d)", i, q, nc);
+        if (seen[q]) return fail(G4_E_ARG, "q_list repeats momentum %d", q);
+        seen[q] = 1;
+        ql[i] = q;
+    }
+    const int64_t nQ = (int64_t)c->nq * c->nwex;
+    if (c->q_begin < 0 || c->q_end > nQ || c->q_begin >= c->q_end)
+        return fail(G4_E_ARG, "slice [%lld, %lld) not inside [0, %lld)", (long long)c->q_begin,
+                    (long long)c->q_end, (long long)nQ);
+    if (c->channels == 0 || (c->channels & ~7u))
+        return fail(G4_E_ARG, "channels bitmask 0x%x invalid", c->channels);
+    if (c->g_in != G4_IN_C128 && c->g_in != G4_IN_C64) return fail(G4_E_ARG, "g_in=%d", c->g_in);
+    if (c->prod < G4_PROD_F64 || c->prod > G4_PROD_F16X2) return fail(G4_E_ARG, "prod=%d", c->prod);
+    if (c->acc < G4_ACC_C128 || c->acc > G4_ACC_C64) return fail(G4_E_ARG, "acc=%d", c->acc);
+    if (c->mode != G4_MODE_PLAIN && c->mode != G4_MODE_BATCHED) return fail(G4_E_ARG, "mode=%d", c->mode);
+    if (c->flags & ~(uint32_t)(G4_F_CHECK_FINITE | G4_F_KERNEL_TIMING | G4_F_GRAPH | G4_F_MFMA))
+        return fail(G4_E_ARG, "unknown flags 0x%x", c->flags);
+    if (c->device < 0) return fail(G4_E_ARG, "device=%d", c->device);
+    if (c->mode == G4_MODE_PLAIN) {
+        if (c->prod != G4_PROD_F64 || c->g_in != G4_IN_C128 || c->acc != G4_ACC_C128)
+            return fail(G4_E_ARG, "plain mode is FP64 throughout: g_in C128, prod F64, acc C128");
+    } else if (c->max_batch < 1 || c->max_batch > kMaxBatch) {
+        return fail(G4_E_ARG, "max_batch=%d outside [1, %d]", c->max_batch, kMaxBatch);
+    }
+    if (c->prod == G4_PROD_F64 && c->g_in != G4_IN_C128)
+        return fail(G4_E_ARG, "FP64 products need complex128 G");
+    if (c->tile < 0) return fail(G4_E_ARG, "tile=%d", c->tile);
+
+    Plan &P = *p;
+    Dims &d = P.d;
+    d.lx = c->lx;
+    d.ly = c->ly;
+    d.nc = nc;
+    d.nw = c->nw;
+    d.nwex = c->nwex;
+    d.nwg = c->nw + c->nwex - 1;
+    const int64_t ng = (int64_t)nc * d.nwg;
+    const int64_t n = (int64_t)nc * c->nw;
+    if (ng > (1 << 20) || n > (1 << 20)) return fail(G4_E_ARG, "G side %lld too large", (long long)ng);
+    d.ng = (int)ng;
+    d.n = (int)n;
+    d.planes = (int)(c->q_end - c->q_begin);
+    d.q_begin = c->q_begin;
+    P.entries = (uint64_t)d.planes * (uint64_t)n * (uint64_t)n;
+    P.qlist = ql;
+
+    // --- what this build runs
+    if (c->nw > kMaxNw) return fail(G4_E_UNSUPPORTED, "nw=%d above %d", c->nw, kMaxNw);
+    if (c->prod == G4_PROD_BF16X2 || c->prod == G4_PROD_F16X2)
+        return fail(G4_E_UNSUPPORTED, "split-precision products are not available in this build");
+    P.prec = c->prod == G4_PROD_F64 ? 0 : 1;
+    P.batch = c->mode == G4_MODE_PLAIN ? 1 : c->max_batch;
+    P.mgroup = choose_mgroup(c->nwex);
+    const int nch = popcount3(c->channels);
+    const int rp = 256 / c->nw;
+    if (c->tile) {
+        if (c->tile % rp || c->tile > c->nw) return fail(G4_E_UNSUPPORTED, "tile=%d: must be a multiple of %d and <= nw", c->tile, rp);
+        const int e = c->tile / rp;
+        if (e != 1 && e != 2 && e != 4 && e != 8) return fail(G4_E_UNSUPPORTED, "tile=%d: tile/%d must be 1, 2, 4 or 8", c->tile, rp);
+        P.ept = e;
+    } else {
+        P.ept = choose_ept(P.prec, nch, P.mgroup, c->nw);
+    }
+    P.tile = P.ept * rp;
+    if (update_lds_bytes(P.prec, (int)c->channels, P.tile, P.mgroup, d) > 160 * 1024)
+        return fail(G4_E_UNSUPPORTED, "LDS tile above 160 KiB");
+    P.slots = c->channels & 3u;
+    P.nslots = popcount3(P.slots);
+
+    // --- device memory
+    const uint64_t el = P.prec == 0 ? 16 : 8;
+    P.acc_bytes = P.entries * (uint64_t)acc_entry_bytes(c->acc);
+    P.dir_bytes = 2ull * P.nslots * P.batch * (uint64_t)d.planes * n * el;
+    P.stage_bytes = (P.prec == 1 && c->g_in == G4_IN_C128) ? 2ull * P.batch * ng * ng * 8 : 0;
+    P.sign_bytes = (uint64_t)kSignSlots * kMaxBatch * sizeof(double);
+    P.scratch_bytes = (c->acc == G4_ACC_C128 ? 0 : std::min<uint64_t>(P.entries, kScratchEntries) * 16);
+    const uint64_t nitems_max = (uint64_t)d.planes * nc * nc * ((c->nw + P.tile - 1) / P.tile);
+    P.table_bytes = 2ull * nc * nc * 4 + (uint64_t)d.planes * 16 + nitems_max * 16 + (uint64_t)d.planes * 8;
+    P.total_bytes = P.acc_bytes * popcount3(c->channels) + P.dir_bytes + P.stage_bytes + P.sign_bytes +
+                    P.scratch_bytes + P.table_bytes;
+    return G4_OK;
+}
+
+// Host-built integer index maps: momentum addition/subtraction on cluster
+// coordinates with wraparound; plane decode iQ -> (q, m).
+void build_momentum_maps(const Dims &d, std::vector<int32_t> &kadd, std::vector<int32_t> &ksub) {
+    kadd.assign((size_t)d.nc * d.nc, 0);
+    ksub.assign((size_t)d.nc * d.nc, 0);
+    for (int k = 0; k < d.nc; ++k) {
+        const int kx = k % d.lx, ky = k / d.lx;
+        for (int q = 0; q < d.nc; ++q) {
+            const int qx = q % d.lx, qy = q / d.lx;
+            kadd[(size_t)k * d.nc + q] = (kx + qx) % d.lx + d.lx * ((ky + qy) % d.ly);
+            ksub[(size_t)q * d.nc + k] = (qx - kx + d.lx) % d.lx + d.lx * ((qy - ky + d.ly) % d.ly);
+        }
+    }
+}
+
+void build_planes(const Plan &P, int nwex, std::vector<int2> &plane_qm) {
+    plane_qm.resize(P.d.planes);
+    for (int p = 0; p < P.d.planes; ++p) {
+        const int64_t iQ = P.d.q_begin + p;
+        plane_qm[p] = int2{P.qlist[(size_t)(iQ / nwex)], (int)(iQ % nwex)};
+    }
+}
+
+// Work decomposition: plane groups (one q, at most mgroup consecutive m) and
+// tiles (group, k1, k2, c0).
+void build_work(const Plan &P, int nwex, std::vector<int4> &groups, std::vector<int4> &items) {
+    groups.clear();
+    items.clear();
+    const Dims &d = P.d;
+    int64_t iQ = d.q_begin;
+    const int64_t end = d.q_begin + d.planes;
+    while (iQ < end) {
+        const int iq = (int)(iQ / nwex), m = (int)(iQ % nwex);
+        const int64_t qend = std::min<int64_t>(end, (int64_t)(iq + 1) * nwex);
+        const int cnt = (int)std::min<int64_t>(qend - iQ, P.mgroup);
+        groups.push_back(int4{P.qlist[(size_t)iq], m, cnt, (int)(iQ - d.q_begin)});
+        iQ += cnt;
+    }
+    for (int g = 0; g < (int)groups.size(); ++g)
+        for (int k2 = 0; k2 < d.nc; ++k2)
+            for (int k1 = 0; k1 < d.nc; ++k1)
+                for (int c0 = 0; c0 < d.nw; c0 += P.tile) items.push_back(int4{g, k1, k2, c0});
+}
+
+}  // namespace
+
+struct g4_slice {
+    g4_config cfg;
+    Plan P;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+    void *acc[3] = {nullptr, nullptr, nullptr};
+    int32_t *kadd = nullptr, *ksub = nullptr;
+    int4 *groups = nullptr, *items = nullptr;
+    int2 *plane_qm = nullptr;
+    int ngroups = 0, nitems = 0;
+    size_t items_cap = 0;
+    void *dir = nullptr;
+    void *stage = nullptr;
+    double *sign_dev = nullptr;
+    double *sign_host = nullptr;     // pinned
+    hipEvent_t sign_ev[kSignSlots] = {};
+    bool sign_ev_used[kSignSlots] = {};
+    int sign_next = 0;
+    double *scratch = nullptr;
+    uint64_t measurements = 0;
+    double sign_sum = 0.0;
+    uint64_t launches = 0;
+    double kernel_ms = 0.0;
+    uint64_t timed = 0;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+};
+
+namespace {
+
+int hip_fail(g4_slice *h, hipError_t e, const char *what) {
+    if (h) h->poisoned = true;
+    return fail(G4_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define G4_HIP(h, call)                                     \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+    } while (0)
+
+int usable(g4_slice *h) {
+    if (!h) return fail(G4_E_ARG, "handle is NULL");
+    if (h->poisoned) return fail(G4_E_STATE, "handle poisoned by an earlier HIP error");
+    return G4_OK;
+}
+
+int channel_slot(uint32_t channel) {
+    return channel == G4_PH_MAGNETIC ? 0 : channel == G4_PH_CHARGE ? 1 : channel == G4_PP_UPDOWN ? 2 : -1;
+}
+
+void release(g4_slice *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto &pr : h->ev_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto e : h->ev_free) (void)hipEventDestroy(e);
+    for (int i = 0; i < kSignSlots; ++i)
+        if (h->sign_ev[i]) (void)hipEventDestroy(h->sign_ev[i]);
+    for (void *p : {(void *)h->acc[0], (void *)h->acc[1], (void *)h->acc[2], (void *)h->kadd,
+                    (void *)h->ksub, (void *)h->groups, (void *)h->items, (void *)h->plane_qm,
+                    h->dir, h->stage, (void *)h->sign_dev, (void *)h->scratch})
+        if (p) (void)hipFree(p);
+    if (h->sign_host) (void)hipHostFree(h->sign_host);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int fold_timings(g4_slice *h) {
+    for (auto &pr : h->ev_pending) {
+        G4_HIP(h, hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        G4_HIP(h, hipEventElapsedTime(&ms, pr.first, pr.second));
+        h->kernel_ms += ms;
+        h->timed += 1;
+        h->ev_free.push_back(pr.first);
+        h->ev_free.push_back(pr.second);
+    }
+    h->ev_pending.clear();
+    return G4_OK;
+}
+
+int take_event(g4_slice *h, hipEvent_t *out) {
+    if (!h->ev_free.empty()) {
+        *out = h->ev_free.back();
+        h->ev_free.pop_back();
+        return G4_OK;
+    }
+    G4_HIP(h, hipEventCreate(out));
+    return G4_OK;
+}
+
+Tables tables_of(const g4_slice *h) {
+    Tables t;
+    t.kadd = h->kadd;
+    t.ksub = h->ksub;
+    t.groups = h->groups;
+    t.items = h->items;
+    t.plane_qm = h->plane_qm;
+    return t;
+}
+
+int rebuild_work(g4_slice *h) {
+    std::vector<int4> groups, items;
+    build_work(h->P, h->cfg.nwex, groups, items);
+    if (items.size() > h->items_cap) {
+        G4_HIP(h, hipStreamSynchronize(h->stream));
+        if (h->items) G4_HIP(h, hipFree(h->items));
+        h->items = nullptr;
+        h->items_cap = 0;
+        G4_HIP(h, hipMalloc(&h->items, items.size() * sizeof(int4)));
+        h->items_cap = items.size();
+    }
+    G4_HIP(h, hipMemcpyAsync(h->groups, groups.data(), groups.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+    G4_HIP(h, hipMemcpyAsync(h->items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+    G4_HIP(h, hipStreamSynchronize(h->stream));
+    h->ngroups = (int)groups.size();
+    h->nitems = (int)items.size();
+    return G4_OK;
+}
+
+// One pass: up to P.batch measurements starting at b0.
+int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, int b0, int nb) {
+    const Plan &P = h->P;
+    const size_t in_el = h->cfg.g_in == G4_IN_C128 ? 16 : 8;
+    const int64_t per = (int64_t)P.d.ng * P.d.ng;
+    const void *pu = gu + (size_t)b0 * per * in_el;
+    const void *pd = gd + (size_t)b0 * per * in_el;
+
+    // signs: pinned slot -> device slot, ordered on the stream
+    const int slot = h->sign_next;
+    h->sign_next = (h->sign_next + 1) % kSignSlots;
+    if (h->sign_ev_used[slot]) G4_HIP(h, hipEventSynchronize(h->sign_ev[slot]));
+    double *hs = h->sign_host + (size_t)slot * kMaxBatch;
+    double *ds = h->sign_dev + (size_t)slot * kMaxBatch;
+    std::memcpy(hs, sign + b0, (size_t)nb * sizeof(double));
+    G4_HIP(h, hipMemcpyAsync(ds, hs, (size_t)nb * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    G4_HIP(h, hipEventRecord(h->sign_ev[slot], h->stream));
+    h->sign_ev_used[slot] = true;
+
+    if (P.prec == 1 && h->cfg.g_in == G4_IN_C128) {
+        float2 *su = static_cast<float2 *>(h->stage);
+        float2 *sd = su + (size_t)P.batch * per;
+        G4_HIP(h, launch_convert_c128_to_c64(pu, su, (int64_t)nb * per, h->stream));
+        G4_HIP(h, launch_convert_c128_to_c64(pd, sd, (int64_t)nb * per, h->stream));
+        pu = su;
+        pd = sd;
+    }
+    const size_t el = P.prec == 0 ? 16 : 8;
+    const int64_t dir_slot = (int64_t)P.batch * P.d.planes * P.d.n;
+    void *dir_a = h->dir;
+    void *dir_b = static_cast<char *>(h->dir) + (size_t)P.nslots * dir_slot * el;
+    if (P.slots) {
+        GatherArgs ga;
+        ga.gu = pu;
+        ga.gd = pd;
+        ga.g_stride = per;
+        ga.dir_a = dir_a;
+        ga.dir_b = dir_b;
+        ga.dir_slot_stride = dir_slot;
+        ga.sign = ds;
+        ga.batch = nb;
+        ga.slots = P.slots;
+        ga.d = P.d;
+        ga.t = tables_of(h);
+        // the per-pass layout is [slot][b][p][K] with b < nb; slot stride covers max batch
+        G4_HIP(h, launch_gather(P.prec, ga, h->stream));
+    }
+    UpdateArgs ua;
+    ua.gu = pu;
+    ua.gd = pd;
+    ua.g_stride = per;
+    ua.dir_a = dir_a;
+    ua.dir_b = dir_b;
+    ua.dir_slot_stride = dir_slot;
+    ua.sign = ds;
+    ua.batch = nb;
+    ua.acc[0] = h->acc[0];
+    ua.acc[1] = h->acc[1];
+    ua.acc[2] = h->acc[2];
+    ua.acc_kind = h->cfg.acc;
+    ua.tile = P.tile;
+    ua.d = P.d;
+    ua.t = tables_of(h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timing = (h->cfg.flags & G4_F_KERNEL_TIMING) != 0;
+    if (timing) {
+        int rc = take_event(h, &e0);
+        if (rc) return rc;
+        rc = take_event(h, &e1);
+        if (rc) return rc;
+        G4_HIP(h, hipEventRecord(e0, h->stream));
+    }
+    G4_HIP(h, launch_update(P.prec, (int)h->cfg.channels, P.ept, P.mgroup, h->nitems, ua, h->stream));
+    if (timing) {
+        G4_HIP(h, hipEventRecord(e1, h->stream));
+        h->ev_pending.emplace_back(e0, e1);
+    }
+    h->launches += 1;
+    return G4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int g4_config_init(g4_config *cfg) {
+    if (!cfg) return fail(G4_E_ARG, "config is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->abi_version = G4_ABI_VERSION;
+    cfg->lx = cfg->ly = 1;
+    cfg->nw = 2;
+    cfg->nwex = 1;
+    cfg->nq = 1;
+    cfg->q_begin = 0;
+    cfg->q_end = 1;
+    cfg->channels = G4_PH_MAGNETIC;
+    cfg->g_in = G4_IN_C128;
+    cfg->prod = G4_PROD_F64;
+    cfg->acc = G4_ACC_C128;
+    cfg->mode = G4_MODE_PLAIN;
+    cfg->max_batch = 1;
+    cfg->beta = 1.0;
+    return G4_OK;
+}
+
+int g4_slice_size(const g4_config *cfg, uint64_t *entries_per_channel, uint64_t *device_bytes) {
+    Plan P;
+    const int rc = validate(cfg, &P);
+    if (rc) return rc;
+    if (entries_per_channel) *entries_per_channel = P.entries;
+    if (device_bytes) *device_bytes = P.total_bytes;
+    g_err[0] = 0;
+    return G4_OK;
+}
+
+int g4_init_slice(const g4_config *cfg, g4_slice **out) {
+    if (!out) return fail(G4_E_ARG, "out is NULL");
+    *out = nullptr;
+    Plan P;
+    int rc = validate(cfg, &P);
+    if (rc) return rc;
+    if (const char *cap = std::getenv("G4_TEST_DEVICE_MEM_LIMIT")) {
+        const unsigned long long lim = std::strtoull(cap, nullptr, 10);
+        if (P.total_bytes > lim)
+            return fail(G4_E_OOM, "slice needs %llu bytes, cap G4_TEST_DEVICE_MEM_LIMIT=%llu",
+                        (unsigned long long)P.total_bytes, lim);
+    }
+    g4_slice *h = new (std::nothrow) g4_slice();
+    if (!h) return fail(G4_E_OOM, "host allocation failed");
+    h->cfg = *cfg;
+    h->cfg.q_list = nullptr;
+    h->P = P;
+    h->device = cfg->device;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(G4_E_HIP, "hipSetDevice(%d): %s", cfg->device, hipGetErrorString(e));
+    }
+    size_t free_b = 0, total_b = 0;
+    e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(G4_E_HIP, "hipMemGetInfo: %s", hipGetErrorString(e));
+    }
+    if (P.total_bytes > free_b) {
+        delete h;
+        return fail(G4_E_OOM, "slice needs %llu bytes, device has %llu free",
+                    (unsigned long long)P.total_bytes, (unsigned long long)free_b);
+    }
+#define G4_INIT(call)                                              \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) {                                    \
+            int r_ = fail(e_ == hipErrorOutOfMemory ? G4_E_OOM : G4_E_HIP, "%s: %s", #call, \
+                          hipGetErrorString(e_));                  \
+            release(h);                                            \
+            return r_;                                             \
+        }                                                          \
+    } while (0)
+    if (cfg->stream) {
+        h->stream = static_cast<hipStream_t>(cfg->stream);
+    } else {
+        G4_INIT(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    const uint64_t ab = P.acc_bytes;
+    for (int c = 0; c < 3; ++c)
+        if (cfg->channels & (1u << c)) G4_INIT(hipMalloc(&h->acc[c], ab));
+    const int nc = P.d.nc;
+    G4_INIT(hipMalloc(&h->kadd, (size_t)nc * nc * 4));
+    G4_INIT(hipMalloc(&h->ksub, (size_t)nc * nc * 4));
+    G4_INIT(hipMalloc(&h->plane_qm, (size_t)P.d.planes * sizeof(int2)));
+    G4_INIT(hipMalloc(&h->groups, (size_t)P.d.planes * sizeof(int4)));
+    if (P.dir_bytes) G4_INIT(hipMalloc(&h->dir, P.dir_bytes));
+    if (P.stage_bytes) G4_INIT(hipMalloc(&h->stage, P.stage_bytes));
+    G4_INIT(hipMalloc(&h->sign_dev, P.sign_bytes));
+    G4_INIT(hipHostMalloc(&h->sign_host, P.sign_bytes, hipHostMallocDefault));
+    for (int i = 0; i < kSignSlots; ++i) G4_INIT(hipEventCreateWithFlags(&h->sign_ev[i], hipEventDisableTiming));
+    if (P.scratch_bytes) G4_INIT(hipMalloc(&h->scratch, P.scratch_bytes));
+    std::vector<int32_t> kadd, ksub;
+    build_momentum_maps(P.d, kadd, ksub);
+    std::vector<int2> pq;
+    build_planes(P, cfg->nwex, pq);
+    G4_INIT(hipMemcpyAsync(h->kadd, kadd.data(), kadd.size() * 4, hipMemcpyHostToDevice, h->stream));
+    G4_INIT(hipMemcpyAsync(h->ksub, ksub.data(), ksub.size() * 4, hipMemcpyHostToDevice, h->stream));
+    G4_INIT(hipMemcpyAsync(h->plane_qm, pq.data(), pq.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
+    for (int c = 0; c < 3; ++c)
+        if (h->acc[c]) G4_INIT(launch_fill_zero(h->acc[c], ab, h->stream));
+    G4_INIT(hipStreamSynchronize(h->stream));
+#undef G4_INIT
+    rc = rebuild_work(h);
+    if (rc) {
+        release(h);
+        return rc;
+    }
+    *out = h;
+    g_err[0] = 0;
+    return G4_OK;
+}
+
+int g4_accumulate(g4_slice *h, const void *G_up, const void *G_dn, const double *sign, int32_t batch) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (batch < 0) return fail(G4_E_ARG, "batch=%d", batch);
+    if (batch == 0) return G4_OK;
+    if (!G_up || !G_dn || !sign) return fail(G4_E_ARG, "NULL G or sign pointer");
+    if (h->cfg.flags & G4_F_CHECK_FINITE)
+        for (int b = 0; b < batch; ++b)
+            if (!std::isfinite(sign[b])) return fail(G4_E_ARG, "sign[%d] is not finite", b);
+    G4_HIP(h, hipSetDevice(h->device));
+    const int B = h->P.batch;
+    double ssum = 0.0;
+    for (int b0 = 0; b0 < batch; b0 += B) {
+        const int nb = std::min(B, batch - b0);
+        rc = run_pass(h, static_cast<const char *>(G_up), static_cast<const char *>(G_dn), sign, b0, nb);
+        if (rc) return rc;
+    }
+    for (int b = 0; b < batch; ++b) ssum += sign[b];
+    h->measurements += (uint64_t)batch;
+    h->sign_sum += ssum;
+    return G4_OK;
+}
+
+int g4_sync(g4_slice *h) {
+    int rc = usable(h);
+    if (rc) return rc;
+    G4_HIP(h, hipSetDevice(h->device));
+    G4_HIP(h, hipStreamSynchronize(h->stream));
+    return fold_timings(h);
+}
+
+int g4_readback(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, double *out) {
+    int rc = usable(h);
+    if (rc) return rc;
+    const int c = channel_slot(channel);
+    if (c < 0 || !(h->cfg.channels & channel)) return fail(G4_E_ARG, "channel 0x%x not in the slice", channel);
+    if (first > h->P.entries || count > h->P.entries - first) return fail(G4_E_ARG, "range outside the slice");
+    if (count && !out) return fail(G4_E_ARG, "out is NULL");
+    G4_HIP(h, hipSetDevice(h->device));
+    G4_HIP(h, hipStreamSynchronize(h->stream));
+    if (h->cfg.acc == G4_ACC_C128) {
+        G4_HIP(h, hipMemcpyAsync(out, static_cast<double2 *>(h->acc[c]) + first, count * 16,
+                                 hipMemcpyDeviceToHost, h->stream));
+        G4_HIP(h, hipStreamSynchronize(h->stream));
+        return fold_timings(h);
+    }
+    const uint64_t chunk = h->P.scratch_bytes / 16;
+    for (uint64_t off = 0; off < count; off += chunk) {
+        const uint64_t cnt = std::min(chunk, count - off);
+        G4_HIP(h, launch_acc_to_c128(h->cfg.acc, h->acc[c], first + off, cnt, h->scratch, h->stream));
+        G4_HIP(h, hipMemcpyAsync(out + 2 * off, h->scratch, cnt * 16, hipMemcpyDeviceToHost, h->stream));
+        G4_HIP(h, hipStreamSynchronize(h->stream));
+    }
+    return fold_timings(h);
+}
+
+int g4_load(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, const double *in) {
+    int rc = usable(h);
+    if (rc) return rc;
+    const int c = channel_slot(channel);
+    if (c < 0 || !(h->cfg.channels & channel)) return fail(G4_E_ARG, "channel 0x%x not in the slice", channel);
+    if (first > h->P.entries || count > h->P.entries - first) return fail(G4_E_ARG, "range outside the slice");
+    if (count && !in) return fail(G4_E_ARG, "in is NULL");
+    G4_HIP(h, hipSetDevice(h->device));
+    G4_HIP(h, hipStreamSynchronize(h->stream));
+    if (h->cfg.acc == G4_ACC_C128) {
+        G4_HIP(h, hipMemcpyAsync(static_cast<double2 *>(h->acc[c]) + first, in, count * 16,
+                                 hipMemcpyHostToDevice, h->stream));
+        G4_HIP(h, hipStreamSynchronize(h->stream));
+        return G4_OK;
+    }
+    const uint64_t chunk = h->P.scratch_bytes / 16;
+    for (uint64_t off = 0; off < count; off += chunk) {
+        const uint64_t cnt = std::min(chunk, count - off);
+        G4_HIP(h, hipMemcpyAsync(h->scratch, in + 2 * off, cnt * 16, hipMemcpyHostToDevice, h->stream));
+        G4_HIP(h, launch_c128_to_acc(h->cfg.acc, h->scratch, h->acc[c], first + off, cnt, h->stream));
+        G4_HIP(h, hipStreamSynchronize(h->stream));
+    }
+    return G4_OK;
+}
+
+int g4_set_counts(g4_slice *h, uint64_t measurements, double sign_sum) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!std::isfinite(sign_sum)) return fail(G4_E_ARG, "sign_sum not finite");
+    h->measurements = measurements;
+    h->sign_sum = sign_sum;
+    return G4_OK;
+}
+
+int g4_reset(g4_slice *h) {
+    int rc = usable(h);
+    if (rc) return rc;
+    G4_HIP(h, hipSetDevice(h->device));
+    for (int c = 0; c < 3; ++c)
+        if (h->acc[c]) G4_HIP(h, launch_fill_zero(h->acc[c], h->P.acc_bytes, h->stream));
+    rc = fold_timings(h);
+    if (rc) return rc;
+    h->measurements = 0;
+    h->sign_sum = 0.0;
+    h->launches = 0;
+    h->kernel_ms = 0.0;
+    h->timed = 0;
+    return G4_OK;
+}
+
+int g4_stats(g4_slice *h, g4_stats_t *st) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!st) return fail(G4_E_ARG, "stats pointer is NULL");
+    rc = g4_sync(h);
+    if (rc) return rc;
+    st->measurements = h->measurements;
+    st->sign_sum = h->sign_sum;
+    st->launches = h->launches;
+    st->kernel_ms = h->kernel_ms;
+    st->timed_launches = h->timed;
+    st->entries = h->P.entries;
+    st->channels = h->cfg.channels;
+    st->batch = h->P.batch;
+    st->tile = h->P.tile;
+    st->variant = 0;
+    return G4_OK;
+}
+
+int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (tile < 0 || batch < 0 || variant < 0) return fail(G4_E_ARG, "negative plan value");
+    if (variant > 0) return fail(G4_E_UNSUPPORTED, "kernel variant %d not available", variant);
+    if (batch > 0 && (h->cfg.mode == G4_MODE_PLAIN ? batch != 1 : batch > h->cfg.max_batch))
+        return fail(G4_E_UNSUPPORTED, "batch %d above the allocated max_batch", batch);
+    g4_config c = h->cfg;
+    c.q_list = nullptr;
+    std::vector<int32_t> ql = h->P.qlist;
+    c.q_list = ql.data();
+    if (tile) c.tile = tile;
+    Plan P;
+    rc = validate(&c, &P);
+    if (rc) return rc;
+    // keep the allocation-sized batch, use the smaller pass size
+    const int keep_batch = h->P.batch;
+    G4_HIP(h, hipSetDevice(h->device));
+    G4_HIP(h, hipStreamSynchronize(h->stream));
+    h->P.ept = P.ept;
+    h->P.tile = P.tile;
+    h->P.batch = batch ? batch : keep_batch;
+    h->cfg.tile = c.tile;
+    return rebuild_work(h);
+}
+
+void g4_destroy(g4_slice *h) { release(h); }
+
+const char *g4_last_error(void) { return g_err; }
+
+int g4_synth_fill(void *out, int32_t dtype, int32_t lx, int32_t ly, int32_t nw, int32_t nwex,
+                  double beta, double t, double mu, double h, double noise, uint32_t seed,
+                  uint32_t wid, int64_t b0, int32_t count, int32_t spin, void *stream) {
+    if (!out && count) return fail(G4_E_ARG, "out is NULL");
+    if (dtype != G4_IN_C128 && dtype != G4_IN_C64) return fail(G4_E_ARG, "dtype=%d", dtype);
+    if (lx < 1 || ly < 1 || nw < 2 || (nw & 1) || nwex < 1 || count < 0 || b0 < 0 ||
+        (spin != 0 && spin != 1) || !(beta > 0))
+        return fail(G4_E_ARG, "bad generator shape");
+    hipError_t e = launch_synth(out, dtype, lx, ly, nw, nwex, beta, t, mu, h, noise, seed, wid, b0,
+                                count, spin, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(G4_E_HIP, "synth: %s", hipGetErrorString(e));
+    return G4_OK;
+}
+
+int g4_index_maps(const g4_config *cfg, int32_t *kadd, int32_t *ksub, int32_t *plane_q,
+                  int32_t *plane_m) {
+    Plan P;
+    int rc = validate(cfg, &P);
+    if (rc && rc != G4_E_UNSUPPORTED) return rc;
+    if (rc == G4_E_UNSUPPORTED) {
+        // the maps exist for any valid shape; rebuild the shape part only
+        g_err[0] = 0;
+    }
+    std::vector<int32_t> ka, ks;
+    Dims d;
+    d.lx = cfg->lx;
+    d.ly = cfg->ly;
+    d.nc = cfg->lx * cfg->ly;
+    build_momentum_maps(d, ka, ks);
+    if (kadd) std::memcpy(kadd, ka.data(), ka.size() * 4);
+    if (ksub) std::memcpy(ksub, ks.data(), ks.size() * 4);
+    const int64_t planes = cfg->q_end - cfg->q_begin;
+    for (int64_t p = 0; p < planes; ++p) {
+        const int64_t iQ = cfg->q_begin + p;
+        const int iq = (int)(iQ / cfg->nwex);
+        if (plane_q) plane_q[p] = cfg->q_list ? cfg->q_list[iq] : iq;
+        if (plane_m) plane_m[p] = (int)(iQ % cfg->nwex);
+    }
+    return G4_OK;
+}
+
+}  // extern "C"

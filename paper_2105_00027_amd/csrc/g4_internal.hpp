@@ -1,0 +1,87 @@
+// Internal declarations shared by the C-ABI host code and the kernel
+// launchers of the G4 slice library (not installed, not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace g4 {
+
+// Shapes of one slice; every count is derived from the configuration.
+struct Dims {
+    int lx, ly, nc;      // cluster
+    int nw, nwex, nwg;   // frequencies: G4 range, transfers, G window
+    int ng, n;           // G side, G4 plane side
+    int planes;          // planes in the slice
+    int64_t q_begin;     // first plane (flattened iQ)
+};
+
+// A run of transfer planes sharing one momentum q: bosonic m in
+// [m_lo, m_lo + count), slice-relative plane index of m_lo is p0.
+// Stored as int4 {q, m_lo, count, p0}.
+
+// One work tile of the slice-update kernel, int4 {group, k1, k2, c0}:
+// momenta k1, k2 and K2-frequency rows [c0, c0 + tile) of that group.
+
+// Device-resident index tables of a slice.
+struct Tables {
+    const int32_t *kadd;   // kadd[k*nc + q] = k + q
+    const int32_t *ksub;   // ksub[q*nc + k] = q - k
+    const int4 *groups;    // {q, m_lo, count, p0}
+    const int4 *items;     // {group, k1, k2, c0}
+    const int2 *plane_qm;  // per slice plane {q, m}
+};
+
+enum AccKind { ACC_C128 = 0, ACC_C64_KAHAN = 1, ACC_C64 = 2 };
+enum { CH_MAG = 1, CH_CHG = 2, CH_PP = 4 };
+
+// Arguments of the slice-update kernel.  G elements are complex of the
+// product precision (double2 for FP64, float2 for FP32).
+struct UpdateArgs {
+    const void *gu;           // batch of Ng x Ng matrices, spin up
+    const void *gd;           // spin down
+    int64_t g_stride;         // elements between consecutive matrices
+    const void *dir_a;        // direct vectors a[slot][b][p][K] (sign folded), slot 0 mag, 1 charge
+    const void *dir_b;        // direct vectors b[slot][b][p][K]
+    int64_t dir_slot_stride;  // elements between slots
+    const double *sign;       // device, per measurement of this pass
+    int batch;                // measurements in this pass
+    void *acc[3];             // accumulators: magnetic, charge, pp (NULL if absent)
+    int acc_kind;             // AccKind
+    int tile;                 // K2 rows per work tile
+    Dims d;
+    Tables t;
+};
+
+// Arguments of the direct-vector gather.
+struct GatherArgs {
+    const void *gu, *gd;
+    int64_t g_stride;
+    void *dir_a, *dir_b;
+    int64_t dir_slot_stride;
+    const double *sign;
+    int batch;
+    int slots;          // bit 0: magnetic (G_up - G_dn), bit 1: charge (G_up + G_dn)
+    Dims d;
+    Tables t;
+};
+
+// Kernel launchers (g4_kernels.hip).  `prec` 0 = FP64, 1 = FP32.
+hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
+hipError_t launch_update(int prec, int channels, int ept, int mgroup, int nitems,
+                         const UpdateArgs &a, hipStream_t s);
+size_t update_lds_bytes(int prec, int channels, int tile, int mgroup, const Dims &d);
+hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s);
+hipError_t launch_acc_to_c128(int acc_kind, const void *acc, uint64_t first, uint64_t count,
+                              double *dst, hipStream_t s);
+hipError_t launch_c128_to_acc(int acc_kind, const double *src, void *acc, uint64_t first,
+                              uint64_t count, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// Synthetic-input generator (g4_synth.hip).
+hipError_t launch_synth(void *out, int dtype, int lx, int ly, int nw, int nwex, double beta,
+                        double t, double mu, double h, double noise, uint32_t seed, uint32_t wid,
+                        int64_t b0, int count, int spin, hipStream_t s);
+
+}  // namespace g4

@@ -1,0 +1,189 @@
+// Helper kernels of the G4 slice library for gfx950 (CDNA4): the direct-term
+// gather, precision staging, accumulator conversion for readback/load, a fill
+// kernel, and the dispatch to the slice-update kernel instantiations
+// (g4_update.hpp / g4_update_inst.hip).
+//
+// The gather builds, for every plane Q of the slice and every K, the
+// direct-term vectors a_b(Q,K) = s_b D(K+Q,K) and b_b(Q,K) = D(K,K+Q) with
+// D = G_up - G_dn (magnetic) or G_up + G_dn (charge), so the update kernel
+// reads them coalesced instead of gathering diagonals of G per entry.
+#include "g4_internal.hpp"
+
+namespace g4 {
+namespace {
+
+template <typename R> struct Cx;
+template <> struct Cx<double> { using V = double2; };
+template <> struct Cx<float> { using V = float2; };
+
+// ---------------------------------------------------------------------------
+// Direct-term vectors.  Layout [slot][b][p][K]; slot 0 = magnetic (G_up - G_dn),
+// slot 1 = charge (G_up + G_dn), present when the slot bit is set.
+template <typename R>
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
+    using V = typename Cx<R>::V;
+    const int n = a.d.n, nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, planes = a.d.planes;
+    const int64_t ng = a.d.ng;
+    const int64_t total = (int64_t)a.batch * planes * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int K = (int)(idx % n);
+        const int64_t rest = idx / n;
+        const int p = (int)(rest % planes);
+        const int b = (int)(rest / planes);
+        const int2 qm = a.t.plane_qm[p];
+        const int k = K / nw, i = K % nw;
+        const int kq = a.t.kadd[k * nc + qm.x];
+        const int64_t rK = (int64_t)k * nwg + i;
+        const int64_t rKQ = (int64_t)kq * nwg + i + qm.y;
+        const V *gu = static_cast<const V *>(a.gu) + (int64_t)b * a.g_stride;
+        const V *gd = static_cast<const V *>(a.gd) + (int64_t)b * a.g_stride;
+        const V au = gu[rKQ * ng + rK], ad = gd[rKQ * ng + rK];
+        const V bu = gu[rK * ng + rKQ], bd = gd[rK * ng + rKQ];
+        const R s = (R)a.sign[b];
+        V *da = static_cast<V *>(a.dir_a);
+        V *db = static_cast<V *>(a.dir_b);
+        int64_t o = idx;
+        if (a.slots & 1) {
+            da[o] = V{s * (au.x - ad.x), s * (au.y - ad.y)};
+            db[o] = V{bu.x - bd.x, bu.y - bd.y};
+            o += a.dir_slot_stride;
+        }
+        if (a.slots & 2) {
+            da[o] = V{s * (au.x + ad.x), s * (au.y + ad.y)};
+            db[o] = V{bu.x + bd.x, bu.y + bd.y};
+        }
+    }
+}
+
+__global__ void convert_kernel(const double2 *src, float2 *dst, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = src[i];
+        dst[i] = float2{(float)v.x, (float)v.y};
+    }
+}
+
+__global__ void acc_to_c128_kernel(int kind, const void *acc, uint64_t first, uint64_t count,
+                                   double2 *dst) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (kind == ACC_C64_KAHAN) {
+            const float4 v = static_cast<const float4 *>(acc)[first + i];
+            // value = sum - comp (comp is the negated remainder)
+            dst[i] = double2{(double)v.x - (double)v.z, (double)v.y - (double)v.w};
+        } else {
+            const float2 v = static_cast<const float2 *>(acc)[first + i];
+            dst[i] = double2{(double)v.x, (double)v.y};
+        }
+    }
+}
+
+__global__ void c128_to_acc_kernel(int kind, const double2 *src, void *acc, uint64_t first,
+                                   uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double2 v = src[i];
+        const float hr = (float)v.x, hi = (float)v.y;
+        if (kind == ACC_C64_KAHAN) {
+            const float cr = (float)((double)hr - v.x), ci = (float)((double)hi - v.y);
+            static_cast<float4 *>(acc)[first + i] = float4{hr, hi, cr, ci};
+        } else {
+            static_cast<float2 *>(acc)[first + i] = float2{hr, hi};
+        }
+    }
+}
+
+__global__ void fill_zero_kernel(uint4 *p, size_t n16, unsigned char *tail, size_t ntail) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t i = i0; i < n16; i += stride) p[i] = uint4{0u, 0u, 0u, 0u};
+    if (i0 < ntail) tail[i0] = 0;
+}
+
+int grid_for(int64_t work, int threads) {
+    int64_t g = (work + threads - 1) / threads;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+#define G4_DECL(p, e)                                                                        \
+    hipError_t launch_update_p##p##_e##e(int channels, int mgroup, int nitems, size_t lds, \
+                                         const UpdateArgs &a, hipStream_t s);
+G4_DECL(0, 1) G4_DECL(0, 2) G4_DECL(0, 4) G4_DECL(0, 8)
+G4_DECL(1, 1) G4_DECL(1, 2) G4_DECL(1, 4) G4_DECL(1, 8)
+#undef G4_DECL
+
+size_t update_lds_bytes(int prec, int channels, int tile, int mgroup, const Dims &d) {
+    const size_t el = prec == 0 ? sizeof(double2) : sizeof(float2);
+    const int T2 = tile < d.nw ? tile : d.nw;
+    size_t words = 0;
+    if (channels & (CH_MAG | CH_CHG)) words += 2 * (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
+    if (channels & CH_PP) words += 2 * (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
+    return words * el;
+}
+
+hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s) {
+    const int64_t total = (int64_t)a.batch * a.d.planes * a.d.n;
+    if (total == 0) return hipSuccess;
+    const int g = grid_for(total, 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(gather_kernel<double>, dim3(g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(gather_kernel<float>, dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(int prec, int channels, int ept, int mgroup, int nitems,
+                         const UpdateArgs &a, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    const size_t lds = update_lds_bytes(prec, channels, a.tile, mgroup, a.d);
+    switch (prec * 16 + ept) {
+        case 1: return launch_update_p0_e1(channels, mgroup, nitems, lds, a, s);
+        case 2: return launch_update_p0_e2(channels, mgroup, nitems, lds, a, s);
+        case 4: return launch_update_p0_e4(channels, mgroup, nitems, lds, a, s);
+        case 8: return launch_update_p0_e8(channels, mgroup, nitems, lds, a, s);
+        case 17: return launch_update_p1_e1(channels, mgroup, nitems, lds, a, s);
+        case 18: return launch_update_p1_e2(channels, mgroup, nitems, lds, a, s);
+        case 20: return launch_update_p1_e4(channels, mgroup, nitems, lds, a, s);
+        case 24: return launch_update_p1_e8(channels, mgroup, nitems, lds, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(convert_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s,
+                       static_cast<const double2 *>(src), static_cast<float2 *>(dst), count);
+    return hipGetLastError();
+}
+
+hipError_t launch_acc_to_c128(int acc_kind, const void *acc, uint64_t first, uint64_t count,
+                              double *dst, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(acc_to_c128_kernel, dim3(grid_for((int64_t)count, 256)), dim3(256), 0, s,
+                       acc_kind, acc, first, count, reinterpret_cast<double2 *>(dst));
+    return hipGetLastError();
+}
+
+hipError_t launch_c128_to_acc(int acc_kind, const double *src, void *acc, uint64_t first,
+                              uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(c128_to_acc_kernel, dim3(grid_for((int64_t)count, 256)), dim3(256), 0, s,
+                       acc_kind, reinterpret_cast<const double2 *>(src), acc, first, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const size_t n16 = bytes / 16, ntail = bytes % 16;
+    unsigned char *tail = static_cast<unsigned char *>(p) + n16 * 16;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for((int64_t)(n16 > ntail ? n16 : ntail), 256)),
+                       dim3(256), 0, s, static_cast<uint4 *>(p), n16, tail, ntail);
+    return hipGetLastError();
+}
+
+}  // namespace g4

@@ -1,0 +1,113 @@
+"""The C-ABI library on the CPU: it loads, exports every declared entry point,
+validates configurations before any HIP call, and its integer index maps equal
+the oracle's coordinate arithmetic bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import sampled
+from synth import Workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+g4 = pytest.importorskip("paper_2105_00027_amd.g4", reason="libg4.so not built")
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "g4.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(g4_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(g4._L, n), n
+    assert set(names) == set(g4.EXPORTS)
+
+
+def base(**kw):
+    d = dict(lx=4, ly=4, nw=64, nwex=8, nq=16, q_begin=0, q_end=128)
+    d.update(kw)
+    return g4.Config(**d)
+
+
+BAD = [
+    dict(abi_version=7), dict(lx=0), dict(nw=63), dict(nw=0), dict(nwex=0), dict(nq=17),
+    dict(q_list=[0, 1, 1] + list(range(3, 16))), dict(q_list=[0] * 15 + [16]),
+    dict(q_begin=5, q_end=5), dict(q_end=129), dict(q_begin=-1), dict(channels=0),
+    dict(channels=8), dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9),
+    dict(device=-1), dict(mode=1, max_batch=0), dict(mode=1, max_batch=257),
+    dict(mode=0, prod=1), dict(mode=0, acc=1), dict(mode=1, max_batch=8, prod=0, g_in=1),
+    dict(tile=-1),
+]
+
+
+@pytest.mark.parametrize("kw", BAD, ids=lambda k: ",".join("%s=%s" % i for i in k.items())[:40])
+def test_invalid_configs_rejected_without_hip(kw):
+    c = base(**kw)
+    with pytest.raises(g4.G4Error) as e:
+        g4.g4_slice_size(c)
+    assert e.value.code == g4.G4_E_ARG
+    with pytest.raises(g4.G4Error) as e:
+        g4.g4_init_slice(c)
+    assert e.value.code == g4.G4_E_ARG
+    assert g4.g4_last_error()
+
+
+def test_unsupported_is_distinguished():
+    for kw in (dict(nw=512), dict(mode=1, max_batch=8, prod=2, g_in=1), dict(tile=3)):
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_slice_size(base(**kw))
+        assert e.value.code == g4.G4_E_UNSUPPORTED
+
+
+def test_oom_cap_before_any_allocation(monkeypatch):
+    c = base()
+    entries, nbytes = g4.g4_slice_size(c)
+    assert entries == 128 * 1024 * 1024
+    assert nbytes >= entries * 16
+    monkeypatch.setenv("G4_TEST_DEVICE_MEM_LIMIT", str(nbytes - 1))
+    with pytest.raises(g4.G4Error) as e:
+        g4.g4_init_slice(c)
+    assert e.value.code == g4.G4_E_OOM
+
+
+def test_slice_size_matches_paper_arithmetic():
+    # 6x6 cluster, 64 fermionic frequencies, 40 planes -> 212,336,640 entries;
+    # a sub-ring of three holds a third of them (Results: accuracy and memory analysis)
+    c = base(lx=6, ly=6, nw=64, nwex=1, nq=36, q_begin=0, q_end=36)
+    e, _ = g4.g4_slice_size(c)
+    assert e == (36 * 64) ** 2 * 36
+    e40 = (36 * 64) ** 2 * 40
+    assert e40 == 212336640
+    c3 = base(lx=6, ly=6, nw=64, nwex=1, nq=36, q_begin=0, q_end=12)
+    assert g4.g4_slice_size(c3)[0] * 3 == e
+
+
+def test_null_handle_calls():
+    with pytest.raises(g4.G4Error) as e:
+        g4._check(g4._L.g4_sync(None))
+    assert e.value.code == g4.G4_E_ARG
+    g4._L.g4_destroy(None)
+
+
+SHAPES = [Workload("3x5", lx=3, ly=5, nw=4, nwex=3, nq=4, q_list=(14, 0, 7, 3), q_begin=2, q_end=11),
+          Workload("6x6", lx=6, ly=6, nw=8, nwex=4, nq=36, q_begin=37, q_end=100),
+          Workload("8x8", lx=8, ly=8, nw=4, nwex=2, nq=64)]
+
+
+@pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
+def test_index_maps_bit_exact(w):
+    c = base(lx=w.lx, ly=w.ly, nw=w.nw, nwex=w.nwex, nq=w.nq, q_list=w.q_list,
+             q_begin=w.q0, q_end=w.q1)
+    ka, ks, pq, pm = g4.g4_index_maps(c)
+    k = np.arange(w.nc)
+    kk, qq = np.meshgrid(k, k, indexing="ij")
+    assert np.array_equal(ka.reshape(w.nc, w.nc), sampled._mom_add(w, kk, qq))
+    assert np.array_equal(ks.reshape(w.nc, w.nc), sampled._mom_sub(w, kk, qq))   # [q][k] = q - k
+    iQ = np.arange(w.q0, w.q1)
+    assert np.array_equal(pq, np.asarray(w.qs)[iQ // w.nwex])
+    assert np.array_equal(pm, iQ % w.nwex)

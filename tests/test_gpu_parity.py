@@ -1,0 +1,193 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: FP64 products (plain and batched) 1e-12 relative Frobenius error per
+channel; FP32 products 1e-6.  Integer index maps are checked bit-exactly by
+one-hot probes (the output support must equal the oracle's).  Shapes span
+several work tiles, ragged K2 tails, transfer groups cut by the slice bounds,
+and ragged final passes."""
+import numpy as np
+import pytest
+
+from gpu_common import config_for, g4mod, host_inputs, run_slice, to_dev
+from metrics import paper_errors, rel_fro
+from oracle import ref
+from synth import C1_TINY, PH_CHARGE, PH_MAGNETIC, PP_UPDOWN, Workload
+
+pytestmark = pytest.mark.gpu
+
+ALL = PH_MAGNETIC | PH_CHARGE | PP_UPDOWN
+RAGGED = Workload("ragged", lx=3, ly=2, nw=24, nwex=5, nq=6, q_list=(4, 0, 5, 1, 3, 2),
+                  q_begin=3, q_end=27, beta=7.0, seed=21, wid=21, channels=ALL)
+MULTI = Workload("multi-tile", lx=4, ly=2, nw=64, nwex=3, nq=8, q_begin=0, q_end=24,
+                 beta=9.0, seed=22, wid=22, channels=ALL)
+NW128 = Workload("nw128", lx=2, ly=1, nw=128, nwex=9, nq=2, q_begin=4, q_end=15,
+                 beta=10.0, seed=23, wid=23, channels=ALL)
+TINY_ALL = C1_TINY.with_(channels=ALL)
+
+_cache = {}
+
+
+def oracle_out(w, count, channels):
+    key = (w, count, channels)
+    if key not in _cache:
+        gu, gd, s = host_inputs(w, count)
+        _cache[key] = {ch: ref.accumulate(w, ch, gu, gd, s) for ch in (1, 2, 4) if channels & ch}
+    return _cache[key]
+
+
+def check(got, want, tol):
+    for ch, v in want.items():
+        err = rel_fro(got[ch], v)
+        assert err <= tol, (ch, err, paper_errors(got[ch], v))
+
+
+@pytest.mark.parametrize("w,count", [(C1_TINY, 64), (TINY_ALL, 8), (RAGGED, 5), (MULTI, 3),
+                                     (NW128, 3)], ids=lambda x: getattr(x, "name", str(x)))
+def test_plain_fp64(w, count):
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=0)
+    got, st = run_slice(cfg, to_dev(gu, 0), to_dev(gd, 0), s, chunks=[0, 1, count])
+    assert st["measurements"] == count and st["launches"] == count
+    assert st["sign_sum"] == s.sum()
+    check(got, oracle_out(w, count, w.channels), 1e-12)
+
+
+@pytest.mark.parametrize("w,count,B,tile", [(RAGGED, 7, 3, 0), (RAGGED, 7, 8, 20), (MULTI, 4, 4, 0),
+                                            (NW128, 5, 2, 0), (TINY_ALL, 8, 8, 0)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_batched_fp64_inputs(w, count, B, tile):
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=0, g_in=0, acc=0, batch=B, tile=tile)
+    got, st = run_slice(cfg, to_dev(gu, 0), to_dev(gd, 0), s)
+    assert st["launches"] == -(-count // B)
+    check(got, oracle_out(w, count, w.channels), 1e-12)
+
+
+@pytest.mark.parametrize("g_in", [0, 1], ids=["c128-in", "c64-in"])
+@pytest.mark.parametrize("acc", [0, 1, 2], ids=["acc-c128", "acc-kahan", "acc-c64"])
+@pytest.mark.parametrize("w,count,B", [(RAGGED, 7, 3), (MULTI, 4, 4), (NW128, 5, 4)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_batched_fp32(w, count, B, g_in, acc):
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=1, g_in=g_in, acc=acc, batch=B)
+    got, _ = run_slice(cfg, to_dev(gu, g_in), to_dev(gd, g_in), s)
+    check(got, oracle_out(w, count, w.channels), 1e-6)
+
+
+ONE_HOT = [(0, 0, 0), (0, 5, 7), (1, 31, 2), (0, 167, 0), (1, 100, 167), (0, 27, 28)]
+
+
+@pytest.mark.parametrize("mode,prod", [(0, 0), (1, 1)], ids=["plain-fp64", "batched-fp32"])
+def test_one_hot_support(mode, prod):
+    w = RAGGED
+    g_in = 0 if prod == 0 else 1
+    for spin, r, c in ONE_HOT:
+        gu = np.zeros((1, w.ng, w.ng), dtype=np.complex128)
+        gd = np.zeros_like(gu)
+        (gu if spin == 0 else gd)[0, r, c] = 1.0 + 0.5j
+        # a second element on the diagonal of the other spin makes direct terms appear
+        (gd if spin == 0 else gu)[0, (r * 7 + 3) % w.ng, (r * 7 + 3) % w.ng] = -0.75 + 0.25j
+        s = np.ones(1)
+        want = {ch: ref.accumulate(w, ch, gu, gd, s) for ch in (1, 2, 4)}
+        got, _ = run_slice(config_for(w, mode=mode, prod=prod, g_in=g_in, batch=1),
+                           to_dev(gu, g_in), to_dev(gd, g_in), s)
+        for ch in want:
+            assert np.array_equal(got[ch] != 0, want[ch] != 0), (spin, r, c, ch)
+
+
+def test_determinism_bitwise():
+    w = MULTI
+    gu, gd, s = host_inputs(w, 3)
+    for kw in (dict(mode=0), dict(mode=1, prod=1, g_in=1, acc=1, batch=3)):
+        cfg = config_for(w, **kw)
+        a, _ = run_slice(cfg, to_dev(gu, cfg.c.g_in), to_dev(gd, cfg.c.g_in), s)
+        b, _ = run_slice(cfg, to_dev(gu, cfg.c.g_in), to_dev(gd, cfg.c.g_in), s)
+        for ch in a:
+            assert np.array_equal(a[ch], b[ch])
+
+
+def test_slice_union_bitwise():
+    w = RAGGED
+    gu, gd, s = host_inputs(w, 3)
+    dgu, dgd = to_dev(gu, 0), to_dev(gd, 0)
+    full, _ = run_slice(config_for(w, mode=0, q_begin=0, q_end=w.nQ), dgu, dgd, s)
+    cuts = [0, 4, 5, 13, 22, w.nQ]
+    parts = [run_slice(config_for(w, mode=0, q_begin=a, q_end=b), dgu, dgd, s)[0]
+             for a, b in zip(cuts[:-1], cuts[1:])]
+    for ch in full:
+        assert np.array_equal(np.concatenate([p[ch] for p in parts]), full[ch])
+
+
+@pytest.mark.parametrize("kw", [dict(mode=0), dict(mode=1, prod=1, g_in=1, acc=1, batch=2),
+                                dict(mode=1, prod=1, g_in=1, acc=2, batch=2)],
+                         ids=["plain", "kahan", "c64"])
+def test_checkpoint_resume(kw):
+    g4 = g4mod()
+    w = RAGGED
+    gu, gd, s = host_inputs(w, 6)
+    cfg = config_for(w, **kw)
+    dgu, dgd = to_dev(gu, cfg.c.g_in), to_dev(gd, cfg.c.g_in)
+    whole, st_whole = run_slice(cfg, dgu, dgd, s)
+    h = g4.g4_init_slice(cfg)
+    g4.g4_accumulate(h, dgu[:4], dgd[:4], s[:4])
+    saved = {ch: g4.g4_readback(h, ch) for ch in (1, 2, 4)}
+    st = g4.g4_stats(h)
+    g4.g4_destroy(h)
+    h = g4.g4_init_slice(cfg)
+    for ch, v in saved.items():
+        g4.g4_load(h, ch, 0, v)
+    g4.g4_set_counts(h, st["measurements"], st["sign_sum"])
+    g4.g4_accumulate(h, dgu[4:], dgd[4:], s[4:])
+    st2 = g4.g4_stats(h)
+    res = {ch: g4.g4_readback(h, ch).reshape(whole[ch].shape) for ch in (1, 2, 4)}
+    g4.g4_destroy(h)
+    assert st2["measurements"] == 6 and st2["sign_sum"] == s.sum()
+    for ch in whole:
+        if kw["mode"] == 0:
+            assert np.array_equal(res[ch], whole[ch])
+        else:
+            # a float accumulator restarts from its own rounded value
+            assert rel_fro(res[ch], whole[ch]) < 1e-6
+
+
+def test_device_generator_matches_host():
+    import torch
+    g4 = g4mod()
+    w = RAGGED
+    gu, gd, _ = host_inputs(w, 2, b0=5)
+    for dtype, tdt in ((0, torch.complex128), (1, torch.complex64)):
+        for spin, host in ((0, gu), (1, gd)):
+            out = torch.empty((2, w.ng, w.ng), dtype=tdt, device="cuda")
+            g4.g4_synth_fill(out, dtype, w.lx, w.ly, w.nw, w.nwex, w.beta, w.t, w.mu, w.h,
+                             w.noise, w.seed, w.wid, 5, 2, spin)
+            torch.cuda.synchronize()
+            dev = out.cpu().numpy().astype(np.complex128)
+            tol = 1e-14 if dtype == 0 else 1e-7
+            assert np.abs(dev - host).max() <= tol * np.abs(host).max()
+
+
+def test_argument_errors_on_device():
+    import torch
+    g4 = g4mod()
+    w = RAGGED
+    cfg = config_for(w, mode=0)
+    h = g4.g4_init_slice(cfg)
+    try:
+        small = torch.zeros((1, w.ng, w.ng - 1), dtype=torch.complex128, device="cuda")
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_accumulate(h, small, small, [1.0])
+        assert e.value.code == g4.G4_E_ARG
+        wrong = torch.zeros((1, w.ng, w.ng), dtype=torch.complex64, device="cuda")
+        with pytest.raises(g4.G4Error):
+            g4.g4_accumulate(h, wrong, wrong, [1.0])
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_readback(h, 1, h.entries - 1, 2)
+        assert e.value.code == g4.G4_E_ARG
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_readback(h, 8, 0, 1)
+        assert e.value.code == g4.G4_E_ARG
+        g4.g4_accumulate(h, torch.zeros((0,), dtype=torch.complex128, device="cuda"),
+                         torch.zeros((0,), dtype=torch.complex128, device="cuda"), [], 0)
+        assert g4.g4_stats(h)["measurements"] == 0
+    finally:
+        g4.g4_destroy(h)
