@@ -1,0 +1,245 @@
+"""Benchmark of the G4 slice accumulation on one MI355X.
+
+Workload: the 4x4-cluster slice (Nc=16, Nw=64 fermionic frequencies, Nq=16
+momentum transfers, Nwex=8 bosonic transfers; 134,217,728 entries of the
+particle-hole magnetic channel), seeded synthetic Hubbard-shaped G.
+
+A step is one g4_accumulate call of B measurements through the batched
+mixed-precision path (G in complex64, FP32 products, complex128 accumulator):
+direct-term gather plus the fused slice-update pass.  The plain FP64
+per-measurement path (complex128 G and accumulator, one pass per measurement)
+is timed on the same slice for comparison.  Inputs are resident in HBM before
+the timed region; the slice is zeroed after the warm-up steps.
+
+Printed: one JSON line with the entry-update rate (entries x measurements per
+second), the dominant kernel's roofline position (its average launch time from
+HIP events recorded around each launch on the stream it runs on), the sampled
+error against the FP64 oracle, and the oracle's own rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G4 entry-updates/s per GPU (plain FP64 vs batched mixed) at stated error; % HBM/MFMA peak"
+HBM_PEAK = 8.0e12                                   # bytes/s, MI355X HBM3E
+ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9                 # FP32 or FP64 FMA, non-packed: 78.6 TFLOP/s
+FLOPS_PER_EU = {1: 24, 2: 24, 4: 16}                 # per channel: direct 8 + exchange 16; PP 16
+
+
+def algorithmic(E, ng, B, g_bytes, acc_bytes, channels):
+    """Bytes and flops one update launch must move/do: accumulator read+write
+    for every entry, each G element of the pass read once; flops of the
+    products and sums."""
+    nch = bin(channels).count("1")
+    bytes_ = 2 * acc_bytes * E * nch + 2 * B * ng * ng * g_bytes
+    flops = sum(FLOPS_PER_EU[c] for c in (1, 2, 4) if channels & c) * E * B
+    return bytes_, flops
+
+
+def roofline(E, ng, B, g_bytes, acc_bytes, channels, launch_s):
+    by, fl = algorithmic(E, ng, B, g_bytes, acc_bytes, channels)
+    t_hbm = by / HBM_PEAK
+    t_alu = fl / ALU_PEAK
+    if t_hbm >= t_alu:
+        ach = by / launch_s / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": ach / (HBM_PEAK / 1e9), "traffic": None,
+                "algorithmic_bytes_per_launch": by}
+    ach = fl / launch_s / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": ach / (ALU_PEAK / 1e12), "traffic": None, "algorithmic_flops_per_launch": fl}
+
+
+def sampled_error(w, h, g4, channel, b_seq, sign_seq, nsample):
+    """Relative Frobenius error of sampled slice entries against the oracle."""
+    from oracle import sampled
+    idx = sampled.sample_indices(w, nsample, seed=777)
+    got = np.array([g4.g4_readback(h, channel, int(i), 1)[0] for i in idx])
+    want = np.zeros(len(idx), dtype=np.complex128)
+    # the oracle sums in measurement order over the same sequence
+    start = 0
+    while start < len(b_seq):
+        b0 = b_seq[start]
+        run = 1
+        while start + run < len(b_seq) and b_seq[start + run] == b0 + run:
+            run += 1
+        want += sampled.entries(w, channel, idx, b0=b0, count=run, sign=sign_seq[start:start + run])
+        start += run
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    return err, len(idx)
+
+
+def cpu_baseline(w, seconds):
+    """The oracle, as it stands, on the host cores over a bounded sample."""
+    from oracle import ref
+    from synth import g_matrices, signs
+    nd = 2
+    gu = g_matrices(w, 0, nd, 0)
+    gd = g_matrices(w, 0, nd, 1)
+    s = signs(w, 0, nd)
+    g4 = np.zeros((w.planes, w.n, w.n), dtype=np.complex128)
+    t0 = time.perf_counter()
+    ref.accumulate(w, 1, gu[:1], gd[:1], s[:1], g4=g4)
+    t1 = time.perf_counter() - t0
+    m = max(1, int(seconds / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    for j in range(m):
+        ref.accumulate(w, 1, gu[j % nd:j % nd + 1], gd[j % nd:j % nd + 1], s[j % nd:j % nd + 1], g4=g4)
+    t = time.perf_counter() - t0
+    return {"value": w.entries * m / t, "unit": "entry-updates/s", "cores": ref.max_threads(),
+            "kind": "oracle",
+            "sample": "%d measurements (PH magnetic) over the whole %d-entry slice, C oracle, "
+                      "OpenMP over slice rows" % (m, w.entries)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--acc", default="c128", choices=["c128", "kahan"])
+    ap.add_argument("--plain-measurements", type=int, default=64)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--pool", type=int, default=1024, help="distinct measurements resident in HBM")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the slice is one GPU's share and no "
+              "multi-GPU path is built (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2105_00027_amd import g4
+    from synth import C2_PLAIN, signs
+
+    w = C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    # an explicit stream (default priority): the library enqueues on it and the
+    # timing events are recorded on it
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    sptr = stream.cuda_stream
+    E, ng, B = w.entries, w.ng, args.batch
+
+    def fill(buf, dtype, b0, count, spin):
+        g4.g4_synth_fill(buf, dtype, w.lx, w.ly, w.nw, w.nwex, w.beta, w.t, w.mu, w.h, w.noise,
+                         w.seed, w.wid, b0, count, spin, sptr)
+
+    def cfg(**kw):
+        return g4.Config(lx=w.lx, ly=w.ly, nw=w.nw, nwex=w.nwex, nq=w.nq, q_begin=w.q0, q_end=w.q1,
+                         channels=w.channels, beta=w.beta, stream=sptr,
+                         flags=g4.G4_F_KERNEL_TIMING, **kw)
+
+    out = {"metric": METRIC, "unit": "entry-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+
+    # ---- batched mixed precision (the headline) -------------------------------
+    total = (args.warmup + args.steps) * B
+    pool = max(B, min(args.pool, total))
+    pool -= pool % B
+    gu = torch.empty((pool, ng, ng), dtype=torch.complex64, device=dev)
+    gd = torch.empty_like(gu)
+    fill(gu, g4.G4_IN_C64, 0, pool, 0)
+    fill(gd, g4.G4_IN_C64, 0, pool, 1)
+    sg = signs(w, 0, pool)
+    acc = g4.G4_ACC_C128 if args.acc == "c128" else g4.G4_ACC_C64_KAHAN
+    h = g4.g4_init_slice(cfg(mode=g4.G4_MODE_BATCHED, prod=g4.G4_PROD_F32, g_in=g4.G4_IN_C64,
+                             acc=acc, max_batch=B, tile=args.tile))
+    nblk = pool // B
+
+    def step(i):
+        j = i % nblk
+        g4.g4_accumulate(h, gu[j * B:(j + 1) * B], gd[j * B:(j + 1) * B], sg[j * B:(j + 1) * B])
+
+    for i in range(args.warmup):
+        step(i)
+    g4.g4_sync(h)
+    g4.g4_reset(h)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    b_seq = []
+    e0.record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i)
+        j = (args.warmup + i) % nblk
+        b_seq.extend(range(j * B, (j + 1) * B))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = g4.g4_stats(h)
+    launch_s = st["kernel_ms"] / max(1, st["timed_launches"]) / 1e3
+    value = E * args.steps * B / (ms / 1e3)
+    out["value"] = value
+    out["ms_per_step"] = ms / args.steps
+    out["config"] = {"workload": "4x4 Hubbard cluster G4 slice: Nc=16, Nw=64, Nq=16, Nwex=8, "
+                                 "E=%d entries, PH magnetic, batched B=%d, complex64 G, FP32 "
+                                 "products, %s accumulator" % (E, B, args.acc),
+                     "entries": E, "batch": B, "tile": st["tile"], "accumulator": args.acc,
+                     "measurements_timed": args.steps * B}
+    out["kernel"] = {"name": "update_kernel", "avg_launch_ms": launch_s * 1e3,
+                     "launches": st["timed_launches"]}
+    out["roofline"] = roofline(E, ng, B, 8, 16, w.channels, launch_s)
+    if not args.no_check:
+        err, ns = sampled_error(w, h, g4, 1, b_seq, sg[b_seq], 256)
+        out["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-6}
+    g4.g4_destroy(h)
+    del gu, gd
+    torch.cuda.empty_cache()
+
+    # ---- plain FP64, one pass per measurement ------------------------------
+    if not args.no_plain:
+        M = args.plain_measurements
+        pu = torch.empty((M, ng, ng), dtype=torch.complex128, device=dev)
+        pd = torch.empty_like(pu)
+        fill(pu, g4.G4_IN_C128, 0, M, 0)
+        fill(pd, g4.G4_IN_C128, 0, M, 1)
+        ps = signs(w, 0, M)
+        hp = g4.g4_init_slice(cfg(mode=g4.G4_MODE_PLAIN))
+        g4.g4_accumulate(hp, pu[:2], pd[:2], ps[:2])      # warm-up
+        g4.g4_sync(hp)
+        g4.g4_reset(hp)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g4.g4_accumulate(hp, pu, pd, ps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1)
+        pst = g4.g4_stats(hp)
+        plaunch = pst["kernel_ms"] / max(1, pst["timed_launches"]) / 1e3
+        pval = E * M / (pms / 1e3)
+        plain = {"value": pval, "unit": "entry-updates/s", "measurements": M,
+                 "ms_per_measurement": pms / M, "dtype": "f64", "tile": pst["tile"],
+                 "kernel_avg_launch_ms": plaunch * 1e3,
+                 "roofline": roofline(E, ng, 1, 16, 16, w.channels, plaunch)}
+        if not args.no_check:
+            err, ns = sampled_error(w, hp, g4, 1, list(range(M)), ps, 256)
+            plain["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-12}
+        g4.g4_destroy(hp)
+        del pu, pd
+        torch.cuda.empty_cache()
+        out["plain_fp64"] = plain
+        out["speedup_vs_plain_fp64"] = value / pval
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

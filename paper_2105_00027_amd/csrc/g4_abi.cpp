@@ -43,6 +43,7 @@ int popcount3(uint32_t c) { return (c & 1) + ((c >> 1) & 1) + ((c >> 2) & 1); }
 struct Plan {
     Dims d;
     int prec;          // 0 FP64 products, 1 FP32
+    int kind;          // update kernel: 0 plain FP64, 1 batched FP64, 2 batched FP32
     int batch;         // measurements per pass
     int mgroup;        // transfer planes per work tile (compile-time bound)
     int tile;          // K2 rows per work tile
@@ -120,6 +121,8 @@ int validate(const g4_config *c, Plan *p) {
     const int64_t ng = (int64_t)nc * d.nwg;
     const int64_t n = (int64_t)nc * c->nw;
     if (ng > (1 << 20) || n > (1 << 20)) return fail(G4_E_ARG, "G side %lld too large", (long long)ng);
+    if (ng * ng >= (int64_t)1 << 31)
+        return fail(G4_E_UNSUPPORTED, "G side %lld: matrices above 2^31 elements", (long long)ng);
     d.ng = (int)ng;
     d.n = (int)n;
     d.planes = (int)(c->q_end - c->q_begin);
@@ -132,6 +135,7 @@ int validate(const g4_config *c, Plan *p) {
     if (c->prod == G4_PROD_BF16X2 || c->prod == G4_PROD_F16X2)
         return fail(G4_E_UNSUPPORTED, "split-precision products are not available in this build");
     P.prec = c->prod == G4_PROD_F64 ? 0 : 1;
+    P.kind = c->mode == G4_MODE_PLAIN ? 0 : (P.prec == 0 ? 1 : 2);
     P.batch = c->mode == G4_MODE_PLAIN ? 1 : c->max_batch;
     P.mgroup = choose_mgroup(c->nwex);
     const int nch = popcount3(c->channels);
@@ -145,7 +149,7 @@ int validate(const g4_config *c, Plan *p) {
         P.ept = choose_ept(P.prec, nch, P.mgroup, c->nw);
     }
     P.tile = P.ept * rp;
-    if (update_lds_bytes(P.prec, (int)c->channels, P.tile, P.mgroup, d) > 160 * 1024)
+    if (update_lds_bytes(P.kind, (int)c->channels, P.tile, P.mgroup, d) > 160 * 1024)
         return fail(G4_E_UNSUPPORTED, "LDS tile above 160 KiB");
     P.slots = c->channels & 3u;
     P.nslots = popcount3(P.slots);
@@ -154,6 +158,8 @@ int validate(const g4_config *c, Plan *p) {
     const uint64_t el = P.prec == 0 ? 16 : 8;
     P.acc_bytes = P.entries * (uint64_t)acc_entry_bytes(c->acc);
     P.dir_bytes = 2ull * P.nslots * P.batch * (uint64_t)d.planes * n * el;
+    if ((uint64_t)P.nslots * P.batch * d.planes * n >= (1ull << 31))
+        return fail(G4_E_UNSUPPORTED, "direct-term vectors above 2^31 elements; lower max_batch");
     P.stage_bytes = (P.prec == 1 && c->g_in == G4_IN_C128) ? 2ull * P.batch * ng * ng * 8 : 0;
     P.sign_bytes = (uint64_t)kSignSlots * kMaxBatch * sizeof(double);
     P.scratch_bytes = (c->acc == G4_ACC_C128 ? 0 : std::min<uint64_t>(P.entries, kScratchEntries) * 16);
@@ -408,7 +414,7 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
         if (rc) return rc;
         G4_HIP(h, hipEventRecord(e0, h->stream));
     }
-    G4_HIP(h, launch_update(P.prec, (int)h->cfg.channels, P.ept, P.mgroup, h->nitems, ua, h->stream));
+    G4_HIP(h, launch_update(P.kind, (int)h->cfg.channels, P.ept, P.mgroup, h->nitems, ua, h->stream));
     if (timing) {
         G4_HIP(h, hipEventRecord(e1, h->stream));
         h->ev_pending.emplace_back(e0, e1);

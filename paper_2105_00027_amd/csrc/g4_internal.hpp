@@ -67,11 +67,13 @@ struct GatherArgs {
     Tables t;
 };
 
-// Kernel launchers (g4_kernels.hip).  `prec` 0 = FP64, 1 = FP32.
+// Kernel launchers (g4_kernels.hip).  Gather `prec` 0 = FP64, 1 = FP32.
+// Update `kind` 0 = plain FP64 (one measurement per pass), 1 = batched FP64,
+// 2 = batched FP32.
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
-hipError_t launch_update(int prec, int channels, int ept, int mgroup, int nitems,
+hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems,
                          const UpdateArgs &a, hipStream_t s);
-size_t update_lds_bytes(int prec, int channels, int tile, int mgroup, const Dims &d);
+size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d);
 hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s);
 hipError_t launch_acc_to_c128(int acc_kind, const void *acc, uint64_t first, uint64_t count,
                               double *dst, hipStream_t s);

@@ -110,20 +110,24 @@ int grid_for(int64_t work, int threads) {
 
 }  // namespace
 
-#define G4_DECL(p, e)                                                                        \
-    hipError_t launch_update_p##p##_e##e(int channels, int mgroup, int nitems, size_t lds, \
+#define G4_DECL(k, e)                                                                        \
+    hipError_t launch_update_k##k##_e##e(int channels, int mgroup, int nitems, size_t lds, \
                                          const UpdateArgs &a, hipStream_t s);
-G4_DECL(0, 1) G4_DECL(0, 2) G4_DECL(0, 4) G4_DECL(0, 8)
-G4_DECL(1, 1) G4_DECL(1, 2) G4_DECL(1, 4) G4_DECL(1, 8)
+#define G4_DECL_KIND(k) G4_DECL(k, 1) G4_DECL(k, 2) G4_DECL(k, 4) G4_DECL(k, 8)
+G4_DECL_KIND(0) G4_DECL_KIND(1) G4_DECL_KIND(2)
+#undef G4_DECL_KIND
 #undef G4_DECL
 
-size_t update_lds_bytes(int prec, int channels, int tile, int mgroup, const Dims &d) {
-    const size_t el = prec == 0 ? sizeof(double2) : sizeof(float2);
+size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d) {
+    // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct vectors
+    const size_t el = kind == 2 ? sizeof(float2) : sizeof(double2);
     const int T2 = tile < d.nw ? tile : d.nw;
-    size_t words = 0;
-    if (channels & (CH_MAG | CH_CHG)) words += 2 * (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
-    if (channels & CH_PP) words += 2 * (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
-    return words * el;
+    const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
+    size_t pairs = (size_t)T2 * d.nw;
+    if (nph) pairs += (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
+    if (channels & CH_PP) pairs += (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
+    const size_t vecs = (size_t)nph * mgroup * (d.nw + T2);
+    return pairs * 2 * el + vecs * el;
 }
 
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s) {
@@ -137,21 +141,20 @@ hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_update(int prec, int channels, int ept, int mgroup, int nitems,
+hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems,
                          const UpdateArgs &a, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    const size_t lds = update_lds_bytes(prec, channels, a.tile, mgroup, a.d);
-    switch (prec * 16 + ept) {
-        case 1: return launch_update_p0_e1(channels, mgroup, nitems, lds, a, s);
-        case 2: return launch_update_p0_e2(channels, mgroup, nitems, lds, a, s);
-        case 4: return launch_update_p0_e4(channels, mgroup, nitems, lds, a, s);
-        case 8: return launch_update_p0_e8(channels, mgroup, nitems, lds, a, s);
-        case 17: return launch_update_p1_e1(channels, mgroup, nitems, lds, a, s);
-        case 18: return launch_update_p1_e2(channels, mgroup, nitems, lds, a, s);
-        case 20: return launch_update_p1_e4(channels, mgroup, nitems, lds, a, s);
-        case 24: return launch_update_p1_e8(channels, mgroup, nitems, lds, a, s);
+    const size_t lds = update_lds_bytes(kind, channels, a.tile, mgroup, a.d);
+#define G4_K(k)                                                                     \
+    case k * 16 + 1: return launch_update_k##k##_e1(channels, mgroup, nitems, lds, a, s); \
+    case k * 16 + 2: return launch_update_k##k##_e2(channels, mgroup, nitems, lds, a, s); \
+    case k * 16 + 4: return launch_update_k##k##_e4(channels, mgroup, nitems, lds, a, s); \
+    case k * 16 + 8: return launch_update_k##k##_e8(channels, mgroup, nitems, lds, a, s);
+    switch (kind * 16 + ept) {
+        G4_K(0) G4_K(1) G4_K(2)
         default: return hipErrorInvalidValue;
     }
+#undef G4_K
 }
 
 hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s) {

@@ -1,5 +1,5 @@
 // Slice-update kernel template for gfx950, included by g4_update_inst.hip,
-// which is compiled once per (precision, K2 rows per thread) pair.
+// which is compiled once per (kind, K2 rows per thread) pair.
 //
 // Per measurement b (weight s_b) and slice entry (Q, K2, K1):
 //   PH magnetic/charge: s_b [ D(K1+Q,K1) D(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q) ],
@@ -7,18 +7,24 @@
 //   PP (Eq. (1) of the paper, K3 -> Q): s_b sum_s G_s(Q-K2,Q-K1) G_{-s}(K2,K1)
 //
 // One work tile = (plane group {q, m-range}, k1, k2, K2-frequency rows
-// [c0, c0+tile)).  Per measurement the block stages into LDS the G sub-blocks
-// holding the exchange operand (rows k1+q, columns k2+q) and the PP operand
-// (rows q-k2, columns q-k1), reads G(K2,K1) straight from memory (coalesced
-// along K1), takes the direct-term vectors built by the gather kernel, and
-// accumulates the pass's measurements in registers; then every slice entry
-// is read, updated and written exactly once (no atomics, deterministic).
+// [c0, c0+tile)).  Per measurement the block stages into LDS, both spins side
+// by side, the G sub-blocks that hold the exchange operand (rows k1+q, columns
+// k2+q; column-major so that lanes walking K1 read consecutive words) and the
+// PP operand (rows q-k2, columns q-k1; row-major, lanes read a descending
+// run), plus the direct-term vector b(Q,K2) of the tile's rows.  G(K2,K1) and
+// a(Q,K1) are read straight from memory, coalesced along K1, and reused over
+// the tile's planes and rows.  The pass's measurements are summed in
+// registers; then every slice entry is read, updated and written exactly once
+// (no atomics, deterministic).  In the plain FP64 kind (one measurement per
+// pass) the accumulators are loaded before the tile is staged so that the
+// HBM reads overlap the staging and the arithmetic.
 // Lanes run along K1 frequencies, so each G4 access of a wavefront is one
 // contiguous run of nw complex values.
 #pragma once
 
-#include "g4_internal.hpp"
+#include <type_traits>
 
+#include "g4_internal.hpp"
 
 namespace g4 {
 namespace upd {
@@ -26,6 +32,11 @@ namespace upd {
 template <typename R> struct Cx;
 template <> struct Cx<double> { using V = double2; };
 template <> struct Cx<float> { using V = float2; };
+
+template <typename V>
+struct SpinPair {
+    V u, d;
+};
 
 template <typename V>
 __device__ __forceinline__ V cmul(V a, V b) {
@@ -44,6 +55,21 @@ __device__ __forceinline__ void cmac(V &acc, V a, V b) {
     acc.y = fma(a.y, b.x, acc.y);
 }
 
+// Member-wise copies: whole-struct copies of double2 between address spaces
+// become memcpy calls that keep register arrays in scratch.
+template <typename V>
+__device__ __forceinline__ V ld(const V *p) {
+    V v;
+    v.x = p->x;
+    v.y = p->y;
+    return v;
+}
+template <typename V>
+__device__ __forceinline__ void st(V *p, V v) {
+    p->x = v.x;
+    p->y = v.y;
+}
+
 template <typename V, typename R>
 __device__ __forceinline__ V cscale(V a, R s) {
     V r;
@@ -52,7 +78,6 @@ __device__ __forceinline__ V cscale(V a, R s) {
     return r;
 }
 
-// ---------------------------------------------------------------------------
 // Accumulator read-modify-write of one entry.
 template <typename V>
 __device__ __forceinline__ void acc_update(void *base, int kind, int64_t e, V v) {
@@ -63,7 +88,7 @@ __device__ __forceinline__ void acc_update(void *base, int kind, int64_t e, V v)
         o.y += (double)v.y;
         *p = o;
     } else if (kind == ACC_C64_KAHAN) {
-        // {sum.re, sum.im, comp.re, comp.im}; comp holds the negated lost low part
+        // {sum.re, sum.im, comp.re, comp.im}; value = sum - comp
         float4 *p = static_cast<float4 *>(base) + e;
         float4 o = *p;
         float yr = (float)v.x - o.z;
@@ -84,7 +109,19 @@ __device__ __forceinline__ void acc_update(void *base, int kind, int64_t e, V v)
     }
 }
 
-constexpr int NT = 256;
+// Calls f(integral_constant<int, I>) for I = B..E-1: array indices stay
+// compile-time constants without relying on loop unrolling.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+constexpr int NT = 256;   // threads per block
+constexpr int SX = 32;    // staging lanes along a G row
+constexpr int SY = NT / SX;
 
 template <int CH>
 struct ChanInfo {
@@ -93,22 +130,34 @@ struct ChanInfo {
     static constexpr bool pp = (CH & CH_PP) != 0;
     static constexpr bool ph = mag || chg;
     static constexpr int count = (mag ? 1 : 0) + (chg ? 1 : 0) + (pp ? 1 : 0);
+    static constexpr int nph = (mag ? 1 : 0) + (chg ? 1 : 0);
     static constexpr int slot_chg = mag ? 1 : 0;
-    static constexpr int slot_pp = (mag ? 1 : 0) + (chg ? 1 : 0);
+    static constexpr int slot_pp = nph;
 };
 
-// LDS: PH exchange tiles Y_s stored column-major (row index fastest) so that
-// lanes (consecutive K1 rows of G) read consecutive words; PP tiles Z_s
-// row-major (lanes read descending consecutive columns).
-template <typename R, int EPT, int MG, int CH>
+// Kind: 0 plain FP64 (one measurement, c128 accumulator, prefetched);
+//       1 batched FP64; 2 batched FP32.
+template <int KIND> struct KindInfo;
+template <> struct KindInfo<0> { using R = double; static constexpr bool prefetch = true; };
+template <> struct KindInfo<1> { using R = double; static constexpr bool prefetch = false; };
+template <> struct KindInfo<2> { using R = float; static constexpr bool prefetch = false; };
+
+// Staging slots per thread held in registers across the compute of the
+// previous measurement (G-block elements, both spins; direct-vector elements).
+constexpr int NSG = 8;
+constexpr int NSV = 4;
+
+template <int KIND, int EPT, int MG, int CH>
 __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
+    using R = typename KindInfo<KIND>::R;
     using V = typename Cx<R>::V;
+    using P = SpinPair<V>;
     using CI = ChanInfo<CH>;
+    constexpr bool PF = KindInfo<KIND>::prefetch;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    V *smem = reinterpret_cast<V *>(smem_raw);
 
     const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n, planes = a.d.planes;
-    const int64_t ng = a.d.ng;
+    const int ng = a.d.ng;
     const int4 it = a.t.items[blockIdx.x];
     const int4 gr = a.t.groups[it.x];
     const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
@@ -120,132 +169,234 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     const int i1 = tid % nw;
     const int r0 = tid / nw;
 
-    const int yr = nw + M - 1, yc = T2 + M - 1;    // exchange tile: rows x cols
-    const int zr = T2 + M - 1, zc = nw + M - 1;    // PP tile
-    V *Y0 = smem;
-    V *Y1 = Y0 + (CI::ph ? yr * yc : 0);
-    V *Z0 = Y1 + (CI::ph ? yr * yc : 0);
-    V *Z1 = Z0 + (CI::pp ? zr * zc : 0);
+    // ---- LDS layout: [Y | Z | X] spin pairs, then [A | Bv] direct vectors
+    const int yr = nw + M - 1, yc = T2 + M - 1;    // exchange operand block
+    const int zr = T2 + M - 1, zc = nw + M - 1;    // PP operand block
+    const int nY = CI::ph ? yr * yc : 0;
+    const int nZ = CI::pp ? zr * zc : 0;
+    const int nX = T2 * nw;                        // G(K2, K1) rows of the tile
+    const int nG = nY + nZ + nX;
+    const int nA = CI::nph * M * nw;               // a(Q, K1) per PH channel
+    const int nB = CI::nph * M * T2;               // b(Q, K2) per PH channel
+    const int nV = nA + nB;
+    P *Yt = reinterpret_cast<P *>(smem_raw);
+    P *Zt = Yt + nY;
+    P *Xt = Zt + nZ;
+    V *At = reinterpret_cast<V *>(Xt + nX);
+    V *Bt = At + nA;
 
-    const int64_t rowY = CI::ph ? (int64_t)a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
-    const int64_t colY = CI::ph ? (int64_t)a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
-    const int64_t rowZ = CI::pp ? (int64_t)a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
-    const int64_t colZ = CI::pp ? (int64_t)a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
-    const int64_t rowX = (int64_t)k2 * nwg + c0;
-    const int64_t colX = (int64_t)k1 * nwg + i1;
+    const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
+    const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
+    const int rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
+    const int colZ = CI::pp ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
+    const int rowX = k2 * nwg + c0, colX = k1 * nwg;
 
-    V acc[CI::count][EPT][MG];
-#pragma unroll
-    for (int c = 0; c < CI::count; ++c)
-#pragma unroll
-        for (int j = 0; j < EPT; ++j)
-#pragma unroll
-            for (int m = 0; m < MG; ++m) acc[c][j][m] = V{0, 0};
+    // element e of the staged G blocks -> (offset in G, offset in LDS)
+    auto g_slot = [&](int e, int &goff, int &loff) __attribute__((always_inline)) {
+        if (e < nY) {            // exchange block, stored column-major
+            const int r = e / yc, c = e - r * yc;
+            goff = (rowY + r) * ng + colY + c;
+            loff = c * yr + r;
+        } else if (e < nY + nZ) {   // PP block, row-major
+            const int f = e - nY;
+            const int r = f / zc, c = f - r * zc;
+            goff = (rowZ + r) * ng + colZ + c;
+            loff = nY + f;
+        } else {                 // G(K2, K1) rows, row-major
+            const int f = e - nY - nZ;
+            const int r = f / nw, c = f - r * nw;
+            goff = (rowX + r) * ng + colX + c;
+            loff = nY + nZ + f;
+        }
+    };
+    // element e of the staged direct vectors -> (offset in dir arrays at b = 0, LDS offset)
+    auto v_slot = [&](int e, int &goff, int &loff, bool &isb) __attribute__((always_inline)) {
+        isb = e >= nA;
+        const int f = isb ? e - nA : e;
+        const int w = isb ? T2 : nw;
+        const int sm = f / w, c = f - sm * w;          // sm = slot * M + m
+        const int sl = sm / M, m = sm - sl * M;
+        goff = sl * (int)a.dir_slot_stride + (p0 + m) * n + (isb ? k2 * nw + c0 + c : k1 * nw + c);
+        loff = f;
+    };
+
+    int sg_goff[NSG], sg_loff[NSG];
+    static_for<0, NSG>([&](auto k) {
+        const int e = tid + k * NT;
+        if (e < nG) g_slot(e, sg_goff[k], sg_loff[k]);
+        else sg_goff[k] = sg_loff[k] = -1;
+    });
+    int sv_goff[NSV];
+    int sv_loff[NSV];
+    bool sv_isb[NSV];
+    static_for<0, NSV>([&](auto k) {
+        const int e = tid + k * NT;
+        if (CI::ph && e < nV) v_slot(e, sv_goff[k], sv_loff[k], sv_isb[k]);
+        else { sv_goff[k] = 0; sv_loff[k] = -1; sv_isb[k] = false; }
+    });
 
     const V *dA = static_cast<const V *>(a.dir_a);
     const V *dB = static_cast<const V *>(a.dir_b);
-
-    for (int b = 0; b < a.batch; ++b) {
+    const int64_t vstride = (int64_t)planes * n;     // direct vectors: per measurement
+    V rgu[NSG], rgd[NSG];
+    V rv[NSV];
+    auto fetch = [&](int b) __attribute__((always_inline)) {
         const V *gu = static_cast<const V *>(a.gu) + (int64_t)b * a.g_stride;
         const V *gd = static_cast<const V *>(a.gd) + (int64_t)b * a.g_stride;
-        __syncthreads();
-        if (CI::ph) {
-            const int cnt = yr * yc;
-            for (int e = tid; e < cnt; e += NT) {
-                const int r = e / yc, c = e - (e / yc) * yc;
-                const int64_t g = (rowY + r) * ng + colY + c;
-                Y0[c * yr + r] = gu[g];
-                Y1[c * yr + r] = gd[g];
+        static_for<0, NSG>([&](auto k) {
+            if (sg_loff[k] >= 0) {
+                rgu[k] = ld(gu + sg_goff[k]);
+                rgd[k] = ld(gd + sg_goff[k]);
             }
-        }
-        if (CI::pp) {
-            const int cnt = zr * zc;
-            for (int e = tid; e < cnt; e += NT) {
-                const int r = e / zc, c = e - (e / zc) * zc;
-                const int64_t g = (rowZ + r) * ng + colZ + c;
-                Z0[r * zc + c] = gu[g];
-                Z1[r * zc + c] = gd[g];
+        });
+        if (CI::ph)
+            static_for<0, NSV>([&](auto k) {
+                if (sv_loff[k] >= 0) rv[k] = ld((sv_isb[k] ? dB : dA) + sv_goff[k] + b * vstride);
+            });
+    };
+    auto store = [&](int b) __attribute__((always_inline)) {
+        static_for<0, NSG>([&](auto k) {
+            if (sg_loff[k] >= 0) {
+                st(&Yt[sg_loff[k]].u, rgu[k]);
+                st(&Yt[sg_loff[k]].d, rgd[k]);
             }
+        });
+        if (CI::ph)
+            static_for<0, NSV>([&](auto k) {
+                if (sv_loff[k] >= 0) st((sv_isb[k] ? Bt : At) + sv_loff[k], rv[k]);
+            });
+        // elements beyond the register slots (large tiles): direct copy
+        const V *gu = static_cast<const V *>(a.gu) + (int64_t)b * a.g_stride;
+        const V *gd = static_cast<const V *>(a.gd) + (int64_t)b * a.g_stride;
+        for (int e = tid + NSG * NT; e < nG; e += NT) {
+            int go, lo;
+            g_slot(e, go, lo);
+            st(&Yt[lo].u, ld(gu + go));
+            st(&Yt[lo].d, ld(gd + go));
         }
-        __syncthreads();
+        if (CI::ph)
+            for (int e = tid + NSV * NT; e < nV; e += NT) {
+                int go, lo;
+                bool isb;
+                v_slot(e, go, lo, isb);
+                st((isb ? Bt : At) + lo, ld((isb ? dB : dA) + go + b * vstride));
+            }
+    };
+
+    // entry index of (plane p0, row c0 + r0, column i1); + m*n*n + j*RP*n
+    const int64_t ebase = ((int64_t)p0 * n + k2 * nw + c0 + r0) * n + k1 * nw + i1;
+    const int64_t nn = (int64_t)n * n;
+
+    V acc[CI::count][EPT][MG];
+    static_for<0, CI::count>([&](auto c) {
+        static_for<0, EPT>([&](auto j) {
+            static_for<0, MG>([&](auto m) { acc[c][j][m] = V{0, 0}; });
+        });
+    });
+
+    // plain kind: accumulators in flight while the operands are staged
+    double2 pre[PF ? CI::count : 1][PF ? EPT : 1][PF ? MG : 1];
+    if constexpr (PF) {
+        if (act) {
+            static_for<0, EPT>([&](auto j) {
+                static_for<0, MG>([&](auto m) {
+                    if (r0 + j * RP < T2 && m < M) {
+                        const int64_t e = ebase + m * nn + (int64_t)j * RP * n;
+                        if (CI::mag) pre[0][j][m] = ld(static_cast<const double2 *>(a.acc[0]) + e);
+                        if (CI::chg) pre[CI::slot_chg][j][m] = ld(static_cast<const double2 *>(a.acc[1]) + e);
+                        if (CI::pp) pre[CI::slot_pp][j][m] = ld(static_cast<const double2 *>(a.acc[2]) + e);
+                    }
+                });
+            });
+        }
+    }
+
+    const bool full = (T2 == a.tile) && (M == MG);
+    if (a.batch > 0) fetch(0);
+    for (int b = 0; b < a.batch; ++b) {
+        __syncthreads();          // the previous measurement's operands are consumed
+        store(b);
+        __syncthreads();          // this measurement's operands are in LDS
+        if (b + 1 < a.batch) fetch(b + 1);
         if (!act) continue;
         const R s = (R)a.sign[b];
         V xu[EPT], xd[EPT];
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
+        static_for<0, EPT>([&](auto j) {
+            const int i2l = min(r0 + j * RP, T2 - 1);
+            xu[j] = cscale(ld(&Xt[i2l * nw + i1].u), s);
+            xd[j] = cscale(ld(&Xt[i2l * nw + i1].d), s);
+        });
+        auto body = [&](auto j, auto m) __attribute__((always_inline)) {
             const int i2l = r0 + j * RP;
-            if (i2l < T2) {
-                const int64_t g = (rowX + i2l) * ng + colX;
-                xu[j] = cscale(gu[g], s);
-                xd[j] = cscale(gd[g], s);
-            } else {
-                xu[j] = V{0, 0};
-                xd[j] = V{0, 0};
-            }
-        }
-        const int64_t vbase = (int64_t)b * planes * n;
-#pragma unroll
-        for (int m = 0; m < MG; ++m) {
-            if (m >= M) break;
-            const int64_t vrow = vbase + (int64_t)(p0 + m) * n;
-            V am{0, 0}, ac{0, 0};
-            if (CI::mag) am = dA[vrow + k1 * nw + i1];
-            if (CI::chg) ac = dA[(CI::mag ? a.dir_slot_stride : 0) + vrow + k1 * nw + i1];
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const int i2l = r0 + j * RP;
-                if (i2l >= T2) break;
-                if (CI::ph) {
-                    const V yu = Y0[(i2l + m) * yr + i1 + m];
-                    const V yd = Y1[(i2l + m) * yr + i1 + m];
-                    V ex = cmul(xu[j], yu);
-                    cmac(ex, xd[j], yd);
-                    const int K2 = k2 * nw + c0 + i2l;
-                    if (CI::mag) {
-                        const V bm = dB[vrow + K2];
-                        cmac(acc[0][j][m], am, bm);
-                        acc[0][j][m].x -= ex.x;
-                        acc[0][j][m].y -= ex.y;
-                    }
-                    if (CI::chg) {
-                        const V bc = dB[(CI::mag ? a.dir_slot_stride : 0) + vrow + K2];
-                        cmac(acc[CI::slot_chg][j][m], ac, bc);
-                        acc[CI::slot_chg][j][m].x -= ex.x;
-                        acc[CI::slot_chg][j][m].y -= ex.y;
-                    }
+            if (CI::ph) {
+                const P *y = Yt + (i2l + m) * yr + i1 + m;
+                V ex = cmul(xu[j], ld(&y->u));
+                cmac(ex, xd[j], ld(&y->d));
+                if (CI::mag) {
+                    cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
+                    acc[0][j][m].x -= ex.x;
+                    acc[0][j][m].y -= ex.y;
                 }
-                if (CI::pp) {
-                    const int zi = (m + T2 - 1 - i2l) * zc + m + nw - 1 - i1;
-                    cmac(acc[CI::slot_pp][j][m], Z0[zi], xd[j]);
-                    cmac(acc[CI::slot_pp][j][m], Z1[zi], xu[j]);
+                if (CI::chg) {
+                    const int sm = CI::slot_chg * M + m;
+                    cmac(acc[CI::slot_chg][j][m], ld(At + sm * nw + i1), ld(Bt + sm * T2 + i2l));
+                    acc[CI::slot_chg][j][m].x -= ex.x;
+                    acc[CI::slot_chg][j][m].y -= ex.y;
                 }
             }
+            if (CI::pp) {
+                const P *z = Zt + (m + T2 - 1 - i2l) * zc + m + nw - 1 - i1;
+                cmac(acc[CI::slot_pp][j][m], ld(&z->u), xd[j]);
+                cmac(acc[CI::slot_pp][j][m], ld(&z->d), xu[j]);
+            }
+        };
+        if (full && r0 + (EPT - 1) * RP < T2) {
+            static_for<0, MG>([&](auto m) { static_for<0, EPT>([&](auto j) { body(j, m); }); });
+        } else {
+            static_for<0, MG>([&](auto m) {
+                static_for<0, EPT>([&](auto j) {
+                    if (m < M && r0 + j * RP < T2) body(j, m);
+                });
+            });
         }
     }
     if (!act) return;
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const int i2l = r0 + j * RP;
-        if (i2l >= T2) break;
-#pragma unroll
-        for (int m = 0; m < MG; ++m) {
-            if (m >= M) break;
-            const int64_t e = ((int64_t)(p0 + m) * n + k2 * nw + c0 + i2l) * n + k1 * nw + i1;
-            if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
-            if (CI::chg) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_chg][j][m]);
-            if (CI::pp) acc_update(a.acc[2], a.acc_kind, e, acc[CI::slot_pp][j][m]);
-        }
-    }
+    static_for<0, EPT>([&](auto j) {
+        static_for<0, MG>([&](auto m) {
+            if (!(r0 + j * RP < T2 && m < M)) return;
+            const int64_t e = ebase + m * nn + (int64_t)j * RP * n;
+            if constexpr (PF) {
+                if (CI::mag) {
+                    double2 o = pre[0][j][m];
+                    static_cast<double2 *>(a.acc[0])[e] = double2{o.x + (double)acc[0][j][m].x, o.y + (double)acc[0][j][m].y};
+                }
+                if (CI::chg) {
+                    double2 o = pre[CI::slot_chg][j][m];
+                    const V v = acc[CI::slot_chg][j][m];
+                    static_cast<double2 *>(a.acc[1])[e] = double2{o.x + (double)v.x, o.y + (double)v.y};
+                }
+                if (CI::pp) {
+                    double2 o = pre[CI::slot_pp][j][m];
+                    const V v = acc[CI::slot_pp][j][m];
+                    static_cast<double2 *>(a.acc[2])[e] = double2{o.x + (double)v.x, o.y + (double)v.y};
+                }
+            } else {
+                if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
+                if (CI::chg) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_chg][j][m]);
+                if (CI::pp) acc_update(a.acc[2], a.acc_kind, e, acc[CI::slot_pp][j][m]);
+            }
+        });
+    });
 }
 
-// ---- dispatch of update_kernel instantiations ------------------------------
-template <typename R, int EPT, int MG>
+// ---- dispatch over the compile-time parameters -----------------------------
+template <int KIND, int EPT, int MG>
 hipError_t launch_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, hipStream_t s) {
     const void *fn = nullptr;
     switch (channels) {
-#define G4_CASE(CHV)                                                             \
-    case CHV:                                                                    \
-        fn = reinterpret_cast<const void *>(&update_kernel<R, EPT, MG, CHV>);    \
+#define G4_CASE(CHV)                                                                 \
+    case CHV:                                                                        \
+        fn = reinterpret_cast<const void *>(&update_kernel<KIND, EPT, MG, CHV>);     \
         break;
         G4_CASE(1) G4_CASE(2) G4_CASE(3) G4_CASE(4) G4_CASE(5) G4_CASE(6) G4_CASE(7)
 #undef G4_CASE
@@ -261,13 +412,13 @@ hipError_t launch_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, 
     return hipLaunchKernel(fn, dim3(nitems), dim3(NT), params, lds, s);
 }
 
-template <typename R, int EPT>
+template <int KIND, int EPT>
 hipError_t launch_mg(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
                      hipStream_t s) {
     switch (mgroup) {
-        case 1: return launch_ch<R, EPT, 1>(channels, nitems, lds, a, s);
-        case 4: return launch_ch<R, EPT, 4>(channels, nitems, lds, a, s);
-        case 8: return launch_ch<R, EPT, 8>(channels, nitems, lds, a, s);
+        case 1: return launch_ch<KIND, EPT, 1>(channels, nitems, lds, a, s);
+        case 4: return launch_ch<KIND, EPT, 4>(channels, nitems, lds, a, s);
+        case 8: return launch_ch<KIND, EPT, 8>(channels, nitems, lds, a, s);
         default: return hipErrorInvalidValue;
     }
 }
