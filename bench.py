@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--pool", type=int, default=1024, help="distinct measurements resident in HBM")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain elementwise copy of MIB MiB (known traffic) for "
+                         "scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the slice is one GPU's share and no "
@@ -148,10 +152,22 @@ def main():
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
 
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)          # reads nb bytes, writes nb bytes
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = nb
+        del src, dst
+
     # ---- batched mixed precision (the headline) -------------------------------
     total = (args.warmup + args.steps) * B
     pool = max(B, min(args.pool, total))
     pool -= pool % B
+    if args.no_batched:
+        args.steps = 0
+        pool = B
     gu = torch.empty((pool, ng, ng), dtype=torch.complex64, device=dev)
     gd = torch.empty_like(gu)
     fill(gu, g4.G4_IN_C64, 0, pool, 0)
@@ -184,9 +200,9 @@ def main():
     ms = e0.elapsed_time(e1)
     st = g4.g4_stats(h)
     launch_s = st["kernel_ms"] / max(1, st["timed_launches"]) / 1e3
-    value = E * args.steps * B / (ms / 1e3)
+    value = E * args.steps * B / (ms / 1e3) if args.steps else 0.0
     out["value"] = value
-    out["ms_per_step"] = ms / args.steps
+    out["ms_per_step"] = ms / max(1, args.steps)
     out["config"] = {"workload": "4x4 Hubbard cluster G4 slice: Nc=16, Nw=64, Nq=16, Nwex=8, "
                                  "E=%d entries, PH magnetic, batched B=%d, complex64 G, FP32 "
                                  "products, %s accumulator" % (E, B, args.acc),
@@ -194,8 +210,8 @@ def main():
                      "measurements_timed": args.steps * B}
     out["kernel"] = {"name": "update_kernel", "avg_launch_ms": launch_s * 1e3,
                      "launches": st["timed_launches"]}
-    out["roofline"] = roofline(E, ng, B, 8, 16, w.channels, launch_s)
-    if not args.no_check:
+    out["roofline"] = roofline(E, ng, B, 8, 16, w.channels, launch_s) if args.steps else None
+    if not args.no_check and args.steps:
         err, ns = sampled_error(w, h, g4, 1, b_seq, sg[b_seq], 256)
         out["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-6}
     g4.g4_destroy(h)
@@ -234,7 +250,7 @@ def main():
         del pu, pd
         torch.cuda.empty_cache()
         out["plain_fp64"] = plain
-        out["speedup_vs_plain_fp64"] = value / pval
+        out["speedup_vs_plain_fp64"] = value / pval if value else None
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -195,7 +195,18 @@ void build_planes(const Plan &P, int nwex, std::vector<int2> &plane_qm) {
 
 // Work decomposition: plane groups (one q, at most mgroup consecutive m) and
 // tiles (group, k1, k2, c0).
-void build_work(const Plan &P, int nwex, std::vector<int4> &groups, std::vector<int4> &items) {
+//
+// Tile order.  A tile (k1, k2, q) reads the G block (k2, k1) and the G block
+// (k1+q, k2+q); both lie on the block diagonal of momentum difference
+// d = k1 - k2 (and -d).  Tiles are sorted by the difference class {d, -d},
+// then by k1, then by plane group and K2 rows, so that the tiles resident at
+// the same time share G(K2,K1) and a few exchange blocks.  The sorted list is
+// cut into 8 equal contiguous parts, one per XCD, and interleaved so that tile
+// i lands on XCD i mod 8 under round-robin workgroup dispatch: each XCD's L2
+// then serves a narrow band of G blocks.  order 0 keeps the plain
+// (group, k2, k1, rows) order.
+void build_work(const Plan &P, int nwex, int order, std::vector<int4> &groups,
+                std::vector<int4> &items) {
     groups.clear();
     items.clear();
     const Dims &d = P.d;
@@ -208,10 +219,42 @@ void build_work(const Plan &P, int nwex, std::vector<int4> &groups, std::vector<
         groups.push_back(int4{P.qlist[(size_t)iq], m, cnt, (int)(iQ - d.q_begin)});
         iQ += cnt;
     }
-    for (int g = 0; g < (int)groups.size(); ++g)
-        for (int k2 = 0; k2 < d.nc; ++k2)
-            for (int k1 = 0; k1 < d.nc; ++k1)
-                for (int c0 = 0; c0 < d.nw; c0 += P.tile) items.push_back(int4{g, k1, k2, c0});
+    const int ng = (int)groups.size();
+    if (order == 0) {
+        for (int g = 0; g < ng; ++g)
+            for (int k2 = 0; k2 < d.nc; ++k2)
+                for (int k1 = 0; k1 < d.nc; ++k1)
+                    for (int c0 = 0; c0 < d.nw; c0 += P.tile) items.push_back(int4{g, k1, k2, c0});
+        return;
+    }
+    // difference classes: d and -d together
+    auto sub = [&](int a, int b) {   // momentum a - b
+        const int ax = a % d.lx, ay = a / d.lx, bx = b % d.lx, by = b / d.lx;
+        return (ax - bx + d.lx) % d.lx + d.lx * ((ay - by + d.ly) % d.ly);
+    };
+    std::vector<int> cls_done(d.nc, 0);
+    std::vector<int4> sorted;
+    sorted.reserve((size_t)ng * d.nc * d.nc * ((d.nw + P.tile - 1) / P.tile));
+    for (int dd = 0; dd < d.nc; ++dd) {
+        if (cls_done[dd]) continue;
+        const int neg = sub(0, dd);
+        cls_done[dd] = cls_done[neg] = 1;
+        const int members[2] = {dd, neg};
+        for (int mi = 0; mi < (neg == dd ? 1 : 2); ++mi)
+            for (int k1 = 0; k1 < d.nc; ++k1) {
+                const int k2 = sub(k1, members[mi]);
+                for (int g = 0; g < ng; ++g)
+                    for (int c0 = 0; c0 < d.nw; c0 += P.tile) sorted.push_back(int4{g, k1, k2, c0});
+            }
+    }
+    const size_t total = sorted.size(), parts = 8;
+    const size_t per = (total + parts - 1) / parts;
+    items.reserve(total);
+    for (size_t i = 0; i < per; ++i)
+        for (size_t x = 0; x < parts; ++x) {
+            const size_t src = x * per + i;
+            if (src < total) items.push_back(sorted[src]);
+        }
 }
 
 }  // namespace
@@ -229,6 +272,7 @@ struct g4_slice {
     int2 *plane_qm = nullptr;
     int ngroups = 0, nitems = 0;
     size_t items_cap = 0;
+    int order = 1;          // tile order (see build_work); G4_TILE_ORDER overrides
     void *dir = nullptr;
     void *stage = nullptr;
     double *sign_dev = nullptr;
@@ -325,7 +369,7 @@ Tables tables_of(const g4_slice *h) {
 
 int rebuild_work(g4_slice *h) {
     std::vector<int4> groups, items;
-    build_work(h->P, h->cfg.nwex, groups, items);
+    build_work(h->P, h->cfg.nwex, h->order, groups, items);
     if (items.size() > h->items_cap) {
         G4_HIP(h, hipStreamSynchronize(h->stream));
         if (h->items) G4_HIP(h, hipFree(h->items));
@@ -475,6 +519,7 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     h->cfg.q_list = nullptr;
     h->P = P;
     h->device = cfg->device;
+    if (const char *o = std::getenv("G4_TILE_ORDER")) h->order = std::atoi(o) ? 1 : 0;
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) {
         delete h;

@@ -78,19 +78,44 @@ __device__ __forceinline__ V cscale(V a, R s) {
     return r;
 }
 
+// Accumulator access.  Every entry is read and written once per pass, so the
+// accesses are marked non-temporal: the slice streams through without evicting
+// the G blocks that the tiles share from L2 and the MALL.
+template <typename T>
+__device__ __forceinline__ T nt_ld(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void nt_st(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+template <typename V>
+__device__ __forceinline__ V acc_ld(const V *p) {
+    V v;
+    v.x = nt_ld(&p->x);
+    v.y = nt_ld(&p->y);
+    return v;
+}
+template <typename V>
+__device__ __forceinline__ void acc_st(V *p, V v) {
+    nt_st(&p->x, v.x);
+    nt_st(&p->y, v.y);
+}
+
 // Accumulator read-modify-write of one entry.
 template <typename V>
 __device__ __forceinline__ void acc_update(void *base, int kind, int64_t e, V v) {
     if (kind == ACC_C128) {
         double2 *p = static_cast<double2 *>(base) + e;
-        double2 o = *p;
+        double2 o = acc_ld(p);
         o.x += (double)v.x;
         o.y += (double)v.y;
-        *p = o;
+        acc_st(p, o);
     } else if (kind == ACC_C64_KAHAN) {
         // {sum.re, sum.im, comp.re, comp.im}; value = sum - comp
-        float4 *p = static_cast<float4 *>(base) + e;
-        float4 o = *p;
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 *p = reinterpret_cast<f4 *>(static_cast<float4 *>(base) + e);
+        f4 o = nt_ld(p);
         float yr = (float)v.x - o.z;
         float tr = o.x + yr;
         o.z = (tr - o.x) - yr;
@@ -99,13 +124,13 @@ __device__ __forceinline__ void acc_update(void *base, int kind, int64_t e, V v)
         float ti = o.y + yi;
         o.w = (ti - o.y) - yi;
         o.y = ti;
-        *p = o;
+        nt_st(p, o);
     } else {
         float2 *p = static_cast<float2 *>(base) + e;
-        float2 o = *p;
+        float2 o = acc_ld(p);
         o.x += (float)v.x;
         o.y += (float)v.y;
-        *p = o;
+        acc_st(p, o);
     }
 }
 
@@ -138,13 +163,13 @@ struct ChanInfo {
 // Kind: 0 plain FP64 (one measurement, c128 accumulator, prefetched);
 //       1 batched FP64; 2 batched FP32.
 template <int KIND> struct KindInfo;
-template <> struct KindInfo<0> { using R = double; static constexpr bool prefetch = true; };
-template <> struct KindInfo<1> { using R = double; static constexpr bool prefetch = false; };
-template <> struct KindInfo<2> { using R = float; static constexpr bool prefetch = false; };
+template <> struct KindInfo<0> { using R = double; static constexpr bool prefetch = true; static constexpr int nsg = 6; };
+template <> struct KindInfo<1> { using R = double; static constexpr bool prefetch = false; static constexpr int nsg = 8; };
+template <> struct KindInfo<2> { using R = float; static constexpr bool prefetch = false; static constexpr int nsg = 8; };
 
 // Staging slots per thread held in registers across the compute of the
-// previous measurement (G-block elements, both spins; direct-vector elements).
-constexpr int NSG = 8;
+// previous measurement: KindInfo::nsg G-block elements (both spins) and NSV
+// direct-vector elements.  Larger tiles copy the rest directly.
 constexpr int NSV = 4;
 
 template <int KIND, int EPT, int MG, int CH>
@@ -154,6 +179,7 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     using P = SpinPair<V>;
     using CI = ChanInfo<CH>;
     constexpr bool PF = KindInfo<KIND>::prefetch;
+    constexpr int NSG = KindInfo<KIND>::nsg;
     extern __shared__ __align__(16) unsigned char smem_raw[];
 
     const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n, planes = a.d.planes;
@@ -287,24 +313,23 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     const int64_t ebase = ((int64_t)p0 * n + k2 * nw + c0 + r0) * n + k1 * nw + i1;
     const int64_t nn = (int64_t)n * n;
 
+    // register accumulators; in the plain kind they start from the slice values,
+    // loaded here so that the HBM reads overlap the operand staging
     V acc[CI::count][EPT][MG];
     static_for<0, CI::count>([&](auto c) {
         static_for<0, EPT>([&](auto j) {
             static_for<0, MG>([&](auto m) { acc[c][j][m] = V{0, 0}; });
         });
     });
-
-    // plain kind: accumulators in flight while the operands are staged
-    double2 pre[PF ? CI::count : 1][PF ? EPT : 1][PF ? MG : 1];
     if constexpr (PF) {
         if (act) {
             static_for<0, EPT>([&](auto j) {
                 static_for<0, MG>([&](auto m) {
                     if (r0 + j * RP < T2 && m < M) {
                         const int64_t e = ebase + m * nn + (int64_t)j * RP * n;
-                        if (CI::mag) pre[0][j][m] = ld(static_cast<const double2 *>(a.acc[0]) + e);
-                        if (CI::chg) pre[CI::slot_chg][j][m] = ld(static_cast<const double2 *>(a.acc[1]) + e);
-                        if (CI::pp) pre[CI::slot_pp][j][m] = ld(static_cast<const double2 *>(a.acc[2]) + e);
+                        if (CI::mag) acc[0][j][m] = acc_ld(static_cast<const V *>(a.acc[0]) + e);
+                        if (CI::chg) acc[CI::slot_chg][j][m] = acc_ld(static_cast<const V *>(a.acc[1]) + e);
+                        if (CI::pp) acc[CI::slot_pp][j][m] = acc_ld(static_cast<const V *>(a.acc[2]) + e);
                     }
                 });
             });
@@ -320,34 +345,42 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
         if (b + 1 < a.batch) fetch(b + 1);
         if (!act) continue;
         const R s = (R)a.sign[b];
+        // G(K2,K1) times -s_b for the PH exchange (its minus folded in), +s_b for PP
         V xu[EPT], xd[EPT];
         static_for<0, EPT>([&](auto j) {
             const int i2l = min(r0 + j * RP, T2 - 1);
-            xu[j] = cscale(ld(&Xt[i2l * nw + i1].u), s);
-            xd[j] = cscale(ld(&Xt[i2l * nw + i1].d), s);
+            xu[j] = cscale(ld(&Xt[i2l * nw + i1].u), CI::ph ? -s : s);
+            xd[j] = cscale(ld(&Xt[i2l * nw + i1].d), CI::ph ? -s : s);
         });
         auto body = [&](auto j, auto m) __attribute__((always_inline)) {
             const int i2l = r0 + j * RP;
             if (CI::ph) {
                 const P *y = Yt + (i2l + m) * yr + i1 + m;
-                V ex = cmul(xu[j], ld(&y->u));
-                cmac(ex, xd[j], ld(&y->d));
+                const V yu = ld(&y->u), yd = ld(&y->d);
                 if (CI::mag) {
                     cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
-                    acc[0][j][m].x -= ex.x;
-                    acc[0][j][m].y -= ex.y;
+                    cmac(acc[0][j][m], xu[j], yu);
+                    cmac(acc[0][j][m], xd[j], yd);
                 }
                 if (CI::chg) {
                     const int sm = CI::slot_chg * M + m;
                     cmac(acc[CI::slot_chg][j][m], ld(At + sm * nw + i1), ld(Bt + sm * T2 + i2l));
-                    acc[CI::slot_chg][j][m].x -= ex.x;
-                    acc[CI::slot_chg][j][m].y -= ex.y;
+                    cmac(acc[CI::slot_chg][j][m], xu[j], yu);
+                    cmac(acc[CI::slot_chg][j][m], xd[j], yd);
                 }
             }
             if (CI::pp) {
+                // the PP term takes +s_b: undo the PH negation when both are present
                 const P *z = Zt + (m + T2 - 1 - i2l) * zc + m + nw - 1 - i1;
-                cmac(acc[CI::slot_pp][j][m], ld(&z->u), xd[j]);
-                cmac(acc[CI::slot_pp][j][m], ld(&z->d), xu[j]);
+                if (CI::ph) {
+                    V t = cmul(ld(&z->u), xd[j]);
+                    cmac(t, ld(&z->d), xu[j]);
+                    acc[CI::slot_pp][j][m].x -= t.x;
+                    acc[CI::slot_pp][j][m].y -= t.y;
+                } else {
+                    cmac(acc[CI::slot_pp][j][m], ld(&z->u), xd[j]);
+                    cmac(acc[CI::slot_pp][j][m], ld(&z->d), xu[j]);
+                }
             }
         };
         if (full && r0 + (EPT - 1) * RP < T2) {
@@ -366,20 +399,9 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
             if (!(r0 + j * RP < T2 && m < M)) return;
             const int64_t e = ebase + m * nn + (int64_t)j * RP * n;
             if constexpr (PF) {
-                if (CI::mag) {
-                    double2 o = pre[0][j][m];
-                    static_cast<double2 *>(a.acc[0])[e] = double2{o.x + (double)acc[0][j][m].x, o.y + (double)acc[0][j][m].y};
-                }
-                if (CI::chg) {
-                    double2 o = pre[CI::slot_chg][j][m];
-                    const V v = acc[CI::slot_chg][j][m];
-                    static_cast<double2 *>(a.acc[1])[e] = double2{o.x + (double)v.x, o.y + (double)v.y};
-                }
-                if (CI::pp) {
-                    double2 o = pre[CI::slot_pp][j][m];
-                    const V v = acc[CI::slot_pp][j][m];
-                    static_cast<double2 *>(a.acc[2])[e] = double2{o.x + (double)v.x, o.y + (double)v.y};
-                }
+                if (CI::mag) acc_st(static_cast<V *>(a.acc[0]) + e, acc[0][j][m]);
+                if (CI::chg) acc_st(static_cast<V *>(a.acc[1]) + e, acc[CI::slot_chg][j][m]);
+                if (CI::pp) acc_st(static_cast<V *>(a.acc[2]) + e, acc[CI::slot_pp][j][m]);
             } else {
                 if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
                 if (CI::chg) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_chg][j][m]);

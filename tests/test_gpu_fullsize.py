@@ -1,0 +1,154 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark uses, on sampled entries the oracle evaluates one by one
+(regenerating each G element from its Philox counter), plus the long-run
+stability of the float accumulators."""
+import numpy as np
+import pytest
+
+from gpu_common import config_for, g4mod
+from metrics import rel_fro
+from oracle import sampled
+from synth import C1_TINY, C2_PLAIN, C3_BATCHED, C4_RING, C5_SPLIT, signs
+
+pytestmark = pytest.mark.gpu
+
+
+def device_g(w, dtype, b0, count, stream=None):
+    import torch
+    g4 = g4mod()
+    tdt = torch.complex128 if dtype == 0 else torch.complex64
+    out = []
+    for spin in (0, 1):
+        t = torch.empty((count, w.ng, w.ng), dtype=tdt, device="cuda")
+        g4.g4_synth_fill(t, dtype, w.lx, w.ly, w.nw, w.nwex, w.beta, w.t, w.mu, w.h, w.noise,
+                         w.seed, w.wid, b0, count, spin, stream)
+        out.append(t)
+    return out
+
+
+def readback_sample(h, channel, idx):
+    g4 = g4mod()
+    return np.array([g4.g4_readback(h, channel, int(i), 1)[0] for i in idx])
+
+
+def free():
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_plain_slice_full_size():
+    """4x4, Nw 64, Nq 16, Nwex 8: 134M entries, 512 measurements one per pass."""
+    g4 = g4mod()
+    w = C2_PLAIN
+    M = w.measurements
+    gu, gd = device_g(w, 0, 0, M)
+    s = signs(w, 0, M)
+    h = g4.g4_init_slice(config_for(w, mode=0))
+    try:
+        g4.g4_accumulate(h, gu, gd, s)
+        idx = sampled.sample_indices(w, 192, seed=1)
+        got = readback_sample(h, 1, idx)
+        st = g4.g4_stats(h)
+    finally:
+        g4.g4_destroy(h)
+        del gu, gd
+        free()
+    assert st["measurements"] == M and st["launches"] == M
+    want = sampled.entries(w, 1, idx, 0, M)
+    assert rel_fro(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("acc", [0, 1], ids=["acc-c128", "acc-kahan"])
+def test_batched_full_size(acc):
+    """The same slice, 4096 measurements in passes of 16, complex64 G, FP32 products."""
+    g4 = g4mod()
+    w = C3_BATCHED
+    M, B, chunk = w.measurements, w.batch, 512
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=B))
+    try:
+        for b0 in range(0, M, chunk):
+            gu, gd = device_g(w, 1, b0, chunk)
+            g4.g4_accumulate(h, gu, gd, signs(w, b0, chunk))
+            g4.g4_sync(h)
+            del gu, gd
+        idx = sampled.sample_indices(w, 128, seed=2)
+        got = readback_sample(h, 1, idx)
+    finally:
+        g4.g4_destroy(h)
+        free()
+    want = sampled.entries(w, 1, idx, 0, M)
+    assert rel_fro(got, want) <= 1e-6
+
+
+def test_ring_share_slice():
+    """6x6, Nw 128, Nq 36, Nwex 16, rank 3's 1/8 slice (24.5 GB): 8 walkers' buffers
+    of 16 measurements applied in ring order 3, 2, 1, 0, 7, 6, 5, 4."""
+    g4 = g4mod()
+    S, rank = 8, 3
+    per = C4_RING.measurements // S
+    w = C4_RING.with_(q_begin=rank * 72, q_end=(rank + 1) * 72)
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=per))
+    order = [(rank - j) % S for j in range(S)]
+    try:
+        for walker in order:
+            gu, gd = device_g(w, 1, walker * per, per)
+            g4.g4_accumulate(h, gu, gd, signs(w, walker * per, per))
+            g4.g4_sync(h)
+            del gu, gd
+        idx = sampled.sample_indices(w, 96, seed=3)
+        got = readback_sample(h, 1, idx)
+    finally:
+        g4.g4_destroy(h)
+        free()
+    want = np.zeros(len(idx), dtype=np.complex128)
+    for walker in order:
+        want += sampled.entries(w, 1, idx, walker * per, per)
+    assert rel_fro(got, want) <= 1e-6
+
+
+def test_three_channel_quarter_slice():
+    """8x8, Nw 64, Nq 64, Nwex 4, a 1/4 slice, PH magnetic + PH charge + PP in one pass."""
+    g4 = g4mod()
+    w = C5_SPLIT.with_(q_begin=64, q_end=128, measurements=64)
+    M, B = w.measurements, w.batch
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=1, batch=B))
+    try:
+        gu, gd = device_g(w, 1, 0, M)
+        g4.g4_accumulate(h, gu, gd, signs(w, 0, M))
+        g4.g4_sync(h)
+        del gu, gd
+        idx = sampled.sample_indices(w, 64, seed=4)
+        got = {ch: readback_sample(h, ch, idx) for ch in (1, 2, 4)}
+    finally:
+        g4.g4_destroy(h)
+        free()
+    for ch in (1, 2, 4):
+        assert rel_fro(got[ch], sampled.entries(w, ch, idx, 0, M)) <= 1e-6, ch
+
+
+def test_long_run_stability():
+    """30,000 measurements at the tiny shapes, one per pass: the compensated float
+    accumulator stays at the FP32 product error while the plain float one drifts."""
+    g4 = g4mod()
+    w = C1_TINY
+    M = 30000
+    gu, gd = device_g(w, 1, 0, M)
+    s = signs(w, 0, M)
+    idx = sampled.sample_indices(w, 48, seed=5)
+    got = {}
+    try:
+        for acc in (0, 1, 2):
+            h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=1))
+            try:
+                g4.g4_accumulate(h, gu, gd, s)
+                got[acc] = readback_sample(h, 1, idx)
+            finally:
+                g4.g4_destroy(h)
+    finally:
+        del gu, gd
+        free()
+    want = sampled.entries(w, 1, idx, 0, M, sign=s)
+    e = {acc: rel_fro(v, want) for acc, v in got.items()}
+    assert e[0] <= 1e-6 and e[1] <= 1e-6, e
+    assert e[2] > 3 * e[1], e

@@ -1,0 +1,70 @@
+"""The in-process ring delivery: order (CPU) and double-buffered streaming on the
+GPU, which must give exactly the sequential result and be invariant, to
+rounding, under the rank (rotation of the order)."""
+import numpy as np
+import pytest
+
+from gpu_common import config_for, g4mod
+from metrics import rel_fro
+from paper_2105_00027_amd.ring import ring_order
+from synth import Workload, signs
+
+
+def test_ring_order_properties():
+    S = 8
+    for r in range(S):
+        order = ring_order(r, S)
+        assert order[0] == r and sorted(order) == list(range(S))
+        assert order[1] == (r - 1) % S            # first buffer comes from the left
+    # after S-1 steps each walker's buffer sits at the left neighbour of its birth rank
+    for w in range(S):
+        last = [r for r in range(S) if ring_order(r, S)[S - 1] == w]
+        assert last == [(w - 1) % S]
+    with pytest.raises(ValueError):
+        ring_order(8, 8)
+
+
+W = Workload("ring", lx=3, ly=2, nw=24, nwex=5, nq=6, q_begin=5, q_end=23, beta=7.0, seed=31,
+             wid=31, channels=7)
+
+
+@pytest.mark.gpu
+def test_streamed_ring_matches_sequential_and_rotation():
+    import torch
+    from paper_2105_00027_amd import ring
+    g4 = g4mod()
+    S, per = 4, 3
+    main = torch.cuda.Stream()
+    copy = torch.cuda.Stream()
+    sg = {wk: signs(W, wk * per, per) for wk in range(S)}
+
+    def deliver(walker, bu, bd, stream):
+        for spin, buf in ((0, bu), (1, bd)):
+            g4.g4_synth_fill(buf, 0, W.lx, W.ly, W.nw, W.nwex, W.beta, W.t, W.mu, W.h, W.noise,
+                             W.seed, W.wid, walker * per, per, spin, stream.cuda_stream)
+
+    def run(rank, streamed):
+        cfg = config_for(W, mode=1, prod=0, g_in=0, acc=0, batch=per, stream=main.cuda_stream)
+        h = g4.g4_init_slice(cfg)
+        bufs = [tuple(torch.empty((per, W.ng, W.ng), dtype=torch.complex128, device="cuda")
+                      for _ in range(2)) for _ in range(2)]
+        try:
+            if streamed:
+                ring.stream_ring(h, deliver, sg, rank, S, bufs, main, copy)
+            else:
+                for wk in ring.ring_order(rank, S):
+                    with torch.cuda.stream(main):
+                        deliver(wk, bufs[0][0], bufs[0][1], main)
+                        g4.g4_accumulate(h, bufs[0][0], bufs[0][1], sg[wk])
+            g4.g4_sync(h)
+            return {ch: g4.g4_readback(h, ch) for ch in (1, 2, 4)}
+        finally:
+            torch.cuda.synchronize()
+            g4.g4_destroy(h)
+
+    seq = run(2, False)
+    strm = run(2, True)
+    rot = run(0, True)
+    for ch in (1, 2, 4):
+        assert np.array_equal(seq[ch], strm[ch])
+        assert rel_fro(rot[ch], seq[ch]) <= 1e-15
