@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--acc", default="c128", choices=["c128", "kahan"])
     ap.add_argument("--plain-measurements", type=int, default=64)
+    ap.add_argument("--plain-tile", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -226,7 +227,7 @@ def main():
         fill(pu, g4.G4_IN_C128, 0, M, 0)
         fill(pd, g4.G4_IN_C128, 0, M, 1)
         ps = signs(w, 0, M)
-        hp = g4.g4_init_slice(cfg(mode=g4.G4_MODE_PLAIN))
+        hp = g4.g4_init_slice(cfg(mode=g4.G4_MODE_PLAIN, tile=args.plain_tile))
         g4.g4_accumulate(hp, pu[:2], pd[:2], ps[:2])      # warm-up
         g4.g4_sync(hp)
         g4.g4_reset(hp)

@@ -122,7 +122,8 @@ typedef struct g4_config {
     int32_t mode;             /* G4_MODE_* */
     int32_t max_batch;        /* batched: measurements per pass, 1..256 (plain: ignored) */
     int32_t device;           /* HIP device ordinal */
-    void *stream;             /* hipStream_t to enqueue on, or NULL for a library-owned stream */
+    void *stream;             /* hipStream_t to enqueue on, or NULL for a library-owned blocking
+                                 stream (ordered with work on the null stream) */
     uint32_t flags;           /* G4_F_* */
     int32_t tile;             /* rows of K2 frequencies per work tile; 0 = default */
     double beta;              /* inverse temperature; metadata only */

@@ -198,13 +198,15 @@ void build_planes(const Plan &P, int nwex, std::vector<int2> &plane_qm) {
 //
 // Tile order.  A tile (k1, k2, q) reads the G block (k2, k1) and the G block
 // (k1+q, k2+q); both lie on the block diagonal of momentum difference
-// d = k1 - k2 (and -d).  Tiles are sorted by the difference class {d, -d},
-// then by k1, then by plane group and K2 rows, so that the tiles resident at
-// the same time share G(K2,K1) and a few exchange blocks.  The sorted list is
-// cut into 8 equal contiguous parts, one per XCD, and interleaved so that tile
-// i lands on XCD i mod 8 under round-robin workgroup dispatch: each XCD's L2
-// then serves a narrow band of G blocks.  order 0 keeps the plain
-// (group, k2, k1, rows) order.
+// d = k1 - k2 (and -d).  Tiles are sorted by the difference class {d, -d};
+// inside a class (order 2, the default) by windows of up to 4 momenta k1 that
+// are neighbours along a lattice row x 4 consecutive plane groups x half the
+// K2 tiles: k1 + q then stays on one lattice row, so the ~64 tiles an XCD
+// holds at once share about 4 G(K2,K1) blocks and 4 exchange blocks (order 1:
+// one k1 at a time).  The sorted list is cut into 8 equal contiguous parts,
+// one per XCD, and interleaved so that tile i lands on XCD i mod 8 under
+// round-robin workgroup dispatch: each XCD's L2 serves a narrow band of G
+// blocks.  order 0 keeps the plain (group, k2, k1, rows) order.
 void build_work(const Plan &P, int nwex, int order, std::vector<int4> &groups,
                 std::vector<int4> &items) {
     groups.clear();
@@ -232,20 +234,31 @@ void build_work(const Plan &P, int nwex, int order, std::vector<int4> &groups,
         const int ax = a % d.lx, ay = a / d.lx, bx = b % d.lx, by = b / d.lx;
         return (ax - bx + d.lx) % d.lx + d.lx * ((ay - by + d.ly) % d.ly);
     };
+    const int ntile = (d.nw + P.tile - 1) / P.tile;
+    // order 2: inside a class, windows of bk momenta k1 (neighbours along a
+    // lattice row) x bg consecutive plane groups x half the K2 tiles, so that
+    // the tiles resident together read few G(K2,K1) and exchange blocks
+    const int bk = order == 2 ? std::min(d.lx, 4) : 1;
+    const int bg = order == 2 ? std::min(ng, 4) : ng;
+    const int bc = order == 2 ? std::max(1, (ntile + 1) / 2) : ntile;
     std::vector<int> cls_done(d.nc, 0);
     std::vector<int4> sorted;
-    sorted.reserve((size_t)ng * d.nc * d.nc * ((d.nw + P.tile - 1) / P.tile));
+    sorted.reserve((size_t)ng * d.nc * d.nc * ntile);
     for (int dd = 0; dd < d.nc; ++dd) {
         if (cls_done[dd]) continue;
         const int neg = sub(0, dd);
         cls_done[dd] = cls_done[neg] = 1;
         const int members[2] = {dd, neg};
         for (int mi = 0; mi < (neg == dd ? 1 : 2); ++mi)
-            for (int k1 = 0; k1 < d.nc; ++k1) {
-                const int k2 = sub(k1, members[mi]);
-                for (int g = 0; g < ng; ++g)
-                    for (int c0 = 0; c0 < d.nw; c0 += P.tile) sorted.push_back(int4{g, k1, k2, c0});
-            }
+            for (int kb = 0; kb < d.nc; kb += bk)
+                for (int gb = 0; gb < ng; gb += bg)
+                    for (int cb = 0; cb < ntile; cb += bc)
+                        for (int k1 = kb; k1 < std::min(d.nc, kb + bk); ++k1) {
+                            const int k2 = sub(k1, members[mi]);
+                            for (int g = gb; g < std::min(ng, gb + bg); ++g)
+                                for (int c = cb; c < std::min(ntile, cb + bc); ++c)
+                                    sorted.push_back(int4{g, k1, k2, c * P.tile});
+                        }
     }
     const size_t total = sorted.size(), parts = 8;
     const size_t per = (total + parts - 1) / parts;
@@ -272,7 +285,7 @@ struct g4_slice {
     int2 *plane_qm = nullptr;
     int ngroups = 0, nitems = 0;
     size_t items_cap = 0;
-    int order = 1;          // tile order (see build_work); G4_TILE_ORDER overrides
+    int order = 2;          // tile order (see build_work); G4_TILE_ORDER overrides
     void *dir = nullptr;
     void *stage = nullptr;
     double *sign_dev = nullptr;
@@ -519,7 +532,7 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     h->cfg.q_list = nullptr;
     h->P = P;
     h->device = cfg->device;
-    if (const char *o = std::getenv("G4_TILE_ORDER")) h->order = std::atoi(o) ? 1 : 0;
+    if (const char *o = std::getenv("G4_TILE_ORDER")) h->order = std::min(2, std::max(0, std::atoi(o)));
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) {
         delete h;
@@ -549,7 +562,8 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     if (cfg->stream) {
         h->stream = static_cast<hipStream_t>(cfg->stream);
     } else {
-        G4_INIT(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        // blocking: ordered with work the caller puts on the null stream
+        G4_INIT(hipStreamCreateWithFlags(&h->stream, hipStreamDefault));
         h->own_stream = true;
     }
     const uint64_t ab = P.acc_bytes;

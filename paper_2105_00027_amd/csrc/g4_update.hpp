@@ -33,10 +33,6 @@ template <typename R> struct Cx;
 template <> struct Cx<double> { using V = double2; };
 template <> struct Cx<float> { using V = float2; };
 
-template <typename V>
-struct SpinPair {
-    V u, d;
-};
 
 template <typename V>
 __device__ __forceinline__ V cmul(V a, V b) {
@@ -176,7 +172,6 @@ template <int KIND, int EPT, int MG, int CH>
 __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     using R = typename KindInfo<KIND>::R;
     using V = typename Cx<R>::V;
-    using P = SpinPair<V>;
     using CI = ChanInfo<CH>;
     constexpr bool PF = KindInfo<KIND>::prefetch;
     constexpr int NSG = KindInfo<KIND>::nsg;
@@ -205,11 +200,16 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     const int nA = CI::nph * M * nw;               // a(Q, K1) per PH channel
     const int nB = CI::nph * M * T2;               // b(Q, K2) per PH channel
     const int nV = nA + nB;
-    P *Yt = reinterpret_cast<P *>(smem_raw);
-    P *Zt = Yt + nY;
-    P *Xt = Zt + nZ;
-    V *At = reinterpret_cast<V *>(Xt + nX);
+    // Spin pairs of the staged G blocks: element i of [Y | Z | X].  FP32 pairs
+    // (16 bytes) sit side by side and are read with one 16-byte access; FP64
+    // values are kept in two planes so that consecutive lanes stay 16 bytes
+    // apart (no bank conflicts).
+    constexpr bool SOA = sizeof(V) == 16;
+    V *Gp = reinterpret_cast<V *>(smem_raw);
+    V *At = Gp + 2 * nG;
     V *Bt = At + nA;
+    auto pu = [&](int i) __attribute__((always_inline)) { return SOA ? i : 2 * i; };
+    auto pd = [&](int i) __attribute__((always_inline)) { return SOA ? nG + i : 2 * i + 1; };
 
     const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
     const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
@@ -283,8 +283,8 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     auto store = [&](int b) __attribute__((always_inline)) {
         static_for<0, NSG>([&](auto k) {
             if (sg_loff[k] >= 0) {
-                st(&Yt[sg_loff[k]].u, rgu[k]);
-                st(&Yt[sg_loff[k]].d, rgd[k]);
+                st(Gp + pu(sg_loff[k]), rgu[k]);
+                st(Gp + pd(sg_loff[k]), rgd[k]);
             }
         });
         if (CI::ph)
@@ -297,8 +297,8 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
         for (int e = tid + NSG * NT; e < nG; e += NT) {
             int go, lo;
             g_slot(e, go, lo);
-            st(&Yt[lo].u, ld(gu + go));
-            st(&Yt[lo].d, ld(gd + go));
+            st(Gp + pu(lo), ld(gu + go));
+            st(Gp + pd(lo), ld(gd + go));
         }
         if (CI::ph)
             for (int e = tid + NSV * NT; e < nV; e += NT) {
@@ -349,14 +349,15 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
         V xu[EPT], xd[EPT];
         static_for<0, EPT>([&](auto j) {
             const int i2l = min(r0 + j * RP, T2 - 1);
-            xu[j] = cscale(ld(&Xt[i2l * nw + i1].u), CI::ph ? -s : s);
-            xd[j] = cscale(ld(&Xt[i2l * nw + i1].d), CI::ph ? -s : s);
+            const int ix = nY + nZ + i2l * nw + i1;
+            xu[j] = cscale(ld(Gp + pu(ix)), CI::ph ? -s : s);
+            xd[j] = cscale(ld(Gp + pd(ix)), CI::ph ? -s : s);
         });
         auto body = [&](auto j, auto m) __attribute__((always_inline)) {
             const int i2l = r0 + j * RP;
             if (CI::ph) {
-                const P *y = Yt + (i2l + m) * yr + i1 + m;
-                const V yu = ld(&y->u), yd = ld(&y->d);
+                const int iy = (i2l + m) * yr + i1 + m;
+                const V yu = ld(Gp + pu(iy)), yd = ld(Gp + pd(iy));
                 if (CI::mag) {
                     cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
                     cmac(acc[0][j][m], xu[j], yu);
@@ -371,15 +372,16 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
             }
             if (CI::pp) {
                 // the PP term takes +s_b: undo the PH negation when both are present
-                const P *z = Zt + (m + T2 - 1 - i2l) * zc + m + nw - 1 - i1;
+                const int iz = nY + (m + T2 - 1 - i2l) * zc + m + nw - 1 - i1;
+                const V zu = ld(Gp + pu(iz)), zd = ld(Gp + pd(iz));
                 if (CI::ph) {
-                    V t = cmul(ld(&z->u), xd[j]);
-                    cmac(t, ld(&z->d), xu[j]);
+                    V t = cmul(zu, xd[j]);
+                    cmac(t, zd, xu[j]);
                     acc[CI::slot_pp][j][m].x -= t.x;
                     acc[CI::slot_pp][j][m].y -= t.y;
                 } else {
-                    cmac(acc[CI::slot_pp][j][m], ld(&z->u), xd[j]);
-                    cmac(acc[CI::slot_pp][j][m], ld(&z->d), xu[j]);
+                    cmac(acc[CI::slot_pp][j][m], zu, xd[j]);
+                    cmac(acc[CI::slot_pp][j][m], zd, xu[j]);
                 }
             }
         };
