@@ -162,7 +162,7 @@ int validate(const g4_config *c, Plan *p) {
         return fail(G4_E_UNSUPPORTED, "direct-term vectors above 2^31 elements; lower max_batch");
     P.stage_bytes = (P.prec == 1 && c->g_in == G4_IN_C128) ? 2ull * P.batch * ng * ng * 8 : 0;
     P.sign_bytes = (uint64_t)kSignSlots * kMaxBatch * sizeof(double);
-    P.scratch_bytes = (c->acc == G4_ACC_C128 ? 0 : std::min<uint64_t>(P.entries, kScratchEntries) * 16);
+    P.scratch_bytes = std::min<uint64_t>(P.entries, kScratchEntries) * 16;
     const uint64_t nitems_max = (uint64_t)d.planes * nc * nc * ((c->nw + P.tile - 1) / P.tile);
     P.table_bytes = 2ull * nc * nc * 4 + (uint64_t)d.planes * 16 + nitems_max * 16 + (uint64_t)d.planes * 8;
     P.total_bytes = P.acc_bytes * popcount3(c->channels) + P.dir_bytes + P.stage_bytes + P.sign_bytes +
@@ -641,16 +641,10 @@ int g4_readback(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, d
     if (count && !out) return fail(G4_E_ARG, "out is NULL");
     G4_HIP(h, hipSetDevice(h->device));
     G4_HIP(h, hipStreamSynchronize(h->stream));
-    if (h->cfg.acc == G4_ACC_C128) {
-        G4_HIP(h, hipMemcpyAsync(out, static_cast<double2 *>(h->acc[c]) + first, count * 16,
-                                 hipMemcpyDeviceToHost, h->stream));
-        G4_HIP(h, hipStreamSynchronize(h->stream));
-        return fold_timings(h);
-    }
     const uint64_t chunk = h->P.scratch_bytes / 16;
     for (uint64_t off = 0; off < count; off += chunk) {
         const uint64_t cnt = std::min(chunk, count - off);
-        G4_HIP(h, launch_acc_to_c128(h->cfg.acc, h->acc[c], first + off, cnt, h->scratch, h->stream));
+        G4_HIP(h, launch_acc_to_c128(h->cfg.acc, h->acc[c], first + off, cnt, h->scratch, h->P.d.nc, h->P.d.nw, h->stream));
         G4_HIP(h, hipMemcpyAsync(out + 2 * off, h->scratch, cnt * 16, hipMemcpyDeviceToHost, h->stream));
         G4_HIP(h, hipStreamSynchronize(h->stream));
     }
@@ -666,17 +660,11 @@ int g4_load(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, const
     if (count && !in) return fail(G4_E_ARG, "in is NULL");
     G4_HIP(h, hipSetDevice(h->device));
     G4_HIP(h, hipStreamSynchronize(h->stream));
-    if (h->cfg.acc == G4_ACC_C128) {
-        G4_HIP(h, hipMemcpyAsync(static_cast<double2 *>(h->acc[c]) + first, in, count * 16,
-                                 hipMemcpyHostToDevice, h->stream));
-        G4_HIP(h, hipStreamSynchronize(h->stream));
-        return G4_OK;
-    }
     const uint64_t chunk = h->P.scratch_bytes / 16;
     for (uint64_t off = 0; off < count; off += chunk) {
         const uint64_t cnt = std::min(chunk, count - off);
         G4_HIP(h, hipMemcpyAsync(h->scratch, in + 2 * off, cnt * 16, hipMemcpyHostToDevice, h->stream));
-        G4_HIP(h, launch_c128_to_acc(h->cfg.acc, h->scratch, h->acc[c], first + off, cnt, h->stream));
+        G4_HIP(h, launch_c128_to_acc(h->cfg.acc, h->scratch, h->acc[c], first + off, cnt, h->P.d.nc, h->P.d.nw, h->stream));
         G4_HIP(h, hipStreamSynchronize(h->stream));
     }
     return G4_OK;

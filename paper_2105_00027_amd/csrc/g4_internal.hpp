@@ -75,10 +75,12 @@ hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems
                          const UpdateArgs &a, hipStream_t s);
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d);
 hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s);
+// Readback / load between the documented [plane][K2][K1] order (c128, dst/src)
+// and the tile-contiguous device layout of the accumulators.
 hipError_t launch_acc_to_c128(int acc_kind, const void *acc, uint64_t first, uint64_t count,
-                              double *dst, hipStream_t s);
+                              double *dst, int nc, int nw, hipStream_t s);
 hipError_t launch_c128_to_acc(int acc_kind, const double *src, void *acc, uint64_t first,
-                              uint64_t count, hipStream_t s);
+                              uint64_t count, int nc, int nw, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // Synthetic-input generator (g4_synth.hip).

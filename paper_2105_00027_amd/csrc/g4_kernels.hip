@@ -64,32 +64,49 @@ __global__ void convert_kernel(const double2 *src, float2 *dst, int64_t count) {
     }
 }
 
+// Entry j of the documented [plane][K2][K1] order -> its place in the
+// tile-contiguous device layout [plane][k2][k1][i2][i1].
+__device__ __forceinline__ uint64_t phys_index(uint64_t j, uint64_t nc, uint64_t nw) {
+    const uint64_t n = nc * nw;
+    const uint64_t K1 = j % n, t = j / n;
+    const uint64_t K2 = t % n, p = t / n;
+    return ((p * nc + K2 / nw) * nc + K1 / nw) * nw * nw + (K2 % nw) * nw + (K1 % nw);
+}
+
 __global__ void acc_to_c128_kernel(int kind, const void *acc, uint64_t first, uint64_t count,
-                                   double2 *dst) {
+                                   double2 *dst, int nc, int nw) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        if (kind == ACC_C64_KAHAN) {
-            const float4 v = static_cast<const float4 *>(acc)[first + i];
+        const uint64_t e = phys_index(first + i, nc, nw);
+        if (kind == ACC_C128) {
+            dst[i] = static_cast<const double2 *>(acc)[e];
+        } else if (kind == ACC_C64_KAHAN) {
+            const float4 v = static_cast<const float4 *>(acc)[e];
             // value = sum - comp (comp is the negated remainder)
             dst[i] = double2{(double)v.x - (double)v.z, (double)v.y - (double)v.w};
         } else {
-            const float2 v = static_cast<const float2 *>(acc)[first + i];
+            const float2 v = static_cast<const float2 *>(acc)[e];
             dst[i] = double2{(double)v.x, (double)v.y};
         }
     }
 }
 
 __global__ void c128_to_acc_kernel(int kind, const double2 *src, void *acc, uint64_t first,
-                                   uint64_t count) {
+                                   uint64_t count, int nc, int nw) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = phys_index(first + i, nc, nw);
         const double2 v = src[i];
+        if (kind == ACC_C128) {
+            static_cast<double2 *>(acc)[e] = v;
+            continue;
+        }
         const float hr = (float)v.x, hi = (float)v.y;
         if (kind == ACC_C64_KAHAN) {
             const float cr = (float)((double)hr - v.x), ci = (float)((double)hi - v.y);
-            static_cast<float4 *>(acc)[first + i] = float4{hr, hi, cr, ci};
+            static_cast<float4 *>(acc)[e] = float4{hr, hi, cr, ci};
         } else {
-            static_cast<float2 *>(acc)[first + i] = float2{hr, hi};
+            static_cast<float2 *>(acc)[e] = float2{hr, hi};
         }
     }
 }
@@ -165,18 +182,18 @@ hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count,
 }
 
 hipError_t launch_acc_to_c128(int acc_kind, const void *acc, uint64_t first, uint64_t count,
-                              double *dst, hipStream_t s) {
+                              double *dst, int nc, int nw, hipStream_t s) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(acc_to_c128_kernel, dim3(grid_for((int64_t)count, 256)), dim3(256), 0, s,
-                       acc_kind, acc, first, count, reinterpret_cast<double2 *>(dst));
+                       acc_kind, acc, first, count, reinterpret_cast<double2 *>(dst), nc, nw);
     return hipGetLastError();
 }
 
 hipError_t launch_c128_to_acc(int acc_kind, const double *src, void *acc, uint64_t first,
-                              uint64_t count, hipStream_t s) {
+                              uint64_t count, int nc, int nw, hipStream_t s) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(c128_to_acc_kernel, dim3(grid_for((int64_t)count, 256)), dim3(256), 0, s,
-                       acc_kind, reinterpret_cast<const double2 *>(src), acc, first, count);
+                       acc_kind, reinterpret_cast<const double2 *>(src), acc, first, count, nc, nw);
     return hipGetLastError();
 }
 

@@ -309,8 +309,12 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
             }
     };
 
-    // entry index of (plane p0, row c0 + r0, column i1); + m*n*n + j*RP*n
-    const int64_t ebase = ((int64_t)p0 * n + k2 * nw + c0 + r0) * n + k1 * nw + i1;
+    // Accumulator layout in device memory, tile-contiguous:
+    //   [plane][k2][k1][i2][i1]  (K2 = k2*nw + i2, K1 = k1*nw + i1),
+    // so one plane of a tile is a single run of T2*nw entries.  Readback and
+    // load translate to the documented [plane][K2][K1] order.
+    // Physical index of (plane p0, row c0 + r0, column i1); + m*n*n + j*RP*nw.
+    const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * nw * nw + (int64_t)(c0 + r0) * nw + i1;
     const int64_t nn = (int64_t)n * n;
 
     // register accumulators; in the plain kind they start from the slice values,
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
             static_for<0, EPT>([&](auto j) {
                 static_for<0, MG>([&](auto m) {
                     if (r0 + j * RP < T2 && m < M) {
-                        const int64_t e = ebase + m * nn + (int64_t)j * RP * n;
+                        const int64_t e = ebase + m * nn + (int64_t)j * RP * nw;
                         if (CI::mag) acc[0][j][m] = acc_ld(static_cast<const V *>(a.acc[0]) + e);
                         if (CI::chg) acc[CI::slot_chg][j][m] = acc_ld(static_cast<const V *>(a.acc[1]) + e);
                         if (CI::pp) acc[CI::slot_pp][j][m] = acc_ld(static_cast<const V *>(a.acc[2]) + e);
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     static_for<0, EPT>([&](auto j) {
         static_for<0, MG>([&](auto m) {
             if (!(r0 + j * RP < T2 && m < M)) return;
-            const int64_t e = ebase + m * nn + (int64_t)j * RP * n;
+            const int64_t e = ebase + m * nn + (int64_t)j * RP * nw;
             if constexpr (PF) {
                 if (CI::mag) acc_st(static_cast<V *>(a.acc[0]) + e, acc[0][j][m]);
                 if (CI::chg) acc_st(static_cast<V *>(a.acc[1]) + e, acc[CI::slot_chg][j][m]);
