@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--acc", default="c128", choices=["c128", "kahan"])
+    ap.add_argument("--mfma", action="store_true", help="direct term on the matrix cores")
     ap.add_argument("--plain-measurements", type=int, default=64)
     ap.add_argument("--plain-tile", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
@@ -144,10 +145,10 @@ def main():
         g4.g4_synth_fill(buf, dtype, w.lx, w.ly, w.nw, w.nwex, w.beta, w.t, w.mu, w.h, w.noise,
                          w.seed, w.wid, b0, count, spin, sptr)
 
-    def cfg(**kw):
+    def cfg(flags=0, **kw):
         return g4.Config(lx=w.lx, ly=w.ly, nw=w.nw, nwex=w.nwex, nq=w.nq, q_begin=w.q0, q_end=w.q1,
                          channels=w.channels, beta=w.beta, stream=sptr,
-                         flags=g4.G4_F_KERNEL_TIMING, **kw)
+                         flags=g4.G4_F_KERNEL_TIMING | flags, **kw)
 
     out = {"metric": METRIC, "unit": "entry-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
@@ -176,7 +177,8 @@ def main():
     sg = signs(w, 0, pool)
     acc = g4.G4_ACC_C128 if args.acc == "c128" else g4.G4_ACC_C64_KAHAN
     h = g4.g4_init_slice(cfg(mode=g4.G4_MODE_BATCHED, prod=g4.G4_PROD_F32, g_in=g4.G4_IN_C64,
-                             acc=acc, max_batch=B, tile=args.tile))
+                             acc=acc, max_batch=B, tile=args.tile,
+                             flags=g4.G4_F_MFMA if args.mfma else 0))
     nblk = pool // B
 
     def step(i):
@@ -208,9 +210,10 @@ def main():
                                  "E=%d entries, PH magnetic, batched B=%d, complex64 G, FP32 "
                                  "products, %s accumulator" % (E, B, args.acc),
                      "entries": E, "batch": B, "tile": st["tile"], "accumulator": args.acc,
+                     "direct_term": "mfma" if st["variant"] == 1 else "valu",
                      "measurements_timed": args.steps * B}
-    out["kernel"] = {"name": "update_kernel", "avg_launch_ms": launch_s * 1e3,
-                     "launches": st["timed_launches"]}
+    out["kernel"] = {"name": "update_mfma_kernel" if st["variant"] == 1 else "update_kernel",
+                     "avg_launch_ms": launch_s * 1e3, "launches": st["timed_launches"]}
     out["roofline"] = roofline(E, ng, B, 8, 16, w.channels, launch_s) if args.steps else None
     if not args.no_check and args.steps:
         err, ns = sampled_error(w, h, g4, 1, b_seq, sg[b_seq], 256)

@@ -103,7 +103,7 @@ enum {
     G4_F_CHECK_FINITE = 1u,   /* g4_accumulate rejects signs that are not finite */
     G4_F_KERNEL_TIMING = 2u,  /* time every slice-update kernel with HIP events (see g4_stats) */
     G4_F_GRAPH = 4u,          /* replay each batched step as a captured HIP graph */
-    G4_F_MFMA = 8u            /* batched FP32: direct term on MFMA (otherwise VALU) */
+    G4_F_MFMA = 8u            /* batched FP32: direct term on MFMA (nw = 64 or 128; 16-row tiles) */
 };
 
 typedef struct g4_config {
@@ -194,9 +194,10 @@ int g4_reset(g4_slice *h);
 /* Current statistics (synchronous: waits for the stream first). */
 int g4_stats(g4_slice *h, g4_stats_t *st);
 
-/* Override the work tile (K2 rows) and, in batched mode, the pass size and
- * kernel variant (0 VALU, 1 MFMA direct).  0 keeps the current value.
- * G4_E_UNSUPPORTED if the combination cannot run for this slice. */
+/* Override the work tile (K2 rows), the pass size (batched mode, at most the
+ * allocated max_batch) and the kernel variant: 1 = MFMA direct term, 2 =
+ * VALU kernel.  0 keeps the current value.  G4_E_UNSUPPORTED if the
+ * combination cannot run for this slice.  Waits for the handle's stream. */
 int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant);
 
 /* Release everything owned by h (waits for its stream).  NULL is a no-op. */

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libg4.so")
 # (source, object name, extra defines); the update kernel is instantiated once
 # per (kind, K2 rows per thread) pair
 SOURCES = [("g4_abi.cpp", "g4_abi", []), ("g4_kernels.hip", "g4_kernels", []),
-           ("g4_synth.hip", "g4_synth", [])] + [
+           ("g4_synth.hip", "g4_synth", []), ("g4_update_mfma.hip", "g4_update_mfma", [])] + [
     ("g4_update_inst.hip", "g4_update_k%d_e%d" % (k, e), ["-DG4_KIND=%d" % k, "-DG4_EPT=%d" % e])
     for k in (0, 1, 2) for e in (1, 2, 4, 8)]
 ARCH = os.environ.get("G4_OFFLOAD_ARCH", "gfx950")

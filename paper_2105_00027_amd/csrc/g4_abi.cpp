@@ -44,6 +44,7 @@ struct Plan {
     Dims d;
     int prec;          // 0 FP64 products, 1 FP32
     int kind;          // update kernel: 0 plain FP64, 1 batched FP64, 2 batched FP32
+    int variant;       // 0 VALU direct term, 1 MFMA direct term
     int batch;         // measurements per pass
     int mgroup;        // transfer planes per work tile (compile-time bound)
     int tile;          // K2 rows per work tile
@@ -140,7 +141,20 @@ int validate(const g4_config *c, Plan *p) {
     P.mgroup = choose_mgroup(c->nwex);
     const int nch = popcount3(c->channels);
     const int rp = 256 / c->nw;
-    if (c->tile) {
+    P.variant = (c->flags & G4_F_MFMA) ? 1 : 0;
+    if (P.variant == 1) {
+        // MFMA kernel: 16-row tiles, 64-column slabs per wave, register budget
+        if (P.kind != 2) return fail(G4_E_UNSUPPORTED, "MFMA direct term needs batched FP32 products");
+        if (c->nw % 64 || c->nw > 128) return fail(G4_E_UNSUPPORTED, "MFMA direct term needs nw = 64 or 128");
+        if (nch * (c->nw / 64) * P.mgroup > 16)
+            return fail(G4_E_UNSUPPORTED, "MFMA direct term: %d channels x %d slabs x %d planes exceed the register budget",
+                        nch, c->nw / 64, P.mgroup);
+        if (c->tile && c->tile != 16) return fail(G4_E_UNSUPPORTED, "MFMA direct term uses 16-row tiles");
+    }
+    if (P.variant == 1) {
+        P.ept = 0;
+        P.tile = 16;
+    } else if (c->tile) {
         if (c->tile % rp || c->tile > c->nw) return fail(G4_E_UNSUPPORTED, "tile=%d: must be a multiple of %d and <= nw", c->tile, rp);
         const int e = c->tile / rp;
         if (e != 1 && e != 2 && e != 4 && e != 8) return fail(G4_E_UNSUPPORTED, "tile=%d: tile/%d must be 1, 2, 4 or 8", c->tile, rp);
@@ -148,8 +162,8 @@ int validate(const g4_config *c, Plan *p) {
     } else {
         P.ept = choose_ept(P.prec, nch, P.mgroup, c->nw);
     }
-    P.tile = P.ept * rp;
-    if (update_lds_bytes(P.kind, (int)c->channels, P.tile, P.mgroup, d) > 160 * 1024)
+    if (P.variant == 0) P.tile = P.ept * rp;
+    if (update_lds_bytes(P.kind, (int)c->channels, P.tile, P.mgroup, d, P.variant) > 160 * 1024)
         return fail(G4_E_UNSUPPORTED, "LDS tile above 160 KiB");
     P.slots = c->channels & 3u;
     P.nslots = popcount3(P.slots);
@@ -471,7 +485,7 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
         if (rc) return rc;
         G4_HIP(h, hipEventRecord(e0, h->stream));
     }
-    G4_HIP(h, launch_update(P.kind, (int)h->cfg.channels, P.ept, P.mgroup, h->nitems, ua, h->stream));
+    G4_HIP(h, launch_update(P.kind, (int)h->cfg.channels, P.ept, P.mgroup, h->nitems, P.variant, ua, h->stream));
     if (timing) {
         G4_HIP(h, hipEventRecord(e1, h->stream));
         h->ev_pending.emplace_back(e0, e1);
@@ -710,33 +724,36 @@ int g4_stats(g4_slice *h, g4_stats_t *st) {
     st->channels = h->cfg.channels;
     st->batch = h->P.batch;
     st->tile = h->P.tile;
-    st->variant = 0;
+    st->variant = h->P.variant;
     return G4_OK;
 }
 
 int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     int rc = usable(h);
     if (rc) return rc;
-    if (tile < 0 || batch < 0 || variant < 0) return fail(G4_E_ARG, "negative plan value");
-    if (variant > 0) return fail(G4_E_UNSUPPORTED, "kernel variant %d not available", variant);
+    if (tile < 0 || batch < 0 || variant < 0 || variant > 2) return fail(G4_E_ARG, "bad plan value");
     if (batch > 0 && (h->cfg.mode == G4_MODE_PLAIN ? batch != 1 : batch > h->cfg.max_batch))
         return fail(G4_E_UNSUPPORTED, "batch %d above the allocated max_batch", batch);
     g4_config c = h->cfg;
-    c.q_list = nullptr;
     std::vector<int32_t> ql = h->P.qlist;
     c.q_list = ql.data();
+    if (variant == 1) c.flags |= G4_F_MFMA;
+    if (variant == 2) c.flags &= ~(uint32_t)G4_F_MFMA;   // 2: back to the VALU kernel
+    if (variant) c.tile = 0;
     if (tile) c.tile = tile;
     Plan P;
     rc = validate(&c, &P);
     if (rc) return rc;
-    // keep the allocation-sized batch, use the smaller pass size
-    const int keep_batch = h->P.batch;
+    // the workspaces were sized for max_batch; only the pass size changes
     G4_HIP(h, hipSetDevice(h->device));
     G4_HIP(h, hipStreamSynchronize(h->stream));
+    const int keep_batch = h->P.batch;
     h->P.ept = P.ept;
     h->P.tile = P.tile;
+    h->P.variant = P.variant;
     h->P.batch = batch ? batch : keep_batch;
     h->cfg.tile = c.tile;
+    h->cfg.flags = c.flags;
     return rebuild_work(h);
 }
 

@@ -71,9 +71,10 @@ struct GatherArgs {
 // Update `kind` 0 = plain FP64 (one measurement per pass), 1 = batched FP64,
 // 2 = batched FP32.
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
-hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems,
+// `variant` 0 = VALU kernel, 1 = MFMA direct term (kind 2, tile 16, nw % 64 == 0).
+hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems, int variant,
                          const UpdateArgs &a, hipStream_t s);
-size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d);
+size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant);
 hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s);
 // Readback / load between the documented [plane][K2][K1] order (c128, dst/src)
 // and the tile-contiguous device layout of the accumulators.

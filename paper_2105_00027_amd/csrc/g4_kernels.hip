@@ -135,15 +135,19 @@ G4_DECL_KIND(0) G4_DECL_KIND(1) G4_DECL_KIND(2)
 #undef G4_DECL_KIND
 #undef G4_DECL
 
-size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d) {
-    // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct vectors
+hipError_t launch_update_mfma(int channels, int slabs, int mgroup, int nitems, size_t lds,
+                              const UpdateArgs &a, hipStream_t s);
+
+size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant) {
+    // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct
+    // vectors (two copies, by measurement parity, for the MFMA variant)
     const size_t el = kind == 2 ? sizeof(float2) : sizeof(double2);
     const int T2 = tile < d.nw ? tile : d.nw;
     const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
     size_t pairs = (size_t)T2 * d.nw;
     if (nph) pairs += (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
     if (channels & CH_PP) pairs += (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
-    const size_t vecs = (size_t)nph * mgroup * (d.nw + T2);
+    const size_t vecs = (size_t)nph * mgroup * (d.nw + T2) * (variant == 1 ? 2 : 1);
     return pairs * 2 * el + vecs * el;
 }
 
@@ -158,10 +162,14 @@ hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems,
+hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems, int variant,
                          const UpdateArgs &a, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    const size_t lds = update_lds_bytes(kind, channels, a.tile, mgroup, a.d);
+    const size_t lds = update_lds_bytes(kind, channels, a.tile, mgroup, a.d, variant);
+    if (variant == 1) {
+        if (kind != 2 || a.tile != 16 || a.d.nw % 64) return hipErrorInvalidValue;
+        return launch_update_mfma(channels, a.d.nw / 64, mgroup, nitems, lds, a, s);
+    }
 #define G4_K(k)                                                                     \
     case k * 16 + 1: return launch_update_k##k##_e1(channels, mgroup, nitems, lds, a, s); \
     case k * 16 + 2: return launch_update_k##k##_e2(channels, mgroup, nitems, lds, a, s); \

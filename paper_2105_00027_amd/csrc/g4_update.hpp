@@ -159,114 +159,116 @@ struct ChanInfo {
 // Kind: 0 plain FP64 (one measurement, c128 accumulator, prefetched);
 //       1 batched FP64; 2 batched FP32.
 template <int KIND> struct KindInfo;
-template <> struct KindInfo<0> { using R = double; static constexpr bool prefetch = true; static constexpr int nsg = 6; };
-template <> struct KindInfo<1> { using R = double; static constexpr bool prefetch = false; static constexpr int nsg = 8; };
-template <> struct KindInfo<2> { using R = float; static constexpr bool prefetch = false; static constexpr int nsg = 8; };
+template <> struct KindInfo<0> { using R = double; static constexpr bool prefetch = true; static constexpr int nsg = 6; static constexpr bool pipe = true; static constexpr int waves = 1; };
+template <> struct KindInfo<1> { using R = double; static constexpr bool prefetch = false; static constexpr int nsg = 8; static constexpr bool pipe = true; static constexpr int waves = 1; };
+template <> struct KindInfo<2> { using R = float; static constexpr bool prefetch = false; static constexpr int nsg = 8; static constexpr bool pipe = true; static constexpr int waves = 1; };
 
 // Staging slots per thread held in registers across the compute of the
-// previous measurement: KindInfo::nsg G-block elements (both spins) and NSV
+// previous measurement: NSG G-block elements (both spins) and NSV
 // direct-vector elements.  Larger tiles copy the rest directly.
 constexpr int NSV = 4;
 
-template <int KIND, int EPT, int MG, int CH>
-__global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
-    using R = typename KindInfo<KIND>::R;
-    using V = typename Cx<R>::V;
-    using CI = ChanInfo<CH>;
-    constexpr bool PF = KindInfo<KIND>::prefetch;
-    constexpr int NSG = KindInfo<KIND>::nsg;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+// One work tile decoded, with its LDS layout and its operand staging.
+//
+// LDS: [Y | Z | X] G-block elements for both spins, then the direct vectors
+// [A | Bv] (NVB copies, indexed by measurement parity when NVB = 2).
+//   Y  exchange block, rows k1+q, columns k2+q, column-major (lanes walking
+//      K1 read consecutive words);
+//   Z  PP block, rows q-k2, columns q-k1, row-major (descending runs);
+//   X  G(K2, K1) rows of the tile, row-major;
+//   A  a(Q, K1) per PH channel and plane; Bv b(Q, K2) per channel, plane, row.
+// FP32 spin pairs (16 bytes) sit side by side and are read with one 16-byte
+// access; FP64 values are kept in two planes so that consecutive lanes stay
+// 16 bytes apart (no bank conflicts).
+template <typename V, typename CI, int NSG, int NVB>
+struct Tile {
+    int nw, nwg, nc, n, planes, ng;
+    int q, m_lo, M, p0, k1, k2, c0, T2;
+    int yr, yc, zr, zc, nY, nZ, nX, nG, nA, nB, nV;
+    int rowY, colY, rowZ, colZ, rowX, colX;
+    V *Gp, *Vt;
+    const V *dA, *dB;
+    int64_t vstride;
+    int dir_slot;
+    int sg_goff[NSG], sg_loff[NSG];
+    int sv_goff[NSV], sv_loff[NSV];
+    bool sv_isb[NSV];
+    V rgu[NSG], rgd[NSG], rv[NSV];
+    static constexpr bool SOA = sizeof(V) == 16;
 
-    const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n, planes = a.d.planes;
-    const int ng = a.d.ng;
-    const int4 it = a.t.items[blockIdx.x];
-    const int4 gr = a.t.groups[it.x];
-    const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
-    const int k1 = it.y, k2 = it.z, c0 = it.w;
-    const int T2 = min(a.tile, nw - c0);
-    const int RP = NT / nw;            // K2 rows covered by one pass of the block
-    const int tid = threadIdx.x;
-    const bool act = tid < RP * nw;
-    const int i1 = tid % nw;
-    const int r0 = tid / nw;
+    __device__ __forceinline__ int pu(int i) const { return SOA ? i : 2 * i; }
+    __device__ __forceinline__ int pd(int i) const { return SOA ? nG + i : 2 * i + 1; }
+    __device__ __forceinline__ V *At(int b) const { return Vt + (NVB == 2 ? (b & 1) * nV : 0); }
+    __device__ __forceinline__ V *Bt(int b) const { return At(b) + nA; }
 
-    // ---- LDS layout: [Y | Z | X] spin pairs, then [A | Bv] direct vectors
-    const int yr = nw + M - 1, yc = T2 + M - 1;    // exchange operand block
-    const int zr = T2 + M - 1, zc = nw + M - 1;    // PP operand block
-    const int nY = CI::ph ? yr * yc : 0;
-    const int nZ = CI::pp ? zr * zc : 0;
-    const int nX = T2 * nw;                        // G(K2, K1) rows of the tile
-    const int nG = nY + nZ + nX;
-    const int nA = CI::nph * M * nw;               // a(Q, K1) per PH channel
-    const int nB = CI::nph * M * T2;               // b(Q, K2) per PH channel
-    const int nV = nA + nB;
-    // Spin pairs of the staged G blocks: element i of [Y | Z | X].  FP32 pairs
-    // (16 bytes) sit side by side and are read with one 16-byte access; FP64
-    // values are kept in two planes so that consecutive lanes stay 16 bytes
-    // apart (no bank conflicts).
-    constexpr bool SOA = sizeof(V) == 16;
-    V *Gp = reinterpret_cast<V *>(smem_raw);
-    V *At = Gp + 2 * nG;
-    V *Bt = At + nA;
-    auto pu = [&](int i) __attribute__((always_inline)) { return SOA ? i : 2 * i; };
-    auto pd = [&](int i) __attribute__((always_inline)) { return SOA ? nG + i : 2 * i + 1; };
-
-    const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
-    const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
-    const int rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
-    const int colZ = CI::pp ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
-    const int rowX = k2 * nwg + c0, colX = k1 * nwg;
-
+    __device__ __forceinline__ void init(const UpdateArgs &a, int tile, unsigned char *smem, int tid) {
+        nw = a.d.nw; nwg = a.d.nwg; nc = a.d.nc; n = a.d.n; planes = a.d.planes; ng = a.d.ng;
+        const int4 it = a.t.items[blockIdx.x];
+        const int4 gr = a.t.groups[it.x];
+        q = gr.x; m_lo = gr.y; M = gr.z; p0 = gr.w;
+        k1 = it.y; k2 = it.z; c0 = it.w;
+        T2 = min(tile, nw - c0);
+        yr = nw + M - 1; yc = T2 + M - 1;
+        zr = T2 + M - 1; zc = nw + M - 1;
+        nY = CI::ph ? yr * yc : 0;
+        nZ = CI::pp ? zr * zc : 0;
+        nX = T2 * nw;
+        nG = nY + nZ + nX;
+        nA = CI::nph * M * nw;
+        nB = CI::nph * M * T2;
+        nV = nA + nB;
+        Gp = reinterpret_cast<V *>(smem);
+        Vt = Gp + 2 * nG;
+        rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
+        colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
+        rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
+        colZ = CI::pp ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
+        rowX = k2 * nwg + c0;
+        colX = k1 * nwg;
+        dA = static_cast<const V *>(a.dir_a);
+        dB = static_cast<const V *>(a.dir_b);
+        vstride = (int64_t)planes * n;
+        dir_slot = (int)a.dir_slot_stride;
+        static_for<0, NSG>([&](auto k) {
+            const int e = tid + k * NT;
+            if (e < nG) g_slot(e, sg_goff[k], sg_loff[k]);
+            else sg_goff[k] = sg_loff[k] = -1;
+        });
+        static_for<0, NSV>([&](auto k) {
+            const int e = tid + k * NT;
+            if (CI::ph && e < nV) v_slot(e, sv_goff[k], sv_loff[k], sv_isb[k]);
+            else { sv_goff[k] = 0; sv_loff[k] = -1; sv_isb[k] = false; }
+        });
+    }
     // element e of the staged G blocks -> (offset in G, offset in LDS)
-    auto g_slot = [&](int e, int &goff, int &loff) __attribute__((always_inline)) {
-        if (e < nY) {            // exchange block, stored column-major
+    __device__ __forceinline__ void g_slot(int e, int &goff, int &loff) const {
+        if (e < nY) {
             const int r = e / yc, c = e - r * yc;
             goff = (rowY + r) * ng + colY + c;
             loff = c * yr + r;
-        } else if (e < nY + nZ) {   // PP block, row-major
+        } else if (e < nY + nZ) {
             const int f = e - nY;
             const int r = f / zc, c = f - r * zc;
             goff = (rowZ + r) * ng + colZ + c;
             loff = nY + f;
-        } else {                 // G(K2, K1) rows, row-major
+        } else {
             const int f = e - nY - nZ;
             const int r = f / nw, c = f - r * nw;
             goff = (rowX + r) * ng + colX + c;
             loff = nY + nZ + f;
         }
-    };
-    // element e of the staged direct vectors -> (offset in dir arrays at b = 0, LDS offset)
-    auto v_slot = [&](int e, int &goff, int &loff, bool &isb) __attribute__((always_inline)) {
+    }
+    // element e of the staged direct vectors -> (offset at b = 0, LDS offset)
+    __device__ __forceinline__ void v_slot(int e, int &goff, int &loff, bool &isb) const {
         isb = e >= nA;
         const int f = isb ? e - nA : e;
         const int w = isb ? T2 : nw;
         const int sm = f / w, c = f - sm * w;          // sm = slot * M + m
         const int sl = sm / M, m = sm - sl * M;
-        goff = sl * (int)a.dir_slot_stride + (p0 + m) * n + (isb ? k2 * nw + c0 + c : k1 * nw + c);
+        goff = sl * dir_slot + (p0 + m) * n + (isb ? k2 * nw + c0 + c : k1 * nw + c);
         loff = f;
-    };
-
-    int sg_goff[NSG], sg_loff[NSG];
-    static_for<0, NSG>([&](auto k) {
-        const int e = tid + k * NT;
-        if (e < nG) g_slot(e, sg_goff[k], sg_loff[k]);
-        else sg_goff[k] = sg_loff[k] = -1;
-    });
-    int sv_goff[NSV];
-    int sv_loff[NSV];
-    bool sv_isb[NSV];
-    static_for<0, NSV>([&](auto k) {
-        const int e = tid + k * NT;
-        if (CI::ph && e < nV) v_slot(e, sv_goff[k], sv_loff[k], sv_isb[k]);
-        else { sv_goff[k] = 0; sv_loff[k] = -1; sv_isb[k] = false; }
-    });
-
-    const V *dA = static_cast<const V *>(a.dir_a);
-    const V *dB = static_cast<const V *>(a.dir_b);
-    const int64_t vstride = (int64_t)planes * n;     // direct vectors: per measurement
-    V rgu[NSG], rgd[NSG];
-    V rv[NSV];
-    auto fetch = [&](int b) __attribute__((always_inline)) {
+    }
+    __device__ __forceinline__ void fetch(const UpdateArgs &a, int b) {
         const V *gu = static_cast<const V *>(a.gu) + (int64_t)b * a.g_stride;
         const V *gd = static_cast<const V *>(a.gd) + (int64_t)b * a.g_stride;
         static_for<0, NSG>([&](auto k) {
@@ -279,8 +281,9 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
             static_for<0, NSV>([&](auto k) {
                 if (sv_loff[k] >= 0) rv[k] = ld((sv_isb[k] ? dB : dA) + sv_goff[k] + b * vstride);
             });
-    };
-    auto store = [&](int b) __attribute__((always_inline)) {
+    }
+    __device__ __forceinline__ void store(const UpdateArgs &a, int b, int tid) {
+        V *at = At(b);
         static_for<0, NSG>([&](auto k) {
             if (sg_loff[k] >= 0) {
                 st(Gp + pu(sg_loff[k]), rgu[k]);
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
         });
         if (CI::ph)
             static_for<0, NSV>([&](auto k) {
-                if (sv_loff[k] >= 0) st((sv_isb[k] ? Bt : At) + sv_loff[k], rv[k]);
+                if (sv_loff[k] >= 0) st(at + (sv_isb[k] ? nA : 0) + sv_loff[k], rv[k]);
             });
         // elements beyond the register slots (large tiles): direct copy
         const V *gu = static_cast<const V *>(a.gu) + (int64_t)b * a.g_stride;
@@ -305,17 +308,55 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
                 int go, lo;
                 bool isb;
                 v_slot(e, go, lo, isb);
-                st((isb ? Bt : At) + lo, ld((isb ? dB : dA) + go + b * vstride));
+                st(at + (isb ? nA : 0) + lo, ld((isb ? dB : dA) + go + b * vstride));
             }
-    };
+    }
+    // operands of entry (row i2l, column i1, plane m) from LDS
+    __device__ __forceinline__ void x_at(int i2l, int i1, V &u, V &d) const {
+        const int i = nY + nZ + i2l * nw + i1;
+        u = ld(Gp + pu(i));
+        d = ld(Gp + pd(i));
+    }
+    __device__ __forceinline__ void y_at(int i2l, int i1, int m, V &u, V &d) const {
+        const int i = (i2l + m) * yr + i1 + m;
+        u = ld(Gp + pu(i));
+        d = ld(Gp + pd(i));
+    }
+    __device__ __forceinline__ void z_at(int i2l, int i1, int m, V &u, V &d) const {
+        const int i = nY + (m + T2 - 1 - i2l) * zc + m + nw - 1 - i1;
+        u = ld(Gp + pu(i));
+        d = ld(Gp + pd(i));
+    }
+    // physical accumulator index (tile-contiguous layout, see update_kernel)
+    __device__ __forceinline__ int64_t entry(int m, int i2l, int i1) const {
+        return (((int64_t)(p0 + m) * nc + k2) * nc + k1) * nw * nw + (int64_t)(c0 + i2l) * nw + i1;
+    }
+};
 
-    // Accumulator layout in device memory, tile-contiguous:
-    //   [plane][k2][k1][i2][i1]  (K2 = k2*nw + i2, K1 = k1*nw + i1),
-    // so one plane of a tile is a single run of T2*nw entries.  Readback and
-    // load translate to the documented [plane][K2][K1] order.
-    // Physical index of (plane p0, row c0 + r0, column i1); + m*n*n + j*RP*nw.
-    const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * nw * nw + (int64_t)(c0 + r0) * nw + i1;
-    const int64_t nn = (int64_t)n * n;
+// Accumulator layout in device memory, tile-contiguous:
+//   [plane][k2][k1][i2][i1]  (K2 = k2*nw + i2, K1 = k1*nw + i1),
+// so one plane of a tile is a single run of T2*nw entries.  Readback and load
+// translate to the documented [plane][K2][K1] order.
+//
+// VALU kernel: thread (r0 = tid / nw, i1 = tid % nw) owns rows
+// r0 + j*RP (j < EPT, RP = 256/nw) of column i1 for every plane of the group.
+template <int KIND, int EPT, int MG, int CH>
+__global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(UpdateArgs a) {
+    using R = typename KindInfo<KIND>::R;
+    using V = typename Cx<R>::V;
+    using CI = ChanInfo<CH>;
+    constexpr bool PF = KindInfo<KIND>::prefetch;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    Tile<V, CI, KindInfo<KIND>::nsg, 1> t;
+    t.init(a, a.tile, smem_raw, tid);
+    const int nw = t.nw, T2 = t.T2, M = t.M;
+    const int RP = NT / nw;            // K2 rows covered by one pass of the block
+    const bool act = tid < RP * nw;
+    const int i1 = tid % nw;
+    const int r0 = tid / nw;
+    const int64_t nn = (int64_t)t.n * t.n;
+    const int64_t ebase = t.entry(0, r0, i1);   // + m*nn + j*RP*nw
 
     // register accumulators; in the plain kind they start from the slice values,
     // loaded here so that the HBM reads overlap the operand staging
@@ -341,27 +382,33 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     }
 
     const bool full = (T2 == a.tile) && (M == MG);
-    if (a.batch > 0) fetch(0);
+    // PIPE: the next measurement's operands are loaded into registers while the
+    // current one is computed; otherwise each measurement is staged on its own
+    // and latency is covered by more resident blocks (fewer live registers).
+    constexpr bool PIPE = KindInfo<KIND>::pipe;
+    if (PIPE && a.batch > 0) t.fetch(a, 0);
     for (int b = 0; b < a.batch; ++b) {
         __syncthreads();          // the previous measurement's operands are consumed
-        store(b);
+        if (!PIPE) t.fetch(a, b);
+        t.store(a, b, tid);
         __syncthreads();          // this measurement's operands are in LDS
-        if (b + 1 < a.batch) fetch(b + 1);
+        if (PIPE && b + 1 < a.batch) t.fetch(a, b + 1);
         if (!act) continue;
         const R s = (R)a.sign[b];
+        const V *At = t.At(b), *Bt = t.Bt(b);
         // G(K2,K1) times -s_b for the PH exchange (its minus folded in), +s_b for PP
         V xu[EPT], xd[EPT];
         static_for<0, EPT>([&](auto j) {
-            const int i2l = min(r0 + j * RP, T2 - 1);
-            const int ix = nY + nZ + i2l * nw + i1;
-            xu[j] = cscale(ld(Gp + pu(ix)), CI::ph ? -s : s);
-            xd[j] = cscale(ld(Gp + pd(ix)), CI::ph ? -s : s);
+            V u, d;
+            t.x_at(min(r0 + j * RP, T2 - 1), i1, u, d);
+            xu[j] = cscale(u, CI::ph ? -s : s);
+            xd[j] = cscale(d, CI::ph ? -s : s);
         });
         auto body = [&](auto j, auto m) __attribute__((always_inline)) {
             const int i2l = r0 + j * RP;
             if (CI::ph) {
-                const int iy = (i2l + m) * yr + i1 + m;
-                const V yu = ld(Gp + pu(iy)), yd = ld(Gp + pd(iy));
+                V yu, yd;
+                t.y_at(i2l, i1, m, yu, yd);
                 if (CI::mag) {
                     cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
                     cmac(acc[0][j][m], xu[j], yu);
@@ -376,13 +423,13 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
             }
             if (CI::pp) {
                 // the PP term takes +s_b: undo the PH negation when both are present
-                const int iz = nY + (m + T2 - 1 - i2l) * zc + m + nw - 1 - i1;
-                const V zu = ld(Gp + pu(iz)), zd = ld(Gp + pd(iz));
+                V zu, zd;
+                t.z_at(i2l, i1, m, zu, zd);
                 if (CI::ph) {
-                    V t = cmul(zu, xd[j]);
-                    cmac(t, zd, xu[j]);
-                    acc[CI::slot_pp][j][m].x -= t.x;
-                    acc[CI::slot_pp][j][m].y -= t.y;
+                    V w = cmul(zu, xd[j]);
+                    cmac(w, zd, xu[j]);
+                    acc[CI::slot_pp][j][m].x -= w.x;
+                    acc[CI::slot_pp][j][m].y -= w.y;
                 } else {
                     cmac(acc[CI::slot_pp][j][m], zu, xd[j]);
                     cmac(acc[CI::slot_pp][j][m], zd, xu[j]);
@@ -413,6 +460,128 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
                 if (CI::chg) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_chg][j][m]);
                 if (CI::pp) acc_update(a.acc[2], a.acc_kind, e, acc[CI::slot_pp][j][m]);
             }
+        });
+    });
+}
+
+// MFMA kernel (batched FP32, nw a multiple of 64, tile of 16 K2 rows): the
+// direct term of each plane is a complex rank-B update, summed on the matrix
+// cores with v_mfma_f32_16x16x4f32 (K = 4: two measurements x {re, im}):
+//   Re D += sum_b [ Re b(K2) Re a(K1) - Im b(K2) Im a(K1) ]
+//   Im D += sum_b [ Re b(K2) Im a(K1) + Im b(K2) Re a(K1) ]
+// with A[row = K2][k] built from b and B[k][col = K1] from a.  Lane l of wave w
+// holds rows 4*(l/16) + t (t < 4) of column 16*w + 64*s + l%16 (slab s), the
+// MFMA accumulator layout; the exchange and PP Hadamard sums are added into
+// the same registers on the VALU.  The direct vectors of two consecutive
+// measurements are kept in LDS (indexed by parity) for the paired MFMA.
+template <int SL, int MG, int CH>
+__global__ __launch_bounds__(NT) void update_mfma_kernel(UpdateArgs a) {
+    using V = float2;
+    using CI = ChanInfo<CH>;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    Tile<V, CI, 8, 2> t;
+    t.init(a, 16, smem_raw, tid);
+    const int nw = t.nw, T2 = t.T2, M = t.M;
+    const int w = tid / 64, l = tid % 64;
+    const int g4r = l / 16, c16 = l % 16;
+    const int64_t nn = (int64_t)t.n * t.n;
+
+    f4 re[CI::count][SL][MG], im[CI::count][SL][MG];
+    static_for<0, CI::count>([&](auto c) {
+        static_for<0, SL>([&](auto s) {
+            static_for<0, MG>([&](auto m) {
+                re[c][s][m] = f4{0.f, 0.f, 0.f, 0.f};
+                im[c][s][m] = f4{0.f, 0.f, 0.f, 0.f};
+            });
+        });
+    });
+
+    if (a.batch > 0) t.fetch(a, 0);
+    for (int b = 0; b < a.batch; ++b) {
+        __syncthreads();
+        t.store(a, b, tid);
+        __syncthreads();
+        if (b + 1 < a.batch) t.fetch(a, b + 1);
+        const float sg = (float)a.sign[b];
+        // exchange / PP Hadamard terms on the VALU
+        static_for<0, SL>([&](auto s) {
+            const int i1 = 64 * s + 16 * w + c16;
+            static_for<0, 4>([&](auto tt) {
+                const int i2l = 4 * g4r + tt;
+                if (i2l >= T2) return;
+                V xu, xd;
+                t.x_at(i2l, i1, xu, xd);
+                xu = cscale(xu, CI::ph ? -sg : sg);
+                xd = cscale(xd, CI::ph ? -sg : sg);
+                static_for<0, MG>([&](auto m) {
+                    if (m >= M) return;
+                    if (CI::ph) {
+                        V yu, yd;
+                        t.y_at(i2l, i1, m, yu, yd);
+                        V ex = cmul(xu, yu);
+                        cmac(ex, xd, yd);
+                        if (CI::mag) {
+                            re[0][s][m][tt()] += ex.x;
+                            im[0][s][m][tt()] += ex.y;
+                        }
+                        if (CI::chg) {
+                            re[CI::slot_chg][s][m][tt()] += ex.x;
+                            im[CI::slot_chg][s][m][tt()] += ex.y;
+                        }
+                    }
+                    if (CI::pp) {
+                        V zu, zd;
+                        t.z_at(i2l, i1, m, zu, zd);
+                        V w2 = cmul(zu, xd);
+                        cmac(w2, zd, xu);
+                        const float sgn = CI::ph ? -1.f : 1.f;
+                        re[CI::slot_pp][s][m][tt()] += sgn * w2.x;
+                        im[CI::slot_pp][s][m][tt()] += sgn * w2.y;
+                    }
+                });
+            });
+        });
+        // direct term: one MFMA pair per two measurements
+        if (CI::ph && ((b & 1) || b + 1 == a.batch)) {
+            const int b0 = b & ~1;
+            const int bk = b0 + (g4r >> 1);        // measurement of this lane's k slot
+            const bool comp = g4r & 1;
+            const bool live = bk <= b;             // an unpaired last measurement pads with 0
+            const V *At = t.At(bk), *Bt = t.Bt(bk);
+            static_for<0, CI::nph>([&](auto c) {
+                static_for<0, MG>([&](auto m) {
+                    if (m >= M) return;
+                    const int sm = c * M + m;
+                    V bv = live && c16 < T2 ? ld(Bt + sm * T2 + c16) : V{0.f, 0.f};
+                    const float ar = comp ? -bv.y : bv.x;
+                    const float ai = comp ? bv.y : bv.x;
+                    static_for<0, SL>([&](auto s) {
+                        const int i1 = 64 * s + 16 * w + c16;
+                        V av = live ? ld(At + sm * nw + i1) : V{0.f, 0.f};
+                        const float br = comp ? av.y : av.x;
+                        const float bi = comp ? av.x : av.y;
+                        re[c][s][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re[c][s][m], 0, 0, 0);
+                        im[c][s][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, im[c][s][m], 0, 0, 0);
+                    });
+                });
+            });
+        }
+    }
+    static_for<0, SL>([&](auto s) {
+        const int i1 = 64 * s + 16 * w + c16;
+        static_for<0, 4>([&](auto tt) {
+            const int i2l = 4 * g4r + tt;
+            if (i2l >= T2) return;
+            static_for<0, MG>([&](auto m) {
+                if (m >= M) return;
+                const int64_t e = t.entry(m, i2l, i1);
+                static_for<0, CI::count>([&](auto c) {
+                    const int ch = c == 0 ? (CI::mag ? 0 : (CI::chg ? 1 : 2)) : (c == 1 ? (CI::mag && CI::chg ? 1 : 2) : 2);
+                    acc_update(a.acc[ch], a.acc_kind, e, V{re[c][s][m][tt()], im[c][s][m][tt()]});
+                });
+            });
         });
     });
 }

@@ -45,6 +45,11 @@ BAD = [
 ]
 
 
+def test_mfma_plan_accepted_where_it_fits():
+    c = base(mode=1, max_batch=16, prod=1, g_in=1, flags=8)
+    assert g4.g4_slice_size(c)[0] == 128 * 1024 * 1024
+
+
 @pytest.mark.parametrize("kw", BAD, ids=lambda k: ",".join("%s=%s" % i for i in k.items())[:40])
 def test_invalid_configs_rejected_without_hip(kw):
     c = base(**kw)
@@ -58,7 +63,12 @@ def test_invalid_configs_rejected_without_hip(kw):
 
 
 def test_unsupported_is_distinguished():
-    for kw in (dict(nw=512), dict(mode=1, max_batch=8, prod=2, g_in=1), dict(tile=3)):
+    mfma = 8
+    for kw in (dict(nw=512), dict(mode=1, max_batch=8, prod=2, g_in=1), dict(tile=3),
+               dict(flags=mfma),                                    # plain mode
+               dict(mode=1, max_batch=8, prod=1, g_in=1, flags=mfma, nw=24),
+               dict(mode=1, max_batch=8, prod=1, g_in=1, flags=mfma, channels=7),
+               dict(mode=1, max_batch=8, prod=1, g_in=1, flags=mfma, tile=8)):
         with pytest.raises(g4.G4Error) as e:
             g4.g4_slice_size(base(**kw))
         assert e.value.code == g4.G4_E_UNSUPPORTED

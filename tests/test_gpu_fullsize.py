@@ -59,13 +59,13 @@ def test_plain_slice_full_size():
     assert rel_fro(got, want) <= 1e-12
 
 
-@pytest.mark.parametrize("acc", [0, 1], ids=["acc-c128", "acc-kahan"])
-def test_batched_full_size(acc):
+@pytest.mark.parametrize("acc,flags", [(0, 0), (1, 0), (0, 8)], ids=["acc-c128", "acc-kahan", "mfma"])
+def test_batched_full_size(acc, flags):
     """The same slice, 4096 measurements in passes of 16, complex64 G, FP32 products."""
     g4 = g4mod()
     w = C3_BATCHED
     M, B, chunk = w.measurements, w.batch, 512
-    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=B))
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=B, flags=flags))
     try:
         for b0 in range(0, M, chunk):
             gu, gd = device_g(w, 1, b0, chunk)

@@ -191,3 +191,50 @@ def test_argument_errors_on_device():
         assert g4.g4_stats(h)["measurements"] == 0
     finally:
         g4.g4_destroy(h)
+
+
+@pytest.mark.parametrize("w,count,B,channels", [(MULTI, 5, 4, ALL), (MULTI, 4, 3, PH_CHARGE),
+                                               (MULTI, 3, 2, PH_MAGNETIC | PH_CHARGE),
+                                               (NW128, 5, 4, PH_MAGNETIC)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_batched_fp32_mfma_direct(w, count, B, channels):
+    """Direct term on the matrix cores (paired measurements, odd tails padded)."""
+    g4 = g4mod()
+    w = w.with_(channels=channels)
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=B, flags=g4.G4_F_MFMA)
+    got, st = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
+    assert st["variant"] == 1 and st["tile"] == 16
+    check(got, oracle_out(w, count, channels), 1e-6)
+
+
+def test_mfma_register_budget_rejected():
+    g4 = g4mod()
+    w = NW128.with_(channels=PH_MAGNETIC | PH_CHARGE)     # 2 channels x 2 slabs x 8 planes
+    with pytest.raises(g4.G4Error) as e:
+        g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, batch=2, flags=g4.G4_F_MFMA))
+    assert e.value.code == g4.G4_E_UNSUPPORTED
+
+
+def test_set_plan_switches_variant_and_batch():
+    g4 = g4mod()
+    w = MULTI.with_(channels=PH_MAGNETIC)
+    gu, gd, s = host_inputs(w, 6)
+    want = oracle_out(w, 6, PH_MAGNETIC)
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=4))
+    try:
+        du, dd = to_dev(gu, 1), to_dev(gd, 1)
+        g4.g4_accumulate(h, du[:2], dd[:2], s[:2])
+        g4.g4_set_plan(h, 0, 3, 1)                    # MFMA, passes of 3
+        assert g4.g4_stats(h)["variant"] == 1
+        g4.g4_accumulate(h, du[2:5], dd[2:5], s[2:5])
+        g4.g4_set_plan(h, 8, 2, 2)                    # back to VALU, tile 8, passes of 2
+        st = g4.g4_stats(h)
+        assert st["variant"] == 0 and st["tile"] == 8 and st["batch"] == 2
+        g4.g4_accumulate(h, du[5:], dd[5:], s[5:])
+        got = g4.g4_readback(h, 1).reshape(want[1].shape)
+        with pytest.raises(g4.G4Error):
+            g4.g4_set_plan(h, 0, 5, 0)                # above the allocated max_batch
+    finally:
+        g4.g4_destroy(h)
+    assert rel_fro(got, want[1]) <= 1e-6
