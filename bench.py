@@ -59,6 +59,30 @@ def roofline(E, ng, B, g_bytes, acc_bytes, channels, launch_s):
             "frac": ach / (ALU_PEAK / 1e12), "traffic": None, "algorithmic_flops_per_launch": fl}
 
 
+def measured_traffic(plan):
+    """HBM bytes per launch of the kernel that runs `plan`, from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by its copy-kernel
+    calibration), or None when no counter run covers this plan or the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        h = hashlib.sha1()
+        for name in d["source_files"]:
+            with open(os.path.join(ROOT, "paper_2105_00027_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
+    except (OSError, ValueError, KeyError):
+        return None
+    if h.hexdigest() != d.get("source_sha1"):
+        return None
+    for k in d["kernels"].values():
+        if k["plan"] == plan:
+            return k["bytes_per_launch"]
+    return None
+
+
 def sampled_error(w, h, g4, channel, b_seq, sign_seq, nsample):
     """Relative Frobenius error of sampled slice entries against the oracle."""
     from oracle import sampled
@@ -106,7 +130,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64,
+                    help="measurements per step (the slice's max_batch)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default plan instead of timing the candidates first")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--acc", default="c128", choices=["c128", "kahan"])
     ap.add_argument("--mfma", action="store_true", help="direct term on the matrix cores")
@@ -180,6 +207,9 @@ def main():
                              acc=acc, max_batch=B, tile=args.tile,
                              flags=g4.G4_F_MFMA if args.mfma else 0))
     nblk = pool // B
+    if not args.no_autotune:
+        tune = g4.g4_autotune(h, gu[:B], gd[:B], sg[:B], B, 1e-6)
+        out["autotune"] = tune
 
     def step(i):
         j = i % nblk
@@ -207,14 +237,20 @@ def main():
     out["value"] = value
     out["ms_per_step"] = ms / max(1, args.steps)
     out["config"] = {"workload": "4x4 Hubbard cluster G4 slice: Nc=16, Nw=64, Nq=16, Nwex=8, "
-                                 "E=%d entries, PH magnetic, batched B=%d, complex64 G, FP32 "
-                                 "products, %s accumulator" % (E, B, args.acc),
-                     "entries": E, "batch": B, "tile": st["tile"], "accumulator": args.acc,
+                                 "E=%d entries, PH magnetic, %d measurements per step in passes "
+                                 "of %d, complex64 G, FP32 products, %s accumulator"
+                                 % (E, B, st["batch"], args.acc),
+                     "entries": E, "measurements_per_step": B, "pass_batch": st["batch"],
+                     "tile": st["tile"], "accumulator": args.acc,
                      "direct_term": "mfma" if st["variant"] == 1 else "valu",
                      "measurements_timed": args.steps * B}
     out["kernel"] = {"name": "update_mfma_kernel" if st["variant"] == 1 else "update_kernel",
                      "avg_launch_ms": launch_s * 1e3, "launches": st["timed_launches"]}
-    out["roofline"] = roofline(E, ng, B, 8, 16, w.channels, launch_s) if args.steps else None
+    out["roofline"] = roofline(E, ng, st["batch"], 8, 16, w.channels, launch_s) if args.steps else None
+    if out["roofline"]:
+        out["roofline"]["traffic"] = measured_traffic(
+            {"mode": 1, "acc": acc, "batch": st["batch"], "tile": st["tile"],
+             "variant": st["variant"], "channels": w.channels, "entries": E})
     if not args.no_check and args.steps:
         err, ns = sampled_error(w, h, g4, 1, b_seq, sg[b_seq], 256)
         out["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-6}
@@ -247,6 +283,9 @@ def main():
                  "ms_per_measurement": pms / M, "dtype": "f64", "tile": pst["tile"],
                  "kernel_avg_launch_ms": plaunch * 1e3,
                  "roofline": roofline(E, ng, 1, 16, 16, w.channels, plaunch)}
+        plain["roofline"]["traffic"] = measured_traffic(
+            {"mode": 0, "acc": 0, "batch": 1, "tile": pst["tile"], "variant": 0,
+             "channels": w.channels, "entries": E})
         if not args.no_check:
             err, ns = sampled_error(w, hp, g4, 1, list(range(M)), ps, 256)
             plain["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-12}

@@ -200,6 +200,28 @@ int g4_stats(g4_slice *h, g4_stats_t *st);
  * combination cannot run for this slice.  Waits for the handle's stream. */
 int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant);
 
+typedef struct g4_tune_result {
+    int32_t batch;               /* measurements per pass chosen */
+    int32_t tile;                /* K2 rows per work tile chosen */
+    int32_t variant;             /* 0 VALU kernel, 1 MFMA direct term */
+    int32_t candidates;          /* plans timed (0 when taken from the cache) */
+    double ms_per_measurement;   /* pass time per measurement of the chosen plan */
+    double rel_err;              /* its relative difference from the first plan tried, on a
+                                    sample of entries */
+} g4_tune_result;
+
+/* Choose the plan (pass size up to min(max_batch, batch), work-tile height,
+ * kernel variant) with the shortest pass time per measurement on `batch`
+ * caller-supplied measurements (same layout and ownership as g4_accumulate),
+ * among those whose sampled result differs from the first plan tried by at
+ * most tol (relative Frobenius), and install it.  With G4_AUTOTUNE_CACHE
+ * naming a file in the environment, a choice stored there for the same GPU
+ * architecture and slice shape is reused and new choices are appended.
+ * Requires a fresh or reset slice (G4_E_STATE otherwise); leaves the
+ * accumulators and statistics zeroed.  Synchronous. */
+int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *sign, int32_t batch,
+                double tol, g4_tune_result *out);
+
 /* Release everything owned by h (waits for its stream).  NULL is a no-op. */
 void g4_destroy(g4_slice *h);
 

@@ -11,7 +11,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "g4_internal.hpp"
@@ -755,6 +758,188 @@ int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     h->cfg.tile = c.tile;
     h->cfg.flags = c.flags;
     return rebuild_work(h);
+}
+
+// ---- autotuner -----------------------------------------------------------
+namespace {
+
+// Whole-pass time (gather + update) of the current plan on measurements
+// [0, nb) of the caller's sample, after one untimed pass; accumulators zeroed
+// before and after.
+int time_plan(g4_slice *h, const char *gu, const char *gd, const double *sign, int nb, double *ms) {
+    hipEvent_t e0, e1;
+    G4_HIP(h, hipEventCreate(&e0));
+    G4_HIP(h, hipEventCreate(&e1));
+    int rc = G4_OK;
+    for (int rep = 0; rep < 2 && rc == G4_OK; ++rep) {
+        for (int c = 0; c < 3; ++c)
+            if (h->acc[c]) G4_HIP(h, launch_fill_zero(h->acc[c], h->P.acc_bytes, h->stream));
+        G4_HIP(h, hipEventRecord(e0, h->stream));
+        for (int b0 = 0; b0 < nb && rc == G4_OK; b0 += h->P.batch)
+            rc = run_pass(h, gu, gd, sign, b0, std::min(h->P.batch, nb - b0));
+        G4_HIP(h, hipEventRecord(e1, h->stream));
+        G4_HIP(h, hipEventSynchronize(e1));
+    }
+    float f = 0.f;
+    if (rc == G4_OK) G4_HIP(h, hipEventElapsedTime(&f, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = f;
+    return rc;
+}
+
+int sample_entries(g4_slice *h, std::vector<double> &out) {
+    // a block at the start and one at the end of the first channel's slice
+    const uint64_t n = std::min<uint64_t>(h->P.entries / 2, 32768);
+    out.assign(4 * n, 0.0);
+    uint32_t ch = (h->cfg.channels & 1) ? 1u : ((h->cfg.channels & 2) ? 2u : 4u);
+    int rc = g4_readback(h, ch, 0, n, out.data());
+    if (rc) return rc;
+    return g4_readback(h, ch, h->P.entries - n, n, out.data() + 2 * n);
+}
+
+double rel_diff(const std::vector<double> &a, const std::vector<double> &ref) {
+    double num = 0.0, den = 0.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        num += (a[i] - ref[i]) * (a[i] - ref[i]);
+        den += ref[i] * ref[i];
+    }
+    return den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+}
+
+std::string tune_key(g4_slice *h) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    std::ostringstream k;
+    const g4_config &c = h->cfg;
+    k << arch << ":" << c.lx << "x" << c.ly << ":nw" << c.nw << ":nwex" << c.nwex << ":planes"
+      << h->P.d.planes << ":ch" << c.channels << ":in" << c.g_in << ":prod" << c.prod << ":acc"
+      << c.acc << ":mode" << c.mode << ":maxb" << c.max_batch;
+    return k.str();
+}
+
+}  // namespace
+
+int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *sign, int32_t batch,
+                double tol, g4_tune_result *out) {
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!G_up || !G_dn || !sign || batch < 1 || !(tol > 0)) return fail(G4_E_ARG, "bad autotune arguments");
+    if (h->measurements != 0) return fail(G4_E_STATE, "autotune needs a fresh or reset slice");
+    G4_HIP(h, hipSetDevice(h->device));
+    G4_HIP(h, hipStreamSynchronize(h->stream));
+    const char *gu = static_cast<const char *>(G_up), *gd = static_cast<const char *>(G_dn);
+    g4_tune_result res;
+    std::memset(&res, 0, sizeof(res));
+    const std::string key = tune_key(h);
+    const char *cache = std::getenv("G4_AUTOTUNE_CACHE");
+    int cb = 0, ct = 0, cv = -1;
+    if (cache) {
+        std::ifstream f(cache);
+        std::string k;
+        int b, t, v;
+        double ms;
+        while (f >> k >> b >> t >> v >> ms)
+            if (k == key) { cb = b; ct = t; cv = v; res.ms_per_measurement = ms; }
+    }
+    const bool plain = h->cfg.mode == G4_MODE_PLAIN;
+    const int maxb = plain ? 1 : std::min(h->cfg.max_batch, batch);
+    struct Cand { int batch, tile, variant; };
+    std::vector<Cand> cands;
+    if (cv >= 0) {
+        cands.push_back({cb, ct, cv});
+    } else {
+        std::vector<int> bs;
+        for (int b = 1; b <= maxb; b *= 2)
+            if (b >= 4 || b == maxb) bs.push_back(b);
+        if (bs.empty() || bs.back() != maxb) bs.push_back(maxb);
+        const int rp = 256 / h->cfg.nw;
+        for (int v = 0; v < 2; ++v)
+            for (int b : bs)
+                for (int e : {1, 2, 4}) {
+                    if (v == 1 && e > 1) continue;
+                    cands.push_back({b, v == 1 ? 16 : e * rp, v});
+                }
+    }
+    std::vector<double> ref, cur;
+    double best = 1e300;
+    Cand best_c{h->P.batch, h->P.tile, h->P.variant};
+    const Plan keep = h->P;
+    const g4_config keep_cfg = h->cfg;
+    if (cv >= 0) {                 // cached choice: install without timing
+        best = res.ms_per_measurement;
+        best_c = cands[0];
+        cands.clear();
+    }
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const Cand &c = cands[i];
+        g4_config cc = keep_cfg;
+        std::vector<int32_t> ql = keep.qlist;
+        cc.q_list = ql.data();
+        cc.flags = c.variant ? (cc.flags | G4_F_MFMA) : (cc.flags & ~(uint32_t)G4_F_MFMA);
+        cc.tile = c.tile;
+        Plan P;
+        if (validate(&cc, &P) != G4_OK) continue;          // does not fit this slice
+        h->P.ept = P.ept;
+        h->P.tile = P.tile;
+        h->P.variant = P.variant;
+        h->P.batch = c.batch;
+        rc = rebuild_work(h);
+        if (rc) return rc;
+        const int nb = std::max(c.batch, std::min(batch, maxb));
+        double ms = 0.0;
+        rc = time_plan(h, gu, gd, sign, nb, &ms);
+        if (rc) return rc;
+        rc = sample_entries(h, cur);
+        if (rc) return rc;
+        if (ref.empty()) ref = cur;                          // the first plan is the reference
+        const double err = rel_diff(cur, ref);
+        res.candidates += 1;
+        const double per = ms / nb;
+        if (err <= tol && per < best) {
+            best = per;
+            best_c = c;
+            res.rel_err = err;
+        }
+    }
+    if (best == 1e300) {
+        h->P = keep;
+        h->cfg = keep_cfg;
+        rebuild_work(h);
+        return fail(G4_E_UNSUPPORTED, "no plan met the error tolerance");
+    }
+    // install the winner, clear everything it touched
+    g4_config cc = keep_cfg;
+    std::vector<int32_t> ql = keep.qlist;
+    cc.q_list = ql.data();
+    cc.flags = best_c.variant ? (cc.flags | G4_F_MFMA) : (cc.flags & ~(uint32_t)G4_F_MFMA);
+    cc.tile = best_c.tile;
+    Plan P;
+    rc = validate(&cc, &P);
+    if (rc) return rc;
+    h->P.ept = P.ept;
+    h->P.tile = P.tile;
+    h->P.variant = P.variant;
+    h->P.batch = best_c.batch;
+    h->cfg.flags = cc.flags;
+    h->cfg.tile = cc.tile;
+    rc = rebuild_work(h);
+    if (rc) return rc;
+    rc = g4_reset(h);
+    if (rc) return rc;
+    G4_HIP(h, hipStreamSynchronize(h->stream));
+    if (cv < 0) res.ms_per_measurement = best;
+    res.batch = best_c.batch;
+    res.tile = best_c.tile;
+    res.variant = best_c.variant;
+    if (cache && cv < 0) {
+        std::ofstream f(cache, std::ios::app);
+        f << key << " " << res.batch << " " << res.tile << " " << res.variant << " "
+          << res.ms_per_measurement << "\n";
+    }
+    if (out) *out = res;
+    return G4_OK;
 }
 
 void g4_destroy(g4_slice *h) { release(h); }

@@ -52,6 +52,12 @@ class g4_config(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("beta", ctypes.c_double)]
 
 
+class g4_tune_result(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("tile", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("ms_per_measurement", ctypes.c_double),
+                ("rel_err", ctypes.c_double)]
+
+
 class g4_stats_t(ctypes.Structure):
     _fields_ = [("measurements", ctypes.c_uint64), ("sign_sum", ctypes.c_double),
                 ("launches", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
@@ -88,6 +94,8 @@ _sig = {
     "g4_reset": ([_vp], ctypes.c_int),
     "g4_stats": ([_vp, ctypes.POINTER(g4_stats_t)], ctypes.c_int),
     "g4_set_plan": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "g4_autotune": ([_vp, _vp, _vp, _dp, ctypes.c_int32, ctypes.c_double,
+                     ctypes.POINTER(g4_tune_result)], ctypes.c_int),
     "g4_destroy": ([_vp], None),
     "g4_last_error": ([], ctypes.c_char_p),
     "g4_synth_fill": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -246,6 +254,22 @@ def g4_stats(h: Slice) -> dict:
 
 def g4_set_plan(h: Slice, tile: int = 0, batch: int = 0, variant: int = 0) -> None:
     _check(_L.g4_set_plan(h.ptr, tile, batch, variant))
+
+
+def g4_autotune(h: Slice, G_up, G_dn, sign, batch: Optional[int] = None, tol: float = 1e-6) -> dict:
+    s = np.ascontiguousarray(np.asarray(sign, dtype=np.float64).reshape(-1))
+    if batch is None:
+        batch = s.shape[0]
+    if batch > s.shape[0]:
+        raise G4Error(G4_E_ARG, "sign has %d entries, batch=%d" % (s.shape[0], batch))
+    el = 16 if h.cfg.c.g_in == G4_IN_C128 else 8
+    need = batch * h.ng * h.ng * el
+    pu = _device_ptr(G_up, need, el)
+    pd = _device_ptr(G_dn, need, el)
+    r = g4_tune_result()
+    _check(_L.g4_autotune(h.ptr, _vp(pu), _vp(pd), s.ctypes.data_as(_dp), int(batch), tol,
+                          ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in g4_tune_result._fields_}
 
 
 def g4_destroy(h: Slice) -> None:

@@ -238,3 +238,35 @@ def test_set_plan_switches_variant_and_batch():
     finally:
         g4.g4_destroy(h)
     assert rel_fro(got, want[1]) <= 1e-6
+
+
+def test_autotune_installs_a_plan_and_keeps_parity(tmp_path, monkeypatch):
+    g4 = g4mod()
+    w = MULTI.with_(channels=PH_MAGNETIC)
+    gu, gd, s = host_inputs(w, 8)
+    du, dd = to_dev(gu, 1), to_dev(gd, 1)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("G4_AUTOTUNE_CACHE", str(cache))
+    cfg = config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=8)
+    h = g4.g4_init_slice(cfg)
+    try:
+        r = g4.g4_autotune(h, du, dd, s, 8, 1e-6)
+        assert r["candidates"] >= 4 and r["batch"] in (4, 8) and r["rel_err"] <= 1e-6
+        st = g4.g4_stats(h)
+        assert st["measurements"] == 0 and st["batch"] == r["batch"] and st["tile"] == r["tile"]
+        assert np.count_nonzero(g4.g4_readback(h, 1)) == 0          # left zeroed
+        g4.g4_accumulate(h, du, dd, s)
+        got = g4.g4_readback(h, 1).reshape(w.planes, w.n, w.n)
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_autotune(h, du, dd, s, 8, 1e-6)
+        assert e.value.code == g4.G4_E_STATE
+    finally:
+        g4.g4_destroy(h)
+    assert rel_fro(got, oracle_out(w, 8, PH_MAGNETIC)[1]) <= 1e-6
+    h = g4.g4_init_slice(cfg)
+    try:
+        r2 = g4.g4_autotune(h, du, dd, s, 8, 1e-6)          # from the cache
+        assert r2["candidates"] == 0 and (r2["batch"], r2["tile"], r2["variant"]) == \
+            (r["batch"], r["tile"], r["variant"])
+    finally:
+        g4.g4_destroy(h)
