@@ -33,6 +33,8 @@ METRIC = "G4 entry-updates/s per GPU (plain FP64 vs batched mixed) at stated err
 HBM_PEAK = 8.0e12                                   # bytes/s, MI355X HBM3E
 ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9                 # FP32 or FP64 FMA, non-packed: 78.6 TFLOP/s
 FLOPS_PER_EU = {1: 24, 2: 24, 4: 16}                 # per channel: direct 8 + exchange 16; PP 16
+VARIANTS = ["valu", "mfma-direct", "packed-lds", "packed-lds-deep"]
+KERNELS = ["update_kernel", "update_mfma_kernel", "update_packed_kernel", "update_packed_kernel"]
 
 
 def algorithmic(E, ng, B, g_bytes, acc_bytes, channels):
@@ -137,6 +139,10 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--acc", default="c128", choices=["c128", "kahan"])
     ap.add_argument("--mfma", action="store_true", help="direct term on the matrix cores")
+    ap.add_argument("--packed", action="store_true",
+                    help="packed operands copied straight into LDS (the autotuner may switch)")
+    ap.add_argument("--deep", action="store_true",
+                    help="packed operands, 512-thread blocks, three LDS buffers")
     ap.add_argument("--plain-measurements", type=int, default=64)
     ap.add_argument("--plain-tile", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
@@ -205,7 +211,9 @@ def main():
     acc = g4.G4_ACC_C128 if args.acc == "c128" else g4.G4_ACC_C64_KAHAN
     h = g4.g4_init_slice(cfg(mode=g4.G4_MODE_BATCHED, prod=g4.G4_PROD_F32, g_in=g4.G4_IN_C64,
                              acc=acc, max_batch=B, tile=args.tile,
-                             flags=g4.G4_F_MFMA if args.mfma else 0))
+                             flags=(g4.G4_F_MFMA if args.mfma else 0) |
+                                   (g4.G4_F_PACKED if args.packed else 0) |
+                                   (g4.G4_F_PACKED_DEEP if args.deep else 0)))
     nblk = pool // B
     if not args.no_autotune:
         tune = g4.g4_autotune(h, gu[:B], gd[:B], sg[:B], B, 1e-6)
@@ -242,9 +250,9 @@ def main():
                                  % (E, B, st["batch"], args.acc),
                      "entries": E, "measurements_per_step": B, "pass_batch": st["batch"],
                      "tile": st["tile"], "accumulator": args.acc,
-                     "direct_term": "mfma" if st["variant"] == 1 else "valu",
+                     "kernel_variant": VARIANTS[st["variant"]],
                      "measurements_timed": args.steps * B}
-    out["kernel"] = {"name": "update_mfma_kernel" if st["variant"] == 1 else "update_kernel",
+    out["kernel"] = {"name": KERNELS[st["variant"]],
                      "avg_launch_ms": launch_s * 1e3, "launches": st["timed_launches"]}
     out["roofline"] = roofline(E, ng, st["batch"], 8, 16, w.channels, launch_s) if args.steps else None
     if out["roofline"]:

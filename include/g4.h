@@ -102,8 +102,25 @@ enum {
 enum {
     G4_F_CHECK_FINITE = 1u,   /* g4_accumulate rejects signs that are not finite */
     G4_F_KERNEL_TIMING = 2u,  /* time every slice-update kernel with HIP events (see g4_stats) */
-    G4_F_GRAPH = 4u,          /* replay each batched step as a captured HIP graph */
-    G4_F_MFMA = 8u            /* batched FP32: direct term on MFMA (nw = 64 or 128; 16-row tiles) */
+    /* 4u is reserved */
+    G4_F_MFMA = 8u,           /* batched FP32: direct term on MFMA (nw = 64 or 128; 16-row tiles) */
+    G4_F_PACKED = 16u,        /* batched FP32: each pass first packs G_up and G_dn side by side
+                                 (16 bytes per element, padded rows, with the pass's direct
+                                 vectors) and the update kernel copies its operand blocks
+                                 straight from that buffer into LDS; needs an even tile and
+                                 max_batch * (Ng * ldp * 16 + direct vectors) more device bytes,
+                                 ldp = Ng + 1 rounded up to 8.  Exclusive with G4_F_MFMA. */
+    G4_F_PACKED_DEEP = 32u    /* as G4_F_PACKED, with 512-thread blocks and three LDS buffers
+                                 (copies run two measurements ahead); one or two K2 rows per
+                                 thread, tile = 512/nw or 1024/nw.  Exclusive with the others. */
+};
+
+/* slice-update kernel variants (g4_stats, g4_set_plan, g4_tune_result) */
+enum {
+    G4_VARIANT_VALU = 0,      /* operands staged through registers, all terms on the VALU */
+    G4_VARIANT_MFMA = 1,      /* G4_F_MFMA */
+    G4_VARIANT_PACKED = 2,    /* G4_F_PACKED */
+    G4_VARIANT_PACKED_DEEP = 3  /* G4_F_PACKED_DEEP */
 };
 
 typedef struct g4_config {
@@ -141,7 +158,7 @@ typedef struct g4_stats_t {
     uint32_t channels;         /* channel bitmask */
     int32_t batch;             /* measurements per pass in use */
     int32_t tile;              /* K2 rows per tile in use */
-    int32_t variant;           /* kernel variant in use (0 VALU, 1 MFMA direct) */
+    int32_t variant;           /* kernel variant in use (G4_VARIANT_*) */
 } g4_stats_t;
 
 /* Fill *cfg with defaults (magnetic channel, c128, FP64, plain, whole
@@ -194,16 +211,18 @@ int g4_reset(g4_slice *h);
 /* Current statistics (synchronous: waits for the stream first). */
 int g4_stats(g4_slice *h, g4_stats_t *st);
 
-/* Override the work tile (K2 rows), the pass size (batched mode, at most the
- * allocated max_batch) and the kernel variant: 1 = MFMA direct term, 2 =
- * VALU kernel.  0 keeps the current value.  G4_E_UNSUPPORTED if the
- * combination cannot run for this slice.  Waits for the handle's stream. */
+/* Override the work tile (K2 rows; 0 keeps it, or takes the variant's default
+ * when the variant changes), the pass size (batched mode, at most the
+ * allocated max_batch; 0 keeps it) and the kernel variant (G4_VARIANT_*, -1
+ * keeps it).  Selecting G4_VARIANT_PACKED allocates its buffer on first use
+ * (G4_E_OOM if it does not fit).  G4_E_UNSUPPORTED if the combination cannot
+ * run for this slice.  Waits for the handle's stream. */
 int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant);
 
 typedef struct g4_tune_result {
     int32_t batch;               /* measurements per pass chosen */
     int32_t tile;                /* K2 rows per work tile chosen */
-    int32_t variant;             /* 0 VALU kernel, 1 MFMA direct term */
+    int32_t variant;             /* G4_VARIANT_* */
     int32_t candidates;          /* plans timed (0 when taken from the cache) */
     double ms_per_measurement;   /* pass time per measurement of the chosen plan */
     double rel_err;              /* its relative difference from the first plan tried, on a

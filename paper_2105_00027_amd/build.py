@@ -17,11 +17,13 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "g4")
 LIB = os.path.join(HERE, "libg4.so")
 # (source, object name, extra defines); the update kernel is instantiated once
-# per (kind, K2 rows per thread) pair
+# per (kind, K2 rows per thread) pair, the packed-operand kernel once per K2
+# rows per thread
 SOURCES = [("g4_abi.cpp", "g4_abi", []), ("g4_kernels.hip", "g4_kernels", []),
            ("g4_synth.hip", "g4_synth", []), ("g4_update_mfma.hip", "g4_update_mfma", [])] + [
     ("g4_update_inst.hip", "g4_update_k%d_e%d" % (k, e), ["-DG4_KIND=%d" % k, "-DG4_EPT=%d" % e])
-    for k in (0, 1, 2) for e in (1, 2, 4, 8)]
+    for k in (0, 1, 2) for e in (1, 2, 4, 8)] + [
+    ("g4_update_packed.hip", "g4_update_packed_e%d" % e, ["-DG4_EPT=%d" % e]) for e in (1, 2, 4, 8)]
 ARCH = os.environ.get("G4_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -29,9 +31,20 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(spec, verbose: bool) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True when obj is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(d, f) for d in (CSRC, os.path.join(ROOT, "include"))
+                                        for f in os.listdir(d) if f.endswith((".hpp", ".h"))]
+    return max(os.path.getmtime(f) for f in deps) > os.path.getmtime(obj)
+
+
+def _compile(spec, verbose: bool, incremental: bool = False) -> str:
     src, name, defs = spec
     obj = os.path.join(BUILD, name + ".o")
+    if incremental and not _stale(src, obj):
+        return obj
     cmd = ["hipcc", *COMMON, *DEVICE, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = ["hipcc", *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -48,10 +61,12 @@ def _compile(spec, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those whose object is older than
+    the source or a header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 4, 16, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
@@ -62,4 +77,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -47,7 +47,7 @@ struct Plan {
     Dims d;
     int prec;          // 0 FP64 products, 1 FP32
     int kind;          // update kernel: 0 plain FP64, 1 batched FP64, 2 batched FP32
-    int variant;       // 0 VALU direct term, 1 MFMA direct term
+    int variant;       // 0 VALU kernel, 1 MFMA direct term, 2 packed operands (G4_VARIANT_*)
     int batch;         // measurements per pass
     int mgroup;        // transfer planes per work tile (compile-time bound)
     int tile;          // K2 rows per work tile
@@ -55,7 +55,9 @@ struct Plan {
     int slots;         // direct-vector slots (bit 0 magnetic, bit 1 charge)
     int nslots;
     uint64_t entries;  // per channel
-    uint64_t acc_bytes, dir_bytes, stage_bytes, sign_bytes, scratch_bytes, table_bytes;
+    int ldp;           // packed variant: row pitch of a packed G matrix (16-byte elements)
+    uint64_t pack_stride;   // bytes per measurement of the packed buffer (G + direct vectors)
+    uint64_t acc_bytes, dir_bytes, stage_bytes, sign_bytes, scratch_bytes, table_bytes, pack_bytes;
     uint64_t total_bytes;
     std::vector<int32_t> qlist;
 };
@@ -101,7 +103,7 @@ int validate(const g4_config *c, Plan *p) {
     if (c->prod < G4_PROD_F64 || c->prod > G4_PROD_F16X2) return fail(G4_E_ARG, "prod=%d", c->prod);
     if (c->acc < G4_ACC_C128 || c->acc > G4_ACC_C64) return fail(G4_E_ARG, "acc=%d", c->acc);
     if (c->mode != G4_MODE_PLAIN && c->mode != G4_MODE_BATCHED) return fail(G4_E_ARG, "mode=%d", c->mode);
-    if (c->flags & ~(uint32_t)(G4_F_CHECK_FINITE | G4_F_KERNEL_TIMING | G4_F_GRAPH | G4_F_MFMA))
+    if (c->flags & ~(uint32_t)(G4_F_CHECK_FINITE | G4_F_KERNEL_TIMING | G4_F_MFMA | G4_F_PACKED | G4_F_PACKED_DEEP))
         return fail(G4_E_ARG, "unknown flags 0x%x", c->flags);
     if (c->device < 0) return fail(G4_E_ARG, "device=%d", c->device);
     if (c->mode == G4_MODE_PLAIN) {
@@ -144,7 +146,15 @@ int validate(const g4_config *c, Plan *p) {
     P.mgroup = choose_mgroup(c->nwex);
     const int nch = popcount3(c->channels);
     const int rp = 256 / c->nw;
-    P.variant = (c->flags & G4_F_MFMA) ? 1 : 0;
+    if (popcount3((c->flags >> 3) & 7u) > 1)
+        return fail(G4_E_ARG, "G4_F_MFMA, G4_F_PACKED and G4_F_PACKED_DEEP are exclusive");
+    P.variant = (c->flags & G4_F_MFMA) ? G4_VARIANT_MFMA
+              : (c->flags & G4_F_PACKED) ? G4_VARIANT_PACKED
+              : (c->flags & G4_F_PACKED_DEEP) ? G4_VARIANT_PACKED_DEEP : G4_VARIANT_VALU;
+    const bool packed = P.variant == G4_VARIANT_PACKED || P.variant == G4_VARIANT_PACKED_DEEP;
+    if (packed && P.kind != 2) return fail(G4_E_UNSUPPORTED, "packed operands need batched FP32 products");
+    // K2 rows covered by one sweep of the block's threads
+    const int rp_v = P.variant == G4_VARIANT_PACKED_DEEP ? 512 / c->nw : rp;
     if (P.variant == 1) {
         // MFMA kernel: 16-row tiles, 64-column slabs per wave, register budget
         if (P.kind != 2) return fail(G4_E_UNSUPPORTED, "MFMA direct term needs batched FP32 products");
@@ -158,18 +168,43 @@ int validate(const g4_config *c, Plan *p) {
         P.ept = 0;
         P.tile = 16;
     } else if (c->tile) {
-        if (c->tile % rp || c->tile > c->nw) return fail(G4_E_UNSUPPORTED, "tile=%d: must be a multiple of %d and <= nw", c->tile, rp);
-        const int e = c->tile / rp;
-        if (e != 1 && e != 2 && e != 4 && e != 8) return fail(G4_E_UNSUPPORTED, "tile=%d: tile/%d must be 1, 2, 4 or 8", c->tile, rp);
+        if (c->tile % rp_v || c->tile >= c->nw + rp_v)
+            return fail(G4_E_UNSUPPORTED, "tile=%d: must be a multiple of %d below nw + %d", c->tile, rp_v, rp_v);
+        const int e = c->tile / rp_v;
+        if (e != 1 && e != 2 && e != 4 && e != 8) return fail(G4_E_UNSUPPORTED, "tile=%d: tile/%d must be 1, 2, 4 or 8", c->tile, rp_v);
         P.ept = e;
     } else {
         P.ept = choose_ept(P.prec, nch, P.mgroup, c->nw);
+        if (P.variant == G4_VARIANT_PACKED_DEEP) P.ept = std::min(P.ept, 2);
+        // packed operands move direct vectors in pairs: the default tile is even
+        const int emax = P.variant == G4_VARIANT_PACKED_DEEP ? 2 : 8;
+        while (packed && P.ept < emax && ((P.ept * rp_v) % 2 || std::min(P.ept * rp_v, c->nw) % 2)) P.ept *= 2;
     }
-    if (P.variant == 0) P.tile = P.ept * rp;
+    if (P.variant == G4_VARIANT_PACKED_DEEP && P.ept > 2)
+        return fail(G4_E_UNSUPPORTED, "deep packed blocks take one or two K2 rows per thread (tile=%d)", P.ept * rp_v);
+    if (P.variant != 1) P.tile = P.ept * rp_v;
     if (update_lds_bytes(P.kind, (int)c->channels, P.tile, P.mgroup, d, P.variant) > 160 * 1024)
         return fail(G4_E_UNSUPPORTED, "LDS tile above 160 KiB");
     P.slots = c->channels & 3u;
     P.nslots = popcount3(P.slots);
+    // packed operands: one block per measurement, [G rows of ldp 16-byte
+    // elements | direct vectors a | b]; every copy offset inside it is 32-bit
+    P.ldp = (int)((ng + 1 + 7) / 8 * 8);
+    P.pack_stride = ((uint64_t)ng * P.ldp * 16 + 2ull * P.nslots * d.planes * n * 8 + 255) / 256 * 256;
+    P.pack_bytes = 0;
+    if (packed) {
+        const bool deep = P.variant == G4_VARIANT_PACKED_DEEP;
+        const int T2 = std::min(P.tile, c->nw);
+        const PackedGeom g = packed_geom(c->nw, T2, P.mgroup, (int)c->channels);
+        if (P.tile % 2 || T2 % 2) return fail(G4_E_UNSUPPORTED, "packed operands need an even tile (tile=%d)", P.tile);
+        if (packed_slots(g, deep) > kPackedSlots)
+            return fail(G4_E_UNSUPPORTED, "packed operands: %d staging chunks per tile above %d", g.nbuf,
+                        kPackedSlots * packed_threads(deep));
+        if (P.pack_stride >= (1ull << 31))
+            return fail(G4_E_UNSUPPORTED, "packed operands: %llu bytes per measurement above 2^31",
+                        (unsigned long long)P.pack_stride);
+        P.pack_bytes = (uint64_t)P.batch * P.pack_stride;
+    }
 
     // --- device memory
     const uint64_t el = P.prec == 0 ? 16 : 8;
@@ -183,7 +218,7 @@ int validate(const g4_config *c, Plan *p) {
     const uint64_t nitems_max = (uint64_t)d.planes * nc * nc * ((c->nw + P.tile - 1) / P.tile);
     P.table_bytes = 2ull * nc * nc * 4 + (uint64_t)d.planes * 16 + nitems_max * 16 + (uint64_t)d.planes * 8;
     P.total_bytes = P.acc_bytes * popcount3(c->channels) + P.dir_bytes + P.stage_bytes + P.sign_bytes +
-                    P.scratch_bytes + P.table_bytes;
+                    P.scratch_bytes + P.table_bytes + P.pack_bytes;
     return G4_OK;
 }
 
@@ -300,11 +335,13 @@ struct g4_slice {
     int32_t *kadd = nullptr, *ksub = nullptr;
     int4 *groups = nullptr, *items = nullptr;
     int2 *plane_qm = nullptr;
+    int32_t *qpos = nullptr;
     int ngroups = 0, nitems = 0;
     size_t items_cap = 0;
     int order = 2;          // tile order (see build_work); G4_TILE_ORDER overrides
     void *dir = nullptr;
     void *stage = nullptr;
+    void *pack = nullptr;        // packed variant, max_batch blocks of P.pack_stride bytes
     double *sign_dev = nullptr;
     double *sign_host = nullptr;     // pinned
     hipEvent_t sign_ev[kSignSlots] = {};
@@ -355,12 +392,36 @@ void release(g4_slice *h) {
     for (int i = 0; i < kSignSlots; ++i)
         if (h->sign_ev[i]) (void)hipEventDestroy(h->sign_ev[i]);
     for (void *p : {(void *)h->acc[0], (void *)h->acc[1], (void *)h->acc[2], (void *)h->kadd,
-                    (void *)h->ksub, (void *)h->groups, (void *)h->items, (void *)h->plane_qm,
-                    h->dir, h->stage, (void *)h->sign_dev, (void *)h->scratch})
+                    (void *)h->ksub, (void *)h->groups, (void *)h->items, (void *)h->plane_qm, (void *)h->qpos,
+                    h->dir, h->stage, h->pack, (void *)h->sign_dev, (void *)h->scratch})
         if (p) (void)hipFree(p);
     if (h->sign_host) (void)hipHostFree(h->sign_host);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
+}
+
+uint32_t with_variant(uint32_t flags, int variant) {
+    flags &= ~(uint32_t)(G4_F_MFMA | G4_F_PACKED | G4_F_PACKED_DEEP);
+    if (variant == G4_VARIANT_MFMA) flags |= G4_F_MFMA;
+    if (variant == G4_VARIANT_PACKED) flags |= G4_F_PACKED;
+    if (variant == G4_VARIANT_PACKED_DEEP) flags |= G4_F_PACKED_DEEP;
+    return flags;
+}
+
+// The packed buffer is allocated when a plan that uses it is first installed.
+int ensure_pack(g4_slice *h, const Plan &P) {
+    if (P.pack_bytes == 0 || h->pack) return G4_OK;
+    hipError_t e = hipMalloc(&h->pack, P.pack_bytes);
+    if (e != hipSuccess) {
+        h->pack = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? G4_E_OOM : G4_E_HIP, "packed buffer of %llu bytes: %s",
+                    (unsigned long long)P.pack_bytes, hipGetErrorString(e));
+    }
+    h->P.ldp = P.ldp;
+    h->P.pack_stride = P.pack_stride;
+    h->P.pack_bytes = P.pack_bytes;
+    return G4_OK;
 }
 
 int fold_timings(g4_slice *h) {
@@ -394,6 +455,7 @@ Tables tables_of(const g4_slice *h) {
     t.groups = h->groups;
     t.items = h->items;
     t.plane_qm = h->plane_qm;
+    t.qpos = h->qpos;
     return t;
 }
 
@@ -444,23 +506,41 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
         pd = sd;
     }
     const size_t el = P.prec == 0 ? 16 : 8;
-    const int64_t dir_slot = (int64_t)P.batch * P.d.planes * P.d.n;
+    const int64_t pn = (int64_t)P.d.planes * P.d.n;
+    // direct vectors: [slot][b][p][K] in their own buffer, or, for packed
+    // operands, inside each measurement's packed block after its G rows
+    const bool packed = P.variant == G4_VARIANT_PACKED || P.variant == G4_VARIANT_PACKED_DEEP;
+    int64_t dir_slot = (int64_t)P.batch * pn, dir_bstride = pn;
     void *dir_a = h->dir;
-    void *dir_b = static_cast<char *>(h->dir) + (size_t)P.nslots * dir_slot * el;
-    if (P.slots) {
-        GatherArgs ga;
-        ga.gu = pu;
-        ga.gd = pd;
-        ga.g_stride = per;
-        ga.dir_a = dir_a;
-        ga.dir_b = dir_b;
-        ga.dir_slot_stride = dir_slot;
-        ga.sign = ds;
-        ga.batch = nb;
-        ga.slots = P.slots;
-        ga.d = P.d;
-        ga.t = tables_of(h);
-        // the per-pass layout is [slot][b][p][K] with b < nb; slot stride covers max batch
+    if (packed) {
+        if (!h->pack) return fail(G4_E_STATE, "packed operands selected without a packed buffer");
+        dir_slot = pn;
+        dir_bstride = (int64_t)(P.pack_stride / 8);
+        dir_a = static_cast<char *>(h->pack) + (size_t)P.d.ng * P.ldp * 16;
+    }
+    void *dir_b = static_cast<char *>(dir_a) + (size_t)P.nslots * dir_slot * el;
+    GatherArgs ga;
+    ga.gu = pu;
+    ga.gd = pd;
+    ga.g_stride = per;
+    ga.dir_a = dir_a;
+    ga.dir_b = dir_b;
+    ga.dir_slot_stride = dir_slot;
+    ga.dir_b_stride = dir_bstride;
+    ga.sign = ds;
+    ga.batch = nb;
+    ga.slots = P.slots;
+    ga.d = P.d;
+    ga.t = tables_of(h);
+    if (packed) {
+        // one pass over G: packed copy plus the direct vectors
+        PackArgs pa;
+        pa.g = ga;
+        pa.pack = h->pack;
+        pa.pack_stride16 = (int64_t)(P.pack_stride / 16);
+        pa.ldp = P.ldp;
+        G4_HIP(h, launch_pack_gather(pa, h->stream));
+    } else if (P.slots) {
         G4_HIP(h, launch_gather(P.prec, ga, h->stream));
     }
     UpdateArgs ua;
@@ -470,6 +550,11 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
     ua.dir_a = dir_a;
     ua.dir_b = dir_b;
     ua.dir_slot_stride = dir_slot;
+    ua.dir_b_stride = dir_bstride;
+    ua.pack = packed ? h->pack : nullptr;
+    ua.pack_stride = (int64_t)P.pack_stride;
+    ua.ldp = P.ldp;
+    ua.nitems = h->nitems;
     ua.sign = ds;
     ua.batch = nb;
     ua.acc[0] = h->acc[0];
@@ -590,9 +675,11 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     G4_INIT(hipMalloc(&h->kadd, (size_t)nc * nc * 4));
     G4_INIT(hipMalloc(&h->ksub, (size_t)nc * nc * 4));
     G4_INIT(hipMalloc(&h->plane_qm, (size_t)P.d.planes * sizeof(int2)));
+    G4_INIT(hipMalloc(&h->qpos, (size_t)nc * 4));
     G4_INIT(hipMalloc(&h->groups, (size_t)P.d.planes * sizeof(int4)));
     if (P.dir_bytes) G4_INIT(hipMalloc(&h->dir, P.dir_bytes));
     if (P.stage_bytes) G4_INIT(hipMalloc(&h->stage, P.stage_bytes));
+    if (P.pack_bytes) G4_INIT(hipMalloc(&h->pack, P.pack_bytes));
     G4_INIT(hipMalloc(&h->sign_dev, P.sign_bytes));
     G4_INIT(hipHostMalloc(&h->sign_host, P.sign_bytes, hipHostMallocDefault));
     for (int i = 0; i < kSignSlots; ++i) G4_INIT(hipEventCreateWithFlags(&h->sign_ev[i], hipEventDisableTiming));
@@ -604,6 +691,9 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     G4_INIT(hipMemcpyAsync(h->kadd, kadd.data(), kadd.size() * 4, hipMemcpyHostToDevice, h->stream));
     G4_INIT(hipMemcpyAsync(h->ksub, ksub.data(), ksub.size() * 4, hipMemcpyHostToDevice, h->stream));
     G4_INIT(hipMemcpyAsync(h->plane_qm, pq.data(), pq.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
+    std::vector<int32_t> qpos(nc, -1);
+    for (size_t i = 0; i < P.qlist.size(); ++i) qpos[(size_t)P.qlist[i]] = (int32_t)i;
+    G4_INIT(hipMemcpyAsync(h->qpos, qpos.data(), qpos.size() * 4, hipMemcpyHostToDevice, h->stream));
     for (int c = 0; c < 3; ++c)
         if (h->acc[c]) G4_INIT(launch_fill_zero(h->acc[c], ab, h->stream));
     G4_INIT(hipStreamSynchronize(h->stream));
@@ -734,15 +824,16 @@ int g4_stats(g4_slice *h, g4_stats_t *st) {
 int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     int rc = usable(h);
     if (rc) return rc;
-    if (tile < 0 || batch < 0 || variant < 0 || variant > 2) return fail(G4_E_ARG, "bad plan value");
+    if (tile < 0 || batch < 0 || variant < -1 || variant > G4_VARIANT_PACKED_DEEP) return fail(G4_E_ARG, "bad plan value");
     if (batch > 0 && (h->cfg.mode == G4_MODE_PLAIN ? batch != 1 : batch > h->cfg.max_batch))
         return fail(G4_E_UNSUPPORTED, "batch %d above the allocated max_batch", batch);
     g4_config c = h->cfg;
     std::vector<int32_t> ql = h->P.qlist;
     c.q_list = ql.data();
-    if (variant == 1) c.flags |= G4_F_MFMA;
-    if (variant == 2) c.flags &= ~(uint32_t)G4_F_MFMA;   // 2: back to the VALU kernel
-    if (variant) c.tile = 0;
+    if (variant >= 0) {
+        c.flags = with_variant(c.flags, variant);
+        if (variant != h->P.variant) c.tile = 0;
+    }
     if (tile) c.tile = tile;
     Plan P;
     rc = validate(&c, &P);
@@ -750,6 +841,8 @@ int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     // the workspaces were sized for max_batch; only the pass size changes
     G4_HIP(h, hipSetDevice(h->device));
     G4_HIP(h, hipStreamSynchronize(h->stream));
+    rc = ensure_pack(h, P);
+    if (rc) return rc;
     const int keep_batch = h->P.batch;
     h->P.ept = P.ept;
     h->P.tile = P.tile;
@@ -759,6 +852,8 @@ int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     h->cfg.flags = c.flags;
     return rebuild_work(h);
 }
+
+}  // extern "C"
 
 // ---- autotuner -----------------------------------------------------------
 namespace {
@@ -821,6 +916,8 @@ std::string tune_key(g4_slice *h) {
 
 }  // namespace
 
+extern "C" {
+
 int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *sign, int32_t batch,
                 double tol, g4_tune_result *out) {
     int rc = usable(h);
@@ -855,11 +952,11 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
             if (b >= 4 || b == maxb) bs.push_back(b);
         if (bs.empty() || bs.back() != maxb) bs.push_back(maxb);
         const int rp = 256 / h->cfg.nw;
-        for (int v = 0; v < 2; ++v)
+        for (int v = 0; v <= G4_VARIANT_PACKED_DEEP; ++v)
             for (int b : bs)
                 for (int e : {1, 2, 4}) {
-                    if (v == 1 && e > 1) continue;
-                    cands.push_back({b, v == 1 ? 16 : e * rp, v});
+                    if ((v == 1 && e > 1) || (v == 3 && e > 2)) continue;
+                    cands.push_back({b, v == 1 ? 16 : e * (v == 3 ? 512 / h->cfg.nw : rp), v});
                 }
     }
     std::vector<double> ref, cur;
@@ -877,10 +974,11 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
         g4_config cc = keep_cfg;
         std::vector<int32_t> ql = keep.qlist;
         cc.q_list = ql.data();
-        cc.flags = c.variant ? (cc.flags | G4_F_MFMA) : (cc.flags & ~(uint32_t)G4_F_MFMA);
+        cc.flags = with_variant(cc.flags, c.variant);
         cc.tile = c.tile;
         Plan P;
         if (validate(&cc, &P) != G4_OK) continue;          // does not fit this slice
+        if (ensure_pack(h, P) != G4_OK) continue;           // no room for the packed buffer
         h->P.ept = P.ept;
         h->P.tile = P.tile;
         h->P.variant = P.variant;
@@ -913,10 +1011,12 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
     g4_config cc = keep_cfg;
     std::vector<int32_t> ql = keep.qlist;
     cc.q_list = ql.data();
-    cc.flags = best_c.variant ? (cc.flags | G4_F_MFMA) : (cc.flags & ~(uint32_t)G4_F_MFMA);
+    cc.flags = with_variant(cc.flags, best_c.variant);
     cc.tile = best_c.tile;
     Plan P;
     rc = validate(&cc, &P);
+    if (rc) return rc;
+    rc = ensure_pack(h, P);
     if (rc) return rc;
     h->P.ept = P.ept;
     h->P.tile = P.tile;

@@ -31,6 +31,7 @@ struct Tables {
     const int4 *groups;    // {q, m_lo, count, p0}
     const int4 *items;     // {group, k1, k2, c0}
     const int2 *plane_qm;  // per slice plane {q, m}
+    const int32_t *qpos;   // qpos[q] = position of momentum q in the transfer list, or -1
 };
 
 enum AccKind { ACC_C128 = 0, ACC_C64_KAHAN = 1, ACC_C64 = 2 };
@@ -42,17 +43,65 @@ struct UpdateArgs {
     const void *gu;           // batch of Ng x Ng matrices, spin up
     const void *gd;           // spin down
     int64_t g_stride;         // elements between consecutive matrices
-    const void *dir_a;        // direct vectors a[slot][b][p][K] (sign folded), slot 0 mag, 1 charge
-    const void *dir_b;        // direct vectors b[slot][b][p][K]
+    const void *dir_a;        // direct vectors a(slot, b, p, K) (sign folded), slot 0 mag, 1 charge
+    const void *dir_b;        // direct vectors b(slot, b, p, K)
     int64_t dir_slot_stride;  // elements between slots
+    int64_t dir_b_stride;     // elements between measurements (p, K contiguous: p*n + K)
     const double *sign;       // device, per measurement of this pass
     int batch;                // measurements in this pass
     void *acc[3];             // accumulators: magnetic, charge, pp (NULL if absent)
     int acc_kind;             // AccKind
     int tile;                 // K2 rows per work tile
+    const void *pack;         // packed variant: spin-interleaved G of the pass (pack_kernel)
+    int64_t pack_stride;      // bytes between consecutive packed matrices
+    int ldp;                  // row pitch of a packed matrix, in 16-byte elements
+    int nitems;               // work tiles in the list (one block per tile)
     Dims d;
     Tables t;
 };
+
+// LDS geometry of one staging buffer of the packed-operand kernel, in 16-byte
+// chunks (one chunk = one G element with both spins, or two direct-vector
+// values).  Exchange block rows are padded to an odd pitch so that lanes
+// walking K1 (one row apart) fall in distinct banks.
+struct PackedGeom {
+    int ycs;        // exchange-block row pitch
+    int nY, nZ, nX; // exchange block, PP block, G(K2,K1) rows
+    int nG;         // nY + nZ + nX
+    int nA, nB;     // direct vectors a (planes x nw) and b (planes x T2), chunks
+    int nbuf;       // chunks per buffer
+};
+__host__ __device__ inline PackedGeom packed_geom(int nw, int T2, int M, int channels) {
+    PackedGeom g;
+    const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
+    const int yc = T2 + M - 1;
+    g.ycs = yc | 1;
+    g.nY = nph ? (nw + M - 1) * g.ycs : 0;
+    g.nZ = (channels & CH_PP) ? (T2 + M - 1) * (nw + M - 1) : 0;
+    g.nX = T2 * nw;
+    g.nG = g.nY + g.nZ + g.nX;
+    g.nA = nph * M * nw / 2;
+    g.nB = nph * M * T2 / 2;
+    g.nbuf = g.nG + g.nA + g.nB;
+    return g;
+}
+// per-thread staging slots of the packed kernel (256 threads, one chunk each)
+constexpr int kPackedSlots = 16;
+// measurements per pass at most (the packed kernel keeps the pass's weights in LDS)
+constexpr int kMaxPassBatch = 256;
+// Block shape of the packed kernel: threads and staging buffers (deep: 512
+// threads, three buffers, for one or two K2 rows per thread; else 256, two).
+inline int packed_threads(bool deep) { return deep ? 512 : 256; }
+inline int packed_buffers(bool deep) { return deep ? 3 : 2; }
+// Copy instructions per wave and measurement, covering a full tile.
+inline int packed_slots(const PackedGeom &g, bool deep) {
+    return (g.nbuf + packed_threads(deep) - 1) / packed_threads(deep);
+}
+// LDS bytes of the packed kernel: the buffers (a whole number of copy rounds
+// each) and the pass's weights.
+inline size_t packed_lds_bytes(const PackedGeom &g, bool deep) {
+    return (size_t)packed_buffers(deep) * packed_slots(g, deep) * packed_threads(deep) * 16 + kMaxPassBatch * 4;
+}
 
 // Arguments of the direct-vector gather.
 struct GatherArgs {
@@ -60,6 +109,7 @@ struct GatherArgs {
     int64_t g_stride;
     void *dir_a, *dir_b;
     int64_t dir_slot_stride;
+    int64_t dir_b_stride;
     const double *sign;
     int batch;
     int slots;          // bit 0: magnetic (G_up - G_dn), bit 1: charge (G_up + G_dn)
@@ -71,10 +121,24 @@ struct GatherArgs {
 // Update `kind` 0 = plain FP64 (one measurement per pass), 1 = batched FP64,
 // 2 = batched FP32.
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
-// `variant` 0 = VALU kernel, 1 = MFMA direct term (kind 2, tile 16, nw % 64 == 0).
+// `variant` 0 = VALU kernel, 1 = MFMA direct term (kind 2, tile 16, nw % 64 == 0),
+// 2 = packed operands staged straight into LDS (kind 2, even tile).
 hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems, int variant,
                          const UpdateArgs &a, hipStream_t s);
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant);
+// Packing of one pass for the packed-operand kernel, with the direct vectors
+// built on the way: every element (b, r, c) of the pass's complex64 G pairs
+// goes to pack[b*pack_stride16 + r*ldp + c] = {Re up, Im up, Re dn, Im dn}
+// (16-byte units; row pitch ldp >= ng + 1, padding columns written with
+// zeros), and the elements that are direct-term operands are also written,
+// combined over the spins, to the direct vectors of GatherArgs layout.
+struct PackArgs {
+    GatherArgs g;            // source G, direct-vector layout, weights, slots, shapes, tables
+    void *pack;
+    int64_t pack_stride16;   // 16-byte elements between consecutive packed matrices
+    int ldp;
+};
+hipError_t launch_pack_gather(const PackArgs &a, hipStream_t s);
 hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s);
 // Readback / load between the documented [plane][K2][K1] order (c128, dst/src)
 // and the tile-contiguous device layout of the accumulators.

@@ -17,8 +17,9 @@ template <> struct Cx<double> { using V = double2; };
 template <> struct Cx<float> { using V = float2; };
 
 // ---------------------------------------------------------------------------
-// Direct-term vectors.  Layout [slot][b][p][K]; slot 0 = magnetic (G_up - G_dn),
-// slot 1 = charge (G_up + G_dn), present when the slot bit is set.
+// Direct-term vectors: element (slot, b, p, K) at slot*dir_slot_stride +
+// b*dir_b_stride + p*n + K; slot 0 = magnetic (G_up - G_dn), slot 1 = charge
+// (G_up + G_dn), present when the slot bit is set.
 template <typename R>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     using V = typename Cx<R>::V;
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
         const R s = (R)a.sign[b];
         V *da = static_cast<V *>(a.dir_a);
         V *db = static_cast<V *>(a.dir_b);
-        int64_t o = idx;
+        int64_t o = (int64_t)b * a.dir_b_stride + (int64_t)p * n + K;
         if (a.slots & 1) {
             da[o] = V{s * (au.x - ad.x), s * (au.y - ad.y)};
             db[o] = V{bu.x - bd.x, bu.y - bd.y};
@@ -53,6 +54,60 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
             da[o] = V{s * (au.x + ad.x), s * (au.y + ad.y)};
             db[o] = V{bu.x + bd.x, bu.y + bd.y};
         }
+    }
+}
+
+// Packing of one pass for the packed-operand kernel (see PackArgs).  Block
+// (row, b) handles row `row` of matrix b.  Element (R, C) of G lies in block
+// (kr, kc) = (R / nwg, C / nwg) at local (lr, lc); it is
+//   a direct-term operand a_b(Q,K) = s_b D(K+Q, K) when lc < nw and
+//   m = lr - lc is a bosonic index: K = kc*nw + lc, q = kr - kc;
+//   a direct-term operand b_b(Q,K) = D(K, K+Q) when lr < nw and
+//   m = lc - lr is a bosonic index: K = kr*nw + lr, q = kc - kr;
+// for the plane (q, m) when it lies in the slice.  Each (plane, K) pair is hit
+// exactly once for a and once for b.
+__global__ __launch_bounds__(256) void pack_gather_kernel(PackArgs pa) {
+    const GatherArgs &a = pa.g;
+    const int64_t b = blockIdx.y, row = blockIdx.x;
+    const int ng = a.d.ng, nwg = a.d.nwg, nw = a.d.nw, nwex = a.d.nwex, nc = a.d.nc, n = a.d.n;
+    const float2 *su = static_cast<const float2 *>(a.gu) + b * a.g_stride + row * ng;
+    const float2 *sd = static_cast<const float2 *>(a.gd) + b * a.g_stride + row * ng;
+    float4 *d = static_cast<float4 *>(pa.pack) + b * pa.pack_stride16 + row * pa.ldp;
+    const int kr = (int)row / nwg, lr = (int)row - kr * nwg;
+    const float s = (float)a.sign[b];
+    float2 *da = static_cast<float2 *>(a.dir_a) + b * a.dir_b_stride;
+    float2 *db = static_cast<float2 *>(a.dir_b) + b * a.dir_b_stride;
+    for (int c = threadIdx.x; c < pa.ldp; c += 256) {
+        float4 v{0.f, 0.f, 0.f, 0.f};
+        if (c < ng) {
+            const float2 u = su[c], w = sd[c];
+            v = float4{u.x, u.y, w.x, w.y};
+            if (a.slots) {
+                const int kc = c / nwg, lc = c - kc * nwg;
+                const float2 dm{u.x - w.x, u.y - w.y}, dp{u.x + w.x, u.y + w.y};
+                // kind 0: operand a (row block holds K+Q), kind 1: operand b
+                for (int kind = 0; kind < 2; ++kind) {
+                    const int i = kind == 0 ? lc : lr;
+                    const int m = kind == 0 ? lr - lc : lc - lr;
+                    if (i >= nw || m < 0 || m >= nwex) continue;
+                    const int kk = kind == 0 ? kc : kr;               // momentum of K
+                    const int q = kind == 0 ? a.t.ksub[kr * nc + kc] : a.t.ksub[kc * nc + kr];
+                    const int iq = a.t.qpos[q];
+                    if (iq < 0) continue;
+                    const int64_t p = (int64_t)iq * nwex + m - a.d.q_begin;
+                    if (p < 0 || p >= a.d.planes) continue;
+                    int64_t o = p * n + (int64_t)kk * nw + i;
+                    float2 *dst = kind == 0 ? da : db;
+                    const float f = kind == 0 ? s : 1.f;
+                    if (a.slots & 1) {
+                        dst[o] = float2{f * dm.x, f * dm.y};
+                        o += a.dir_slot_stride;
+                    }
+                    if (a.slots & 2) dst[o] = float2{f * dp.x, f * dp.y};
+                }
+            }
+        }
+        d[c] = v;
     }
 }
 
@@ -137,8 +192,17 @@ G4_DECL_KIND(0) G4_DECL_KIND(1) G4_DECL_KIND(2)
 
 hipError_t launch_update_mfma(int channels, int slabs, int mgroup, int nitems, size_t lds,
                               const UpdateArgs &a, hipStream_t s);
+#define G4_PDECL(e)                                                                            \
+    hipError_t launch_update_packed_e##e(int channels, int mgroup, int nitems, size_t lds,    \
+                                         const UpdateArgs &a, hipStream_t s, bool deep);
+G4_PDECL(1) G4_PDECL(2) G4_PDECL(4) G4_PDECL(8)
+#undef G4_PDECL
 
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant) {
+    if (variant == 2 || variant == 3) {
+        // staging buffers of 16-byte chunks, rotating by measurement
+        return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels), variant == 3);
+    }
     // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct
     // vectors (two copies, by measurement parity, for the MFMA variant)
     const size_t el = kind == 2 ? sizeof(float2) : sizeof(double2);
@@ -170,6 +234,17 @@ hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems
         if (kind != 2 || a.tile != 16 || a.d.nw % 64) return hipErrorInvalidValue;
         return launch_update_mfma(channels, a.d.nw / 64, mgroup, nitems, lds, a, s);
     }
+    if (variant == 2 || variant == 3) {
+        if (kind != 2 || !a.pack) return hipErrorInvalidValue;
+        const bool deep = variant == 3;
+        switch (ept) {
+            case 1: return launch_update_packed_e1(channels, mgroup, nitems, lds, a, s, deep);
+            case 2: return launch_update_packed_e2(channels, mgroup, nitems, lds, a, s, deep);
+            case 4: return launch_update_packed_e4(channels, mgroup, nitems, lds, a, s, deep);
+            case 8: return launch_update_packed_e8(channels, mgroup, nitems, lds, a, s, deep);
+            default: return hipErrorInvalidValue;
+        }
+    }
 #define G4_K(k)                                                                     \
     case k * 16 + 1: return launch_update_k##k##_e1(channels, mgroup, nitems, lds, a, s); \
     case k * 16 + 2: return launch_update_k##k##_e2(channels, mgroup, nitems, lds, a, s); \
@@ -180,6 +255,14 @@ hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems
         default: return hipErrorInvalidValue;
     }
 #undef G4_K
+}
+
+hipError_t launch_pack_gather(const PackArgs &a, hipStream_t s) {
+    const int count = a.g.batch, ng = a.g.d.ng;
+    if (count == 0) return hipSuccess;
+    if (a.ldp < ng + 1 || a.pack_stride16 < (int64_t)ng * a.ldp || count > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pack_gather_kernel, dim3(ng, count), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s) {

@@ -227,7 +227,7 @@ struct Tile {
         colX = k1 * nwg;
         dA = static_cast<const V *>(a.dir_a);
         dB = static_cast<const V *>(a.dir_b);
-        vstride = (int64_t)planes * n;
+        vstride = a.dir_b_stride;
         dir_slot = (int)a.dir_slot_stride;
         static_for<0, NSG>([&](auto k) {
             const int e = tid + k * NT;

@@ -1,0 +1,309 @@
+// Slice-update kernel with packed operands (batched FP32), for gfx950.
+// Compiled once per G4_EPT (K2 rows per thread), for every channel
+// combination and plane-group bound.
+//
+// Same arithmetic, work tiles, thread mapping and accumulator epilogue as the
+// batched FP32 VALU kernel in g4_update.hpp; what differs is how a tile's
+// operands reach LDS.  Before the pass, pack_kernel rewrites the pass's G
+// matrices as one array of 16-byte elements {Re G_up, Im G_up, Re G_dn, Im G_dn}
+// with a padded row pitch.  Every operand a tile needs per measurement is then
+// a set of contiguous row runs of that array (the exchange block, the PP block,
+// the G(K2,K1) rows) or of the direct-vector buffer, and each 16-byte chunk is
+// moved by global_load_lds_dwordx4 straight from memory into LDS: no register
+// round trip, no LDS store instructions.  Two LDS buffers alternate by
+// measurement parity, so the copies for measurement b+1 are in flight while
+// measurement b is computed.
+//
+// LDS buffer (16-byte chunks, PackedGeom):
+//   Y  exchange block G(k1+q rows, k2+q columns), row-major, odd row pitch:
+//      lanes walk K1 down a column, one pitch apart, in distinct banks;
+//   Z  PP block G(q-k2 rows, q-k1 columns), row-major (lanes read a
+//      descending run of one row);
+//   X  G(K2, K1) rows of the tile, row-major (lanes read a row);
+//   A  a(Q, K1) per PH channel and plane, Bv b(Q, K2) per channel, plane, row
+//      (complex64 pairs).
+#include "g4_update.hpp"
+
+#if !defined(G4_EPT)
+#error "G4_EPT must be defined"
+#endif
+
+namespace g4 {
+namespace upd {
+namespace {
+
+typedef __attribute__((address_space(3))) unsigned char lds_t;
+
+// global -> LDS, 16 bytes per lane: lane l copies base + off to LDS byte
+// address lds + 16*l (base and lds wave-uniform).  Issued as inline assembly so
+// that the compiler does not make LDS reads of the other buffer wait for these
+// copies; the kernel waits for them itself (s_waitcnt before the barrier that
+// publishes the buffer).  M0 carries the LDS address; one wait state separates
+// its write from the copy.
+__device__ __forceinline__ void dma16(const char *base, unsigned off, unsigned lds) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :
+                 : "v"(off), "s"(base), "s"(lds)
+                 : "memory", "m0");
+}
+
+// Wait until at most n vector-memory operations of this wave are outstanding.
+__device__ __forceinline__ void wait_vm(int n) {
+    switch (n) {
+#define G4_W(k) case k: asm volatile("s_waitcnt vmcnt(" #k ")" ::: "memory"); break;
+        G4_W(1) G4_W(2) G4_W(3) G4_W(4) G4_W(5) G4_W(6) G4_W(7) G4_W(8)
+        G4_W(9) G4_W(10) G4_W(11) G4_W(12) G4_W(13) G4_W(14) G4_W(15) G4_W(16)
+#undef G4_W
+        default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    }
+}
+
+// NTH threads per block, NB staging buffers (copies run NB-1 measurements
+// ahead).  Every wave issues the same number S of copy instructions per
+// measurement (lanes past the tile's chunks copy the block's first chunk into
+// the buffer's padding), and loads complete in issue order, so waiting until
+// S*(copies issued after measurement b's) are outstanding means b's copies
+// have landed.
+template <int EPT, int MG, int CH, int NTH, int NB>
+__global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
+    using V = float2;
+    using CI = ChanInfo<CH>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
+
+    // the pass's weights as floats after the NB buffers (sized for a full
+    // tile); the measurement loop then has no memory read of its own that the
+    // compiler would wait for (and with it for the copies in flight)
+    const int S_full = (packed_geom(nw, min(a.tile, nw), MG, CH).nbuf + NTH - 1) / NTH;
+    float *sg = reinterpret_cast<float *>(smem_raw + NB * S_full * NTH * 16);
+    if (tid < a.batch) sg[tid] = (float)a.sign[tid];
+
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        __syncthreads();   // a previous tile's LDS reads are done (the launch uses one block per tile)
+        // ---- decode the tile -------------------------------------------------
+        const int4 it = a.t.items[item];
+        const int4 gr = a.t.groups[it.x];
+        const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
+        const int k1 = it.y, k2 = it.z, c0 = it.w;
+        const int T2 = min(a.tile, nw - c0);
+        const PackedGeom pg = packed_geom(nw, T2, M, CH);
+        const int zc = nw + M - 1;
+
+        // ---- per-thread copy slots ---------------------------------------------
+        // Chunk e = k*NTH + tid of the buffer [Y | Z | X | A | Bv] comes from byte
+        // offset off[k] of the measurement's packed block (its G matrix followed by
+        // its direct vectors, see pack_gather_kernel); chunks past the tile's end
+        // take offset 0 and land in the padding.  S slots cover a full tile.
+        const int S = (packed_geom(nw, min(a.tile, nw), MG, CH).nbuf + NTH - 1) / NTH;
+        const int ldp = a.ldp;
+        const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
+        const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
+        const int rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
+        const int colZ = CI::pp ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
+        const int rowX = k2 * nwg + c0, colX = k1 * nwg;
+        const int64_t dslot = a.dir_slot_stride;                 // complex64 values
+        const int64_t adelta = static_cast<const char *>(a.dir_a) - static_cast<const char *>(a.pack);
+        const int64_t bdelta = static_cast<const char *>(a.dir_b) - static_cast<const char *>(a.pack);
+        unsigned off[kPackedSlots];
+        static_for<0, kPackedSlots>([&](auto k) {
+            const int e = k * NTH + tid;
+            int64_t o = 0;
+            if (e < pg.nY) {
+                const int r = e / pg.ycs, c = e - r * pg.ycs;
+                o = ((int64_t)(rowY + r) * ldp + colY + c) * 16;
+            } else if (e < pg.nY + pg.nZ) {
+                const int f = e - pg.nY;
+                const int r = f / zc, c = f - r * zc;
+                o = ((int64_t)(rowZ + r) * ldp + colZ + c) * 16;
+            } else if (e < pg.nG) {
+                const int f = e - pg.nY - pg.nZ;
+                const int r = f / nw, c = f - r * nw;
+                o = ((int64_t)(rowX + r) * ldp + colX + c) * 16;
+            } else if (e < pg.nG + pg.nA) {
+                const int f = e - pg.nG, hw = nw / 2;
+                const int sm = f / hw, cc = f - sm * hw;
+                const int sl = sm / M, m = sm - sl * M;
+                o = adelta + (sl * dslot + (int64_t)(p0 + m) * n + k1 * nw + 2 * cc) * 8;
+            } else if (e < pg.nbuf) {
+                const int f = e - pg.nG - pg.nA, ht = T2 / 2;
+                const int sm = f / ht, cc = f - sm * ht;
+                const int sl = sm / M, m = sm - sl * M;
+                o = bdelta + (sl * dslot + (int64_t)(p0 + m) * n + k2 * nw + c0 + 2 * cc) * 8;
+            }
+            off[k] = (unsigned)o;
+        });
+        const int bufb = S * NTH * 16;   // bytes per buffer
+        const unsigned lds_base = (unsigned)(uintptr_t)(lds_t *)smem_raw;
+        const unsigned lds0 = lds_base + wave * 64 * 16;
+        auto issue = [&](int b) __attribute__((always_inline)) {
+            const char *base = static_cast<const char *>(a.pack) + (int64_t)b * a.pack_stride;
+            const unsigned buf = lds0 + (b % NB) * bufb;
+            static_for<0, kPackedSlots>([&](auto k) {
+                if (k < S) dma16(base, off[k], buf + k * NTH * 16);
+            });
+        };
+
+        // ---- accumulation ----------------------------------------------------
+        const int RP = NTH / nw;
+        const bool act = tid < RP * nw;
+        const int i1 = tid % nw;
+        const int r0 = tid / nw;
+        V acc[CI::count][EPT][MG];
+        static_for<0, CI::count>([&](auto c) {
+            static_for<0, EPT>([&](auto j) {
+                static_for<0, MG>([&](auto m) { acc[c][j][m] = V{0.f, 0.f}; });
+            });
+        });
+        const bool full = (T2 == a.tile) && (M == MG);
+        for (int b = 0; b < NB - 1 && b < a.batch; ++b) issue(b);
+        for (int b = 0; b < a.batch; ++b) {
+            // copies issued after b's: those of b+1 .. b+NB-2 that exist
+            wait_vm(S * (min(b + NB - 2, a.batch - 1) - b));
+            __syncthreads();                 // b's copies landed everywhere; b-1's buffer is free
+            if (b + NB - 1 < a.batch) issue(b + NB - 1);
+            if (!act) continue;
+            const float s = sg[b];
+            const float4 *L = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
+            const float4 *Ly = L, *Lz = L + pg.nY, *Lx = L + pg.nY + pg.nZ;
+            const V *At = reinterpret_cast<const V *>(L + pg.nG);
+            const V *Bt = At + 2 * pg.nA;
+            // G(K2,K1) times -s_b for the PH exchange (its minus folded in), +s_b for PP
+            V xu[EPT], xd[EPT];
+            static_for<0, EPT>([&](auto j) {
+                const float4 x = Lx[min(r0 + j * RP, T2 - 1) * nw + i1];
+                const float f = CI::ph ? -s : s;
+                xu[j] = V{x.x * f, x.y * f};
+                xd[j] = V{x.z * f, x.w * f};
+            });
+            // The plane loop is software-pipelined by hand: the LDS operands of
+            // plane m+1 are read into registers before the arithmetic of plane m,
+            // so the LDS latency is covered by that arithmetic even at two
+            // resident blocks per CU.  Partial tiles clamp the reads (in bounds)
+            // and skip the arithmetic of absent entries.
+            struct Ops {
+                float4 y[EPT], z[EPT];
+                V a[CI::nph > 0 ? CI::nph : 1], bb[CI::nph > 0 ? CI::nph : 1][EPT];
+            };
+            auto run = [&](auto FULL) __attribute__((always_inline)) {
+                constexpr bool F = decltype(FULL)::value;
+                auto load = [&](int m, Ops &o) __attribute__((always_inline)) {
+                    const int mm = F ? m : min(m, M - 1);
+                    static_for<0, EPT>([&](auto j) {
+                        const int i2l = F ? r0 + j * RP : min(r0 + j * RP, T2 - 1);
+                        if (CI::ph) o.y[j] = Ly[(i1 + mm) * pg.ycs + i2l + mm];
+                        if (CI::pp) o.z[j] = Lz[(mm + T2 - 1 - i2l) * zc + mm + nw - 1 - i1];
+                        static_for<0, CI::nph>([&](auto c) { o.bb[c][j] = ld(Bt + (c * M + mm) * T2 + i2l); });
+                    });
+                    static_for<0, CI::nph>([&](auto c) { o.a[c] = ld(At + (c * M + mm) * nw + i1); });
+                };
+                auto compute = [&](auto m, const Ops &o) __attribute__((always_inline)) {
+                    static_for<0, EPT>([&](auto j) {
+                        if (!F && !(m < M && r0 + j * RP < T2)) return;
+                        if (CI::ph) {
+                            const V yu{o.y[j].x, o.y[j].y}, yd{o.y[j].z, o.y[j].w};
+                            static_for<0, CI::nph>([&](auto c) {
+                                V &r = acc[c][j][m];
+                                cmac(r, o.a[c], o.bb[c][j]);
+                                cmac(r, xu[j], yu);
+                                cmac(r, xd[j], yd);
+                            });
+                        }
+                        if (CI::pp) {
+                            const V zu{o.z[j].x, o.z[j].y}, zd{o.z[j].z, o.z[j].w};
+                            V &r = acc[CI::slot_pp][j][m];
+                            if (CI::ph) {
+                                // the PP term takes +s_b: undo the PH negation folded into x
+                                V w = cmul(zu, xd[j]);
+                                cmac(w, zd, xu[j]);
+                                r.x -= w.x;
+                                r.y -= w.y;
+                            } else {
+                                cmac(r, zu, xd[j]);
+                                cmac(r, zd, xu[j]);
+                            }
+                        }
+                    });
+                };
+                Ops o[2];
+                load(0, o[0]);
+                static_for<0, MG>([&](auto m) {
+                    if constexpr (m + 1 < MG) load(m + 1, o[(m + 1) & 1]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    compute(m, o[m & 1]);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            };
+            if (full && r0 + (EPT - 1) * RP < T2) run(std::true_type{});
+            else run(std::false_type{});
+        }
+        if (!act) continue;
+        const int64_t nn = (int64_t)n * n;
+        const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * nw * nw + (int64_t)(c0 + r0) * nw + i1;
+        static_for<0, EPT>([&](auto j) {
+            static_for<0, MG>([&](auto m) {
+                if (!(r0 + j * RP < T2 && m < M)) return;
+                const int64_t e = ebase + m * nn + (int64_t)j * RP * nw;
+                if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
+                if (CI::chg) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_chg][j][m]);
+                if (CI::pp) acc_update(a.acc[2], a.acc_kind, e, acc[CI::slot_pp][j][m]);
+            });
+        });
+
+    }
+}
+
+template <int MG, int NTH, int NB>
+hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, hipStream_t s) {
+    const void *fn = nullptr;
+    switch (channels) {
+#define G4_CASE(CHV)                                                                          \
+    case CHV:                                                                                 \
+        fn = reinterpret_cast<const void *>(&update_packed_kernel<G4_EPT, MG, CHV, NTH, NB>); \
+        break;
+        G4_CASE(1) G4_CASE(2) G4_CASE(3) G4_CASE(4) G4_CASE(5) G4_CASE(6) G4_CASE(7)
+#undef G4_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    UpdateArgs arg = a;
+    arg.nitems = nitems;
+    void *params[] = {&arg};
+    return hipLaunchKernel(fn, dim3(nitems), dim3(NTH), params, lds, s);
+}
+
+template <int NTH, int NB>
+hipError_t launch_packed_mg(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
+                            hipStream_t s) {
+    switch (mgroup) {
+        case 1: return launch_packed_ch<1, NTH, NB>(channels, nitems, lds, a, s);
+        case 4: return launch_packed_ch<4, NTH, NB>(channels, nitems, lds, a, s);
+        case 8: return launch_packed_ch<8, NTH, NB>(channels, nitems, lds, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+}  // namespace upd
+
+#define G4_PNAME2(e) launch_update_packed_e##e
+#define G4_PNAME(e) G4_PNAME2(e)
+
+// deep = false: 256-thread blocks, two buffers; deep = true: 512-thread
+// blocks, three buffers (built for one and two K2 rows per thread)
+hipError_t G4_PNAME(G4_EPT)(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
+                            hipStream_t s, bool deep) {
+    if (!deep) return upd::launch_packed_mg<256, 2>(channels, mgroup, nitems, lds, a, s);
+#if G4_EPT <= 2
+    return upd::launch_packed_mg<512, 3>(channels, mgroup, nitems, lds, a, s);
+#else
+    return hipErrorInvalidValue;
+#endif
+}
+
+}  // namespace g4

@@ -38,7 +38,7 @@ BAD = [
     dict(abi_version=7), dict(lx=0), dict(nw=63), dict(nw=0), dict(nwex=0), dict(nq=17),
     dict(q_list=[0, 1, 1] + list(range(3, 16))), dict(q_list=[0] * 15 + [16]),
     dict(q_begin=5, q_end=5), dict(q_end=129), dict(q_begin=-1), dict(channels=0),
-    dict(channels=8), dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9),
+    dict(channels=8), dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9), dict(flags=4),
     dict(device=-1), dict(mode=1, max_batch=0), dict(mode=1, max_batch=257),
     dict(mode=0, prod=1), dict(mode=0, acc=1), dict(mode=1, max_batch=8, prod=0, g_in=1),
     dict(tile=-1),
@@ -60,6 +60,36 @@ def test_invalid_configs_rejected_without_hip(kw):
         g4.g4_init_slice(c)
     assert e.value.code == g4.G4_E_ARG
     assert g4.g4_last_error()
+
+
+def test_packed_plan_accepted_and_sized():
+    plain = base(mode=1, max_batch=16, prod=1, g_in=1)
+    packed = base(mode=1, max_batch=16, prod=1, g_in=1, flags=g4.G4_F_PACKED)
+    e0, b0 = g4.g4_slice_size(plain)
+    e1, b1 = g4.g4_slice_size(packed)
+    ng = 16 * (64 + 8 - 1)
+    ldp = (ng + 1 + 7) // 8 * 8
+    per = ng * ldp * 16 + 2 * 128 * 1024 * 8          # G rows + direct vectors a, b
+    assert e0 == e1 and b1 - b0 == 16 * ((per + 255) // 256 * 256)
+
+
+def test_packed_rejections():
+    P = g4.G4_F_PACKED
+    for other in (g4.G4_F_MFMA, g4.G4_F_PACKED_DEEP):          # exclusive variants
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=P | other))
+        assert e.value.code == g4.G4_E_ARG
+    D = g4.G4_F_PACKED_DEEP
+    with pytest.raises(g4.G4Error) as e:                       # deep blocks: at most 2 rows/thread
+        g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=D, tile=32))
+    assert e.value.code == g4.G4_E_UNSUPPORTED
+    assert g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=D, tile=16))[0] > 0
+    for kw in (dict(mode=0, flags=P),                          # plain FP64
+               dict(mode=1, max_batch=8, prod=0, g_in=0, flags=P),   # batched FP64
+               dict(nw=130, mode=1, max_batch=8, prod=1, g_in=1, flags=P, tile=1)):   # odd tile
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_slice_size(base(**kw))
+        assert e.value.code == g4.G4_E_UNSUPPORTED, kw
 
 
 def test_unsupported_is_distinguished():

@@ -74,11 +74,61 @@ def test_batched_fp32(w, count, B, g_in, acc):
     check(got, oracle_out(w, count, w.channels), 1e-6)
 
 
+PACKED_KINDS = [(16, 2), (32, 3)]      # (flag, variant): packed, packed with deep blocks
+
+
+@pytest.mark.parametrize("g_in", [0, 1], ids=["c128-in", "c64-in"])
+@pytest.mark.parametrize("acc", [0, 1], ids=["acc-c128", "acc-kahan"])
+@pytest.mark.parametrize("w,count,B,tile", [(RAGGED, 7, 3, 0), (RAGGED, 5, 4, 20), (MULTI, 4, 4, 0),
+                                            (MULTI, 3, 3, 16), (NW128, 5, 4, 0), (TINY_ALL, 8, 8, 0)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+@pytest.mark.parametrize("flag,variant", PACKED_KINDS, ids=["packed", "deep"])
+def test_batched_fp32_packed(w, count, B, tile, g_in, acc, flag, variant):
+    """Packed operands copied straight into LDS: same products, same bar;
+    several passes with a ragged last one exercise the buffer rotation."""
+    g4 = g4mod()
+    if variant == 3 and tile == 20:
+        tile = 42                        # deep blocks sweep 21 rows of nw = 24
+    if variant == 3 and tile == 16:
+        tile = 8                         # three channels x 16 rows x 3 buffers exceed the LDS
+    if variant == 3 and w is NW128:
+        w = w.with_(channels=PH_MAGNETIC | PH_CHARGE)   # with PP, 3 buffers exceed the LDS
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=1, g_in=g_in, acc=acc, batch=B, tile=tile, flags=flag)
+    got, st = run_slice(cfg, to_dev(gu, g_in), to_dev(gd, g_in), s)
+    assert st["variant"] == variant and st["launches"] == -(-count // B)
+    check(got, oracle_out(w, count, w.channels), 1e-6)
+
+
+@pytest.mark.parametrize("channels", [PH_MAGNETIC, PH_CHARGE, PP_UPDOWN, PH_MAGNETIC | PP_UPDOWN],
+                         ids=["mag", "chg", "pp", "mag+pp"])
+@pytest.mark.parametrize("flag,variant", PACKED_KINDS, ids=["packed", "deep"])
+def test_packed_channel_subsets(channels, flag, variant):
+    w = RAGGED.with_(channels=channels)
+    gu, gd, s = host_inputs(w, 5)
+    cfg = config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=3, flags=flag)
+    got, st = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
+    assert st["variant"] == variant
+    check(got, oracle_out(w, 5, channels), 1e-6)
+
+
+def test_deep_long_pass():
+    """Passes of 16 measurements: the three-buffer rotation wraps several times."""
+    g4 = g4mod()
+    w = MULTI.with_(channels=PH_MAGNETIC)
+    gu, gd, s = host_inputs(w, 21)
+    for flag in (16, 32):
+        cfg = config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=16, flags=flag)
+        got, _ = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
+        check(got, oracle_out(w, 21, PH_MAGNETIC), 1e-6)
+
+
 ONE_HOT = [(0, 0, 0), (0, 5, 7), (1, 31, 2), (0, 167, 0), (1, 100, 167), (0, 27, 28)]
 
 
-@pytest.mark.parametrize("mode,prod", [(0, 0), (1, 1)], ids=["plain-fp64", "batched-fp32"])
-def test_one_hot_support(mode, prod):
+@pytest.mark.parametrize("mode,prod,flags", [(0, 0, 0), (1, 1, 0), (1, 1, 16), (1, 1, 32)],
+                         ids=["plain-fp64", "batched-fp32", "packed", "deep"])
+def test_one_hot_support(mode, prod, flags):
     w = RAGGED
     g_in = 0 if prod == 0 else 1
     for spin, r, c in ONE_HOT:
@@ -89,7 +139,7 @@ def test_one_hot_support(mode, prod):
         (gd if spin == 0 else gu)[0, (r * 7 + 3) % w.ng, (r * 7 + 3) % w.ng] = -0.75 + 0.25j
         s = np.ones(1)
         want = {ch: ref.accumulate(w, ch, gu, gd, s) for ch in (1, 2, 4)}
-        got, _ = run_slice(config_for(w, mode=mode, prod=prod, g_in=g_in, batch=1),
+        got, _ = run_slice(config_for(w, mode=mode, prod=prod, g_in=g_in, batch=1, flags=flags),
                            to_dev(gu, g_in), to_dev(gd, g_in), s)
         for ch in want:
             assert np.array_equal(got[ch] != 0, want[ch] != 0), (spin, r, c, ch)
@@ -98,7 +148,9 @@ def test_one_hot_support(mode, prod):
 def test_determinism_bitwise():
     w = MULTI
     gu, gd, s = host_inputs(w, 3)
-    for kw in (dict(mode=0), dict(mode=1, prod=1, g_in=1, acc=1, batch=3)):
+    for kw in (dict(mode=0), dict(mode=1, prod=1, g_in=1, acc=1, batch=3),
+               dict(mode=1, prod=1, g_in=1, acc=0, batch=2, flags=16),
+               dict(mode=1, prod=1, g_in=1, acc=0, batch=3, flags=32)):
         cfg = config_for(w, **kw)
         a, _ = run_slice(cfg, to_dev(gu, cfg.c.g_in), to_dev(gd, cfg.c.g_in), s)
         b, _ = run_slice(cfg, to_dev(gu, cfg.c.g_in), to_dev(gd, cfg.c.g_in), s)
@@ -219,8 +271,8 @@ def test_mfma_register_budget_rejected():
 def test_set_plan_switches_variant_and_batch():
     g4 = g4mod()
     w = MULTI.with_(channels=PH_MAGNETIC)
-    gu, gd, s = host_inputs(w, 6)
-    want = oracle_out(w, 6, PH_MAGNETIC)
+    gu, gd, s = host_inputs(w, 11)
+    want = oracle_out(w, 11, PH_MAGNETIC)
     h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=4))
     try:
         du, dd = to_dev(gu, 1), to_dev(gd, 1)
@@ -228,10 +280,17 @@ def test_set_plan_switches_variant_and_batch():
         g4.g4_set_plan(h, 0, 3, 1)                    # MFMA, passes of 3
         assert g4.g4_stats(h)["variant"] == 1
         g4.g4_accumulate(h, du[2:5], dd[2:5], s[2:5])
-        g4.g4_set_plan(h, 8, 2, 2)                    # back to VALU, tile 8, passes of 2
+        g4.g4_set_plan(h, 8, 1, 0)                    # back to VALU, tile 8, passes of 1
         st = g4.g4_stats(h)
-        assert st["variant"] == 0 and st["tile"] == 8 and st["batch"] == 2
-        g4.g4_accumulate(h, du[5:], dd[5:], s[5:])
+        assert st["variant"] == 0 and st["tile"] == 8 and st["batch"] == 1
+        g4.g4_accumulate(h, du[5:6], dd[5:6], s[5:6])
+        g4.g4_set_plan(h, 0, 2, g4.G4_VARIANT_PACKED)  # packed operands, passes of 2
+        st = g4.g4_stats(h)
+        assert st["variant"] == 2 and st["batch"] == 2
+        g4.g4_accumulate(h, du[6:8], dd[6:8], s[6:8])
+        g4.g4_set_plan(h, 0, 0, g4.G4_VARIANT_PACKED_DEEP)  # deep blocks, same pass size
+        assert g4.g4_stats(h)["variant"] == 3
+        g4.g4_accumulate(h, du[8:], dd[8:], s[8:])
         got = g4.g4_readback(h, 1).reshape(want[1].shape)
         with pytest.raises(g4.G4Error):
             g4.g4_set_plan(h, 0, 5, 0)                # above the allocated max_batch
