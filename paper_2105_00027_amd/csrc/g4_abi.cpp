@@ -259,6 +259,19 @@ void build_planes(const Plan &P, int nwex, std::vector<int2> &plane_qm) {
 // one per XCD, and interleaved so that tile i lands on XCD i mod 8 under
 // round-robin workgroup dispatch: each XCD's L2 serves a narrow band of G
 // blocks.  order 0 keeps the plain (group, k2, k1, rows) order.
+// Cut the sorted list into 8 contiguous parts, one per XCD, and interleave
+// them so that tile i lands on XCD i mod 8 under round-robin dispatch.
+void spread_over_xcds(const std::vector<int4> &sorted, std::vector<int4> &items) {
+    const size_t total = sorted.size(), parts = 8;
+    const size_t per = (total + parts - 1) / parts;
+    items.reserve(total);
+    for (size_t i = 0; i < per; ++i)
+        for (size_t x = 0; x < parts; ++x) {
+            const size_t src = x * per + i;
+            if (src < total) items.push_back(sorted[src]);
+        }
+}
+
 void build_work(const Plan &P, int nwex, int order, std::vector<int4> &groups,
                 std::vector<int4> &items) {
     groups.clear();
@@ -287,6 +300,34 @@ void build_work(const Plan &P, int nwex, int order, std::vector<int4> &groups,
         return (ax - bx + d.lx) % d.lx + d.lx * ((ay - by + d.ly) % d.ly);
     };
     const int ntile = (d.nw + P.tile - 1) / P.tile;
+    if (order == 3) {
+        // Inside a class, runs of constant k1 + q: the tiles of a run read the
+        // same exchange block (rows k1+q, columns k2+q = k1+q-d), and tiles
+        // that start one after another on an XCD run about one measurement
+        // apart, so each reuses the lines its predecessor just brought into
+        // L2.  Two K2 tiles side by side share the direct vector a(q, k1)
+        // and half of the exchange block's halo.
+        std::vector<std::vector<int>> groups_of(d.nc);
+        for (int g = 0; g < ng; ++g) groups_of[(size_t)groups[(size_t)g].x].push_back(g);
+        std::vector<int> done(d.nc, 0);
+        std::vector<int4> sorted;
+        sorted.reserve((size_t)ng * d.nc * d.nc * ntile);
+        for (int dd = 0; dd < d.nc; ++dd) {
+            if (done[dd]) continue;
+            const int neg = sub(0, dd);
+            done[dd] = done[neg] = 1;
+            const int members[2] = {dd, neg};
+            for (int mi = 0; mi < (neg == dd ? 1 : 2); ++mi)
+                for (int cb = 0; cb < ntile; cb += 2)
+                    for (int K = 0; K < d.nc; ++K)
+                        for (int k1 = 0; k1 < d.nc; ++k1)
+                            for (int g : groups_of[(size_t)sub(K, k1)])
+                                for (int c = cb; c < std::min(ntile, cb + 2); ++c)
+                                    sorted.push_back(int4{g, k1, sub(k1, members[mi]), c * P.tile});
+        }
+        spread_over_xcds(sorted, items);
+        return;
+    }
     // order 2: inside a class, windows of bk momenta k1 (neighbours along a
     // lattice row) x bg consecutive plane groups x half the K2 tiles, so that
     // the tiles resident together read few G(K2,K1) and exchange blocks
@@ -312,14 +353,7 @@ void build_work(const Plan &P, int nwex, int order, std::vector<int4> &groups,
                                     sorted.push_back(int4{g, k1, k2, c * P.tile});
                         }
     }
-    const size_t total = sorted.size(), parts = 8;
-    const size_t per = (total + parts - 1) / parts;
-    items.reserve(total);
-    for (size_t i = 0; i < per; ++i)
-        for (size_t x = 0; x < parts; ++x) {
-            const size_t src = x * per + i;
-            if (src < total) items.push_back(sorted[src]);
-        }
+    spread_over_xcds(sorted, items);
 }
 
 }  // namespace
@@ -338,7 +372,7 @@ struct g4_slice {
     int32_t *qpos = nullptr;
     int ngroups = 0, nitems = 0;
     size_t items_cap = 0;
-    int order = 2;          // tile order (see build_work); G4_TILE_ORDER overrides
+    int order = -1;         // tile order (see build_work), -1 = by variant; G4_TILE_ORDER overrides
     void *dir = nullptr;
     void *stage = nullptr;
     void *pack = nullptr;        // packed variant, max_batch blocks of P.pack_stride bytes
@@ -461,7 +495,10 @@ Tables tables_of(const g4_slice *h) {
 
 int rebuild_work(g4_slice *h) {
     std::vector<int4> groups, items;
-    build_work(h->P, h->cfg.nwex, h->order, groups, items);
+    // default order: runs of constant k1 + q for the packed kernels, windows otherwise
+    const bool packed = h->P.variant == G4_VARIANT_PACKED || h->P.variant == G4_VARIANT_PACKED_DEEP;
+    const int order = h->order >= 0 ? h->order : (packed ? 3 : 2);
+    build_work(h->P, h->cfg.nwex, order, groups, items);
     if (items.size() > h->items_cap) {
         G4_HIP(h, hipStreamSynchronize(h->stream));
         if (h->items) G4_HIP(h, hipFree(h->items));
@@ -634,7 +671,7 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     h->cfg.q_list = nullptr;
     h->P = P;
     h->device = cfg->device;
-    if (const char *o = std::getenv("G4_TILE_ORDER")) h->order = std::min(2, std::max(0, std::atoi(o)));
+    if (const char *o = std::getenv("G4_TILE_ORDER")) h->order = std::min(3, std::max(0, std::atoi(o)));
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) {
         delete h;
