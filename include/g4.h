@@ -81,8 +81,14 @@ enum {
 enum {
     G4_PROD_F64 = 0,     /* every product in FP64 */
     G4_PROD_F32 = 1,     /* G rounded to FP32, products and batch sums in FP32 */
-    G4_PROD_BF16X2 = 2,  /* direct term on MFMA from bf16 hi+lo split operands, exchange FP32 */
-    G4_PROD_F16X2 = 3    /* direct term on MFMA from scaled fp16 hi+lo split operands, exchange FP32 */
+    G4_PROD_BF16X2 = 2,  /* batched: exchange and PP as G4_PROD_F32; the PH direct term as a
+                            complex GEMM over the pass on MFMA from split operands x = hi + lo,
+                            hi = bf16(x), lo = bf16(x - hi), products hi*hi + hi*lo + lo*hi
+                            (relative error per product below 2^-15), added to the slice in a
+                            second read-modify-write.  Not with G4_F_MFMA. */
+    G4_PROD_F16X2 = 3    /* as G4_PROD_BF16X2 with hi = f16(x), lo = f16(2^11 (x - hi)) (relative
+                            error per product below 2^-21); operands must stay below 65504 in
+                            magnitude (fp16 range) */
 };
 
 /* accumulator held in device memory for every slice entry */

@@ -48,6 +48,7 @@ struct Plan {
     int prec;          // 0 FP64 products, 1 FP32
     int kind;          // update kernel: 0 plain FP64, 1 batched FP64, 2 batched FP32
     int variant;       // 0 VALU kernel, 1 MFMA direct term, 2 packed operands (G4_VARIANT_*)
+    int split;         // direct term from split operands on MFMA: 0 no, 1 bf16 hi+lo, 2 fp16 hi+lo
     int batch;         // measurements per pass
     int mgroup;        // transfer planes per work tile (compile-time bound)
     int tile;          // K2 rows per work tile
@@ -138,8 +139,7 @@ int validate(const g4_config *c, Plan *p) {
 
     // --- what this build runs
     if (c->nw > kMaxNw) return fail(G4_E_UNSUPPORTED, "nw=%d above %d", c->nw, kMaxNw);
-    if (c->prod == G4_PROD_BF16X2 || c->prod == G4_PROD_F16X2)
-        return fail(G4_E_UNSUPPORTED, "split-precision products are not available in this build");
+    P.split = c->prod == G4_PROD_BF16X2 ? 1 : (c->prod == G4_PROD_F16X2 ? 2 : 0);
     P.prec = c->prod == G4_PROD_F64 ? 0 : 1;
     P.kind = c->mode == G4_MODE_PLAIN ? 0 : (P.prec == 0 ? 1 : 2);
     P.batch = c->mode == G4_MODE_PLAIN ? 1 : c->max_batch;
@@ -157,7 +157,7 @@ int validate(const g4_config *c, Plan *p) {
     const int rp_v = P.variant == G4_VARIANT_PACKED_DEEP ? 512 / c->nw : rp;
     if (P.variant == 1) {
         // MFMA kernel: 16-row tiles, 64-column slabs per wave, register budget
-        if (P.kind != 2) return fail(G4_E_UNSUPPORTED, "MFMA direct term needs batched FP32 products");
+        if (P.kind != 2 || P.split) return fail(G4_E_UNSUPPORTED, "MFMA direct term needs batched FP32 products");
         if (c->nw % 64 || c->nw > 128) return fail(G4_E_UNSUPPORTED, "MFMA direct term needs nw = 64 or 128");
         if (nch * (c->nw / 64) * P.mgroup > 16)
             return fail(G4_E_UNSUPPORTED, "MFMA direct term: %d channels x %d slabs x %d planes exceed the register budget",
@@ -592,6 +592,7 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
     ua.pack_stride = (int64_t)P.pack_stride;
     ua.ldp = P.ldp;
     ua.nitems = h->nitems;
+    ua.skip_direct = P.split && P.slots ? 1 : 0;
     ua.sign = ds;
     ua.batch = nb;
     ua.acc[0] = h->acc[0];
@@ -614,6 +615,22 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
     if (timing) {
         G4_HIP(h, hipEventRecord(e1, h->stream));
         h->ev_pending.emplace_back(e0, e1);
+    }
+    if (ua.skip_direct) {
+        // split-precision direct term: GEMM over the pass on MFMA, its own read-modify-write
+        DirectArgs da;
+        da.dir_a = dir_a;
+        da.dir_b = dir_b;
+        da.dir_slot_stride = dir_slot;
+        da.dir_b_stride = dir_bstride;
+        da.batch = nb;
+        da.nslots = P.nslots;
+        da.acc[0] = (P.slots & 1) ? h->acc[0] : h->acc[1];
+        da.acc[1] = h->acc[1];
+        da.acc_kind = h->cfg.acc;
+        da.p0 = 0;
+        da.d = P.d;
+        G4_HIP(h, launch_direct_split(P.split, da, h->stream));
     }
     h->launches += 1;
     return G4_OK;

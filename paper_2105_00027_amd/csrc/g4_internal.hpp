@@ -56,6 +56,7 @@ struct UpdateArgs {
     int64_t pack_stride;      // bytes between consecutive packed matrices
     int ldp;                  // row pitch of a packed matrix, in 16-byte elements
     int nitems;               // work tiles in the list (one block per tile)
+    int skip_direct;          // 1: the PH direct term is added by direct_split_kernel instead
     Dims d;
     Tables t;
 };
@@ -102,6 +103,20 @@ inline int packed_slots(const PackedGeom &g, bool deep) {
 inline size_t packed_lds_bytes(const PackedGeom &g, bool deep) {
     return (size_t)packed_buffers(deep) * packed_slots(g, deep) * packed_threads(deep) * 16 + kMaxPassBatch * 4;
 }
+
+// Arguments of the split-precision direct-term GEMM (g4_direct.hip): direct
+// vectors in the layout of UpdateArgs, one PH channel per slot.
+struct DirectArgs {
+    const void *dir_a, *dir_b;   // complex64
+    int64_t dir_slot_stride, dir_b_stride;
+    int batch;
+    int nslots;                  // PH channels present (slot 0 magnetic or charge, slot 1 charge)
+    void *acc[2];                // accumulator of each slot's channel
+    int acc_kind;
+    int p0;                      // first plane of the launch (0: the whole slice)
+    Dims d;
+};
+hipError_t launch_direct_split(int split, const DirectArgs &a, hipStream_t s);
 
 // Arguments of the direct-vector gather.
 struct GatherArgs {

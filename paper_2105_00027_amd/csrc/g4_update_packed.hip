@@ -205,7 +205,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
                             const V yu{o.y[j].x, o.y[j].y}, yd{o.y[j].z, o.y[j].w};
                             static_for<0, CI::nph>([&](auto c) {
                                 V &r = acc[c][j][m];
-                                cmac(r, o.a[c], o.bb[c][j]);
+                                if (!a.skip_direct) cmac(r, o.a[c], o.bb[c][j]);
                                 cmac(r, xu[j], yu);
                                 cmac(r, xd[j], yd);
                             });

@@ -62,6 +62,15 @@ def test_invalid_configs_rejected_without_hip(kw):
     assert g4.g4_last_error()
 
 
+def test_split_precision_plans_accepted():
+    for prod in (2, 3):
+        for flags in (0, g4.G4_F_PACKED):
+            assert g4.g4_slice_size(base(mode=1, max_batch=8, prod=prod, g_in=1, flags=flags))[0] > 0
+    with pytest.raises(g4.G4Error) as e:                       # plain mode is FP64 throughout
+        g4.g4_slice_size(base(mode=0, prod=2))
+    assert e.value.code == g4.G4_E_ARG
+
+
 def test_packed_plan_accepted_and_sized():
     plain = base(mode=1, max_batch=16, prod=1, g_in=1)
     packed = base(mode=1, max_batch=16, prod=1, g_in=1, flags=g4.G4_F_PACKED)
@@ -94,7 +103,7 @@ def test_packed_rejections():
 
 def test_unsupported_is_distinguished():
     mfma = 8
-    for kw in (dict(nw=512), dict(mode=1, max_batch=8, prod=2, g_in=1), dict(tile=3),
+    for kw in (dict(nw=512), dict(mode=1, max_batch=8, prod=2, g_in=1, flags=8), dict(tile=3),
                dict(flags=mfma),                                    # plain mode
                dict(mode=1, max_batch=8, prod=1, g_in=1, flags=mfma, nw=24),
                dict(mode=1, max_batch=8, prod=1, g_in=1, flags=mfma, channels=7),

@@ -108,12 +108,16 @@ def test_ring_share_slice():
     assert rel_fro(got, want) <= 1e-6
 
 
-def test_three_channel_quarter_slice():
-    """8x8, Nw 64, Nq 64, Nwex 4, a 1/4 slice, PH magnetic + PH charge + PP in one pass."""
+@pytest.mark.parametrize("prod,bar", [(1, 1e-6), (3, 1e-6), (2, 2.0 ** -15 + 1e-6)],
+                         ids=["f32", "f16x2", "bf16x2"])
+def test_three_channel_quarter_slice(prod, bar):
+    """8x8, Nw 64, Nq 64, Nwex 4, a 1/4 slice, PH magnetic + PH charge + PP in one
+    pass, compensated complex64 accumulators; FP32 products or the split-precision
+    direct term on MFMA."""
     g4 = g4mod()
     w = C5_SPLIT.with_(q_begin=64, q_end=128, measurements=64)
     M, B = w.measurements, w.batch
-    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=1, batch=B))
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=prod, g_in=1, acc=1, batch=B))
     try:
         gu, gd = device_g(w, 1, 0, M)
         g4.g4_accumulate(h, gu, gd, signs(w, 0, M))
@@ -124,8 +128,10 @@ def test_three_channel_quarter_slice():
     finally:
         g4.g4_destroy(h)
         free()
-    for ch in (1, 2, 4):
-        assert rel_fro(got[ch], sampled.entries(w, ch, idx, 0, M)) <= 1e-6, ch
+    errs = {ch: rel_fro(got[ch], sampled.entries(w, ch, idx, 0, M)) for ch in (1, 2, 4)}
+    print("three-channel quarter slice, prod %d: sampled relative errors %s" % (prod, errs))
+    for ch, e in errs.items():
+        assert e <= bar, (ch, e)
 
 
 def test_long_run_stability():

@@ -123,6 +123,35 @@ def test_deep_long_pass():
         check(got, oracle_out(w, 21, PH_MAGNETIC), 1e-6)
 
 
+# Split-precision direct term: per product the dropped lo*lo and the rounding
+# of lo leave a relative error below 2^-15 (bf16 hi+lo) or 2^-21 (fp16 hi+lo,
+# lo scaled by 2^11); the exchange and PP sums stay FP32 (1e-6 bar).
+SPLIT_BAR = {2: 2.0 ** -15 + 1e-6, 3: 1e-6}
+
+
+@pytest.mark.parametrize("prod", [2, 3], ids=["bf16x2", "f16x2"])
+@pytest.mark.parametrize("flags", [0, 16], ids=["valu", "packed"])
+@pytest.mark.parametrize("w,count,B", [(RAGGED, 11, 9), (MULTI, 4, 4), (NW128, 5, 4)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_split_precision_direct_term(w, count, B, flags, prod):
+    """Direct term as a GEMM over the pass on MFMA from hi+lo split operands;
+    B = 9 leaves a partial chunk of 8 measurements in every pass."""
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=prod, g_in=1, acc=1, batch=B, flags=flags)
+    got, _ = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
+    want = oracle_out(w, count, w.channels)
+    check(got, want, SPLIT_BAR[prod])
+    # the split really is coarser than FP32 products for bf16 and no worse for fp16
+    ref32, _ = run_slice(config_for(w, mode=1, prod=1, g_in=1, acc=1, batch=B, flags=flags),
+                         to_dev(gu, 1), to_dev(gd, 1), s)
+    e_split = rel_fro(got[PH_MAGNETIC], want[PH_MAGNETIC])
+    e32 = rel_fro(ref32[PH_MAGNETIC], want[PH_MAGNETIC])
+    if prod == 2:
+        assert e_split > e32
+    else:
+        assert e_split < 10 * e32 + 1e-7
+
+
 ONE_HOT = [(0, 0, 0), (0, 5, 7), (1, 31, 2), (0, 167, 0), (1, 100, 167), (0, 27, 28)]
 
 
