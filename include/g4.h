@@ -85,7 +85,8 @@ enum {
                             complex GEMM over the pass on MFMA from split operands x = hi + lo,
                             hi = bf16(x), lo = bf16(x - hi), products hi*hi + hi*lo + lo*hi
                             (relative error per product below 2^-15), added to the slice in a
-                            second read-modify-write.  Not with G4_F_MFMA. */
+                            second read-modify-write.  Runs the packed kernels (G4_F_PACKED is
+                            implied; G4_F_PACKED_DEEP may be given); not with G4_F_MFMA. */
     G4_PROD_F16X2 = 3    /* as G4_PROD_BF16X2 with hi = f16(x), lo = f16(2^11 (x - hi)) (relative
                             error per product below 2^-21); operands must stay below 65504 in
                             magnitude (fp16 range) */

@@ -151,6 +151,9 @@ int validate(const g4_config *c, Plan *p) {
     P.variant = (c->flags & G4_F_MFMA) ? G4_VARIANT_MFMA
               : (c->flags & G4_F_PACKED) ? G4_VARIANT_PACKED
               : (c->flags & G4_F_PACKED_DEEP) ? G4_VARIANT_PACKED_DEEP : G4_VARIANT_VALU;
+    // split-precision plans run the packed kernels (their direct vectors can be
+    // read as zeros there, with no test in the arithmetic loop)
+    if (P.split && P.variant == G4_VARIANT_VALU) P.variant = G4_VARIANT_PACKED;
     const bool packed = P.variant == G4_VARIANT_PACKED || P.variant == G4_VARIANT_PACKED_DEEP;
     if (packed && P.kind != 2) return fail(G4_E_UNSUPPORTED, "packed operands need batched FP32 products");
     // K2 rows covered by one sweep of the block's threads
@@ -892,6 +895,9 @@ int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     Plan P;
     rc = validate(&c, &P);
     if (rc) return rc;
+    if (variant >= 0 && P.variant != variant)
+        return fail(G4_E_UNSUPPORTED, "variant %d cannot run this slice (split-precision plans use a packed variant)",
+                    variant);
     // the workspaces were sized for max_batch; only the pass size changes
     G4_HIP(h, hipSetDevice(h->device));
     G4_HIP(h, hipStreamSynchronize(h->stream));
@@ -1031,7 +1037,7 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
         cc.flags = with_variant(cc.flags, c.variant);
         cc.tile = c.tile;
         Plan P;
-        if (validate(&cc, &P) != G4_OK) continue;          // does not fit this slice
+        if (validate(&cc, &P) != G4_OK || P.variant != c.variant) continue;   // does not fit this slice
         if (ensure_pack(h, P) != G4_OK) continue;           // no room for the packed buffer
         h->P.ept = P.ept;
         h->P.tile = P.tile;

@@ -56,7 +56,8 @@ struct UpdateArgs {
     int64_t pack_stride;      // bytes between consecutive packed matrices
     int ldp;                  // row pitch of a packed matrix, in 16-byte elements
     int nitems;               // work tiles in the list (one block per tile)
-    int skip_direct;          // 1: the PH direct term is added by direct_split_kernel instead
+    int skip_direct;          // packed kernel: 1 = the PH direct term is added by
+                              // direct_split_kernel; the tile's direct vectors read as zeros
     Dims d;
     Tables t;
 };

@@ -410,14 +410,13 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
                 V yu, yd;
                 t.y_at(i2l, i1, m, yu, yd);
                 if (CI::mag) {
-                    if (!a.skip_direct) cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
+                    cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
                     cmac(acc[0][j][m], xu[j], yu);
                     cmac(acc[0][j][m], xd[j], yd);
                 }
                 if (CI::chg) {
                     const int sm = CI::slot_chg * M + m;
-                    if (!a.skip_direct)
-                        cmac(acc[CI::slot_chg][j][m], ld(At + sm * nw + i1), ld(Bt + sm * T2 + i2l));
+                    cmac(acc[CI::slot_chg][j][m], ld(At + sm * nw + i1), ld(Bt + sm * T2 + i2l));
                     cmac(acc[CI::slot_chg][j][m], xu[j], yu);
                     cmac(acc[CI::slot_chg][j][m], xd[j], yd);
                 }

@@ -121,6 +121,10 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
                 const int f = e - pg.nY - pg.nZ;
                 const int r = f / nw, c = f - r * nw;
                 o = ((int64_t)(rowX + r) * ldp + colX + c) * 16;
+            } else if (e < pg.nbuf && a.skip_direct) {
+                // direct term added elsewhere: the vectors read as zeros (a padding
+                // element of row 0, which the pack fills with zeros)
+                o = (int64_t)a.d.ng * 16;
             } else if (e < pg.nG + pg.nA) {
                 const int f = e - pg.nG, hw = nw / 2;
                 const int sm = f / hw, cc = f - sm * hw;
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
                             const V yu{o.y[j].x, o.y[j].y}, yd{o.y[j].z, o.y[j].w};
                             static_for<0, CI::nph>([&](auto c) {
                                 V &r = acc[c][j][m];
-                                if (!a.skip_direct) cmac(r, o.a[c], o.bb[c][j]);
+                                cmac(r, o.a[c], o.bb[c][j]);
                                 cmac(r, xu[j], yu);
                                 cmac(r, xd[j], yd);
                             });
