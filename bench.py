@@ -143,6 +143,8 @@ def main():
                     help="packed operands copied straight into LDS (the autotuner may switch)")
     ap.add_argument("--deep", action="store_true",
                     help="packed operands, 512-thread blocks, three LDS buffers")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay recorded HIP graphs of the passes (warm-up covers the recording)")
     ap.add_argument("--plain-measurements", type=int, default=64)
     ap.add_argument("--plain-tile", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
@@ -211,7 +213,8 @@ def main():
     acc = g4.G4_ACC_C128 if args.acc == "c128" else g4.G4_ACC_C64_KAHAN
     h = g4.g4_init_slice(cfg(mode=g4.G4_MODE_BATCHED, prod=g4.G4_PROD_F32, g_in=g4.G4_IN_C64,
                              acc=acc, max_batch=B, tile=args.tile,
-                             flags=(g4.G4_F_MFMA if args.mfma else 0) |
+                             flags=(g4.G4_F_GRAPH if args.graph else 0) |
+                                   (g4.G4_F_MFMA if args.mfma else 0) |
                                    (g4.G4_F_PACKED if args.packed else 0) |
                                    (g4.G4_F_PACKED_DEEP if args.deep else 0)))
     nblk = pool // B
@@ -223,7 +226,8 @@ def main():
         j = i % nblk
         g4.g4_accumulate(h, gu[j * B:(j + 1) * B], gd[j * B:(j + 1) * B], sg[j * B:(j + 1) * B])
 
-    for i in range(args.warmup):
+    # with graphs every pool block is used twice before timing (run, then record)
+    for i in range(max(args.warmup, 2 * nblk if args.graph else 0)):
         step(i)
     g4.g4_sync(h)
     g4.g4_reset(h)

@@ -109,7 +109,12 @@ enum {
 enum {
     G4_F_CHECK_FINITE = 1u,   /* g4_accumulate rejects signs that are not finite */
     G4_F_KERNEL_TIMING = 2u,  /* time every slice-update kernel with HIP events (see g4_stats) */
-    /* 4u is reserved */
+    G4_F_GRAPH = 4u,          /* batched: a pass on input pointers (and pass size) seen before is
+                                 replayed as a HIP graph of its kernels, recorded on the second
+                                 use (the first runs directly); the weights are uploaded before
+                                 each launch.  Up to 64 recordings per slice, dropped when the
+                                 plan changes.  With G4_F_KERNEL_TIMING a replayed pass is timed
+                                 as a whole.  The caller's stream must not be capturing already. */
     G4_F_MFMA = 8u,           /* batched FP32: direct term on MFMA (nw = 64 or 128; 16-row tiles) */
     G4_F_PACKED = 16u,        /* batched FP32: each pass first packs G_up and G_dn side by side
                                  (16 bytes per element, padded rows, with the pass's direct

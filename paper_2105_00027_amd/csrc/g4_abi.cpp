@@ -104,7 +104,8 @@ int validate(const g4_config *c, Plan *p) {
     if (c->prod < G4_PROD_F64 || c->prod > G4_PROD_F16X2) return fail(G4_E_ARG, "prod=%d", c->prod);
     if (c->acc < G4_ACC_C128 || c->acc > G4_ACC_C64) return fail(G4_E_ARG, "acc=%d", c->acc);
     if (c->mode != G4_MODE_PLAIN && c->mode != G4_MODE_BATCHED) return fail(G4_E_ARG, "mode=%d", c->mode);
-    if (c->flags & ~(uint32_t)(G4_F_CHECK_FINITE | G4_F_KERNEL_TIMING | G4_F_MFMA | G4_F_PACKED | G4_F_PACKED_DEEP))
+    if (c->flags & ~(uint32_t)(G4_F_CHECK_FINITE | G4_F_KERNEL_TIMING | G4_F_GRAPH | G4_F_MFMA | G4_F_PACKED |
+                               G4_F_PACKED_DEEP))
         return fail(G4_E_ARG, "unknown flags 0x%x", c->flags);
     if (c->device < 0) return fail(G4_E_ARG, "device=%d", c->device);
     if (c->mode == G4_MODE_PLAIN) {
@@ -392,6 +393,17 @@ struct g4_slice {
     uint64_t timed = 0;
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    // G4_F_GRAPH: one recorded pass per (inputs, pass size) under the current plan
+    struct GraphEntry {
+        const void *gu, *gd;
+        int nb;
+        double *dsign;            // the pass's weights, uploaded before each launch
+        hipGraphExec_t exec;      // null until recorded (second use)
+        int uses;
+        uint64_t last;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -417,10 +429,19 @@ int channel_slot(uint32_t channel) {
     return channel == G4_PH_MAGNETIC ? 0 : channel == G4_PH_CHARGE ? 1 : channel == G4_PP_UPDOWN ? 2 : -1;
 }
 
+void drop_graphs(g4_slice *h) {
+    for (auto &g : h->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.dsign) (void)hipFree(g.dsign);
+    }
+    h->graphs.clear();
+}
+
 void release(g4_slice *h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
     for (auto &pr : h->ev_pending) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
@@ -497,6 +518,10 @@ Tables tables_of(const g4_slice *h) {
 }
 
 int rebuild_work(g4_slice *h) {
+    if (!h->graphs.empty()) {
+        G4_HIP(h, hipStreamSynchronize(h->stream));
+        drop_graphs(h);
+    }
     std::vector<int4> groups, items;
     // default order: runs of constant k1 + q for the packed kernels, windows otherwise
     const bool packed = h->P.variant == G4_VARIANT_PACKED || h->P.variant == G4_VARIANT_PACKED_DEEP;
@@ -518,25 +543,11 @@ int rebuild_work(g4_slice *h) {
     return G4_OK;
 }
 
-// One pass: up to P.batch measurements starting at b0.
-int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, int b0, int nb) {
+// The device work of one pass (conversion, packing or gather, update, split
+// direct term) on inputs pu, pd with weights already at device address ds.
+int enqueue_pass(g4_slice *h, const void *pu, const void *pd, const double *ds, int nb, bool timing) {
     const Plan &P = h->P;
-    const size_t in_el = h->cfg.g_in == G4_IN_C128 ? 16 : 8;
     const int64_t per = (int64_t)P.d.ng * P.d.ng;
-    const void *pu = gu + (size_t)b0 * per * in_el;
-    const void *pd = gd + (size_t)b0 * per * in_el;
-
-    // signs: pinned slot -> device slot, ordered on the stream
-    const int slot = h->sign_next;
-    h->sign_next = (h->sign_next + 1) % kSignSlots;
-    if (h->sign_ev_used[slot]) G4_HIP(h, hipEventSynchronize(h->sign_ev[slot]));
-    double *hs = h->sign_host + (size_t)slot * kMaxBatch;
-    double *ds = h->sign_dev + (size_t)slot * kMaxBatch;
-    std::memcpy(hs, sign + b0, (size_t)nb * sizeof(double));
-    G4_HIP(h, hipMemcpyAsync(ds, hs, (size_t)nb * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    G4_HIP(h, hipEventRecord(h->sign_ev[slot], h->stream));
-    h->sign_ev_used[slot] = true;
-
     if (P.prec == 1 && h->cfg.g_in == G4_IN_C128) {
         float2 *su = static_cast<float2 *>(h->stage);
         float2 *sd = su + (size_t)P.batch * per;
@@ -606,7 +617,6 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
     ua.d = P.d;
     ua.t = tables_of(h);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timing = (h->cfg.flags & G4_F_KERNEL_TIMING) != 0;
     if (timing) {
         int rc = take_event(h, &e0);
         if (rc) return rc;
@@ -634,6 +644,96 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
         da.p0 = 0;
         da.d = P.d;
         G4_HIP(h, launch_direct_split(P.split, da, h->stream));
+    }
+    h->launches += 1;
+    return G4_OK;
+}
+
+// The recorded pass for these inputs, created (without a recording) if new;
+// the least recently used of 64 is dropped to make room.
+int graph_entry(g4_slice *h, const void *pu, const void *pd, int nb, g4_slice::GraphEntry **out) {
+    for (auto &g : h->graphs)
+        if (g.gu == pu && g.gd == pd && g.nb == nb) {
+            *out = &g;
+            return G4_OK;
+        }
+    if (h->graphs.size() >= 64) {
+        size_t lru = 0;
+        for (size_t i = 1; i < h->graphs.size(); ++i)
+            if (h->graphs[i].last < h->graphs[lru].last) lru = i;
+        G4_HIP(h, hipStreamSynchronize(h->stream));
+        if (h->graphs[lru].exec) G4_HIP(h, hipGraphExecDestroy(h->graphs[lru].exec));
+        G4_HIP(h, hipFree(h->graphs[lru].dsign));
+        h->graphs.erase(h->graphs.begin() + (std::ptrdiff_t)lru);
+    }
+    g4_slice::GraphEntry g{pu, pd, nb, nullptr, nullptr, 0, 0};
+    G4_HIP(h, hipMalloc(&g.dsign, kMaxBatch * sizeof(double)));
+    h->graphs.push_back(g);
+    *out = &h->graphs.back();
+    return G4_OK;
+}
+
+// One pass: up to P.batch measurements starting at b0.  With G4_F_GRAPH a pass
+// on inputs seen before replays its recorded graph (the first use runs
+// directly, the second records); the weights are uploaded before the launch.
+int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, int b0, int nb) {
+    const Plan &P = h->P;
+    const size_t in_el = h->cfg.g_in == G4_IN_C128 ? 16 : 8;
+    const int64_t per = (int64_t)P.d.ng * P.d.ng;
+    const void *pu = gu + (size_t)b0 * per * in_el;
+    const void *pd = gd + (size_t)b0 * per * in_el;
+    const bool graph = (h->cfg.flags & G4_F_GRAPH) && h->cfg.mode == G4_MODE_BATCHED;
+    const bool timing = (h->cfg.flags & G4_F_KERNEL_TIMING) != 0;
+    g4_slice::GraphEntry *ge = nullptr;
+    if (graph) {
+        int rc = graph_entry(h, pu, pd, nb, &ge);
+        if (rc) return rc;
+    }
+
+    // signs: pinned slot -> device (the ring's slot, or the recorded pass's buffer)
+    const int slot = h->sign_next;
+    h->sign_next = (h->sign_next + 1) % kSignSlots;
+    if (h->sign_ev_used[slot]) G4_HIP(h, hipEventSynchronize(h->sign_ev[slot]));
+    double *hs = h->sign_host + (size_t)slot * kMaxBatch;
+    double *ds = graph ? ge->dsign : h->sign_dev + (size_t)slot * kMaxBatch;
+    std::memcpy(hs, sign + b0, (size_t)nb * sizeof(double));
+    G4_HIP(h, hipMemcpyAsync(ds, hs, (size_t)nb * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    G4_HIP(h, hipEventRecord(h->sign_ev[slot], h->stream));
+    h->sign_ev_used[slot] = true;
+
+    if (!graph) return enqueue_pass(h, pu, pd, ds, nb, timing);
+    ge->last = ++h->graph_clock;
+    if (!ge->exec && ge->uses++ == 0) return enqueue_pass(h, pu, pd, ds, nb, timing);
+    if (!ge->exec) {
+        hipGraph_t g = nullptr;
+        G4_HIP(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_pass(h, pu, pd, ds, nb, false);
+        const hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+        h->launches -= 1;                     // counted below, when the graph runs
+        const hipError_t ei = hipGraphInstantiate(&ge->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            ge->exec = nullptr;
+            return hip_fail(h, ei, "hipGraphInstantiate");
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing) {
+        int rc = take_event(h, &e0);
+        if (rc) return rc;
+        rc = take_event(h, &e1);
+        if (rc) return rc;
+        G4_HIP(h, hipEventRecord(e0, h->stream));
+    }
+    G4_HIP(h, hipGraphLaunch(ge->exec, h->stream));
+    if (timing) {
+        G4_HIP(h, hipEventRecord(e1, h->stream));
+        h->ev_pending.emplace_back(e0, e1);
     }
     h->launches += 1;
     return G4_OK;
@@ -1024,6 +1124,7 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
     Cand best_c{h->P.batch, h->P.tile, h->P.variant};
     const Plan keep = h->P;
     const g4_config keep_cfg = h->cfg;
+    h->cfg.flags &= ~(uint32_t)G4_F_GRAPH;   // candidates are timed running directly
     if (cv >= 0) {                 // cached choice: install without timing
         best = res.ms_per_measurement;
         best_c = cands[0];

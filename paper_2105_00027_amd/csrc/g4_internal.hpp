@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace g4 {
 
@@ -35,6 +38,23 @@ struct Tables {
 };
 
 enum AccKind { ACC_C128 = 0, ACC_C64_KAHAN = 1, ACC_C64 = 2 };
+
+// Raise a kernel's dynamic-LDS limit once per (kernel, device): launches can
+// then be recorded into a HIP graph with no attribute call in between.
+inline hipError_t ensure_lds_limit(const void *fn, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = done.find({fn, dev});
+    if (it != done.end() && it->second >= lds) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) done[{fn, dev}] = lds;
+    return e;
+}
 enum { CH_MAG = 1, CH_CHG = 2, CH_PP = 4 };
 
 // Arguments of the slice-update kernel.  G elements are complex of the

@@ -19,10 +19,7 @@ hipError_t launch_mfma_ch(int channels, int nitems, size_t lds, const UpdateArgs
         default:
             return hipErrorInvalidValue;
     }
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
     UpdateArgs arg = a;
     void *params[] = {&arg};
     return hipLaunchKernel(fn, dim3(nitems), dim3(upd::NT), params, lds, s);

@@ -271,10 +271,7 @@ hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateAr
         default:
             return hipErrorInvalidValue;
     }
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
     UpdateArgs arg = a;
     arg.nitems = nitems;
     void *params[] = {&arg};

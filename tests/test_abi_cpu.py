@@ -38,7 +38,7 @@ BAD = [
     dict(abi_version=7), dict(lx=0), dict(nw=63), dict(nw=0), dict(nwex=0), dict(nq=17),
     dict(q_list=[0, 1, 1] + list(range(3, 16))), dict(q_list=[0] * 15 + [16]),
     dict(q_begin=5, q_end=5), dict(q_end=129), dict(q_begin=-1), dict(channels=0),
-    dict(channels=8), dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9), dict(flags=4),
+    dict(channels=8), dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9), dict(flags=64),
     dict(device=-1), dict(mode=1, max_batch=0), dict(mode=1, max_batch=257),
     dict(mode=0, prod=1), dict(mode=0, acc=1), dict(mode=1, max_batch=8, prod=0, g_in=1),
     dict(tile=-1),

@@ -152,6 +152,46 @@ def test_split_precision_direct_term(w, count, B, flags, prod):
         assert e_split < 10 * e32 + 1e-7
 
 
+@pytest.mark.parametrize("flags", [0, 16], ids=["valu", "packed"])
+def test_graph_replay_matches_direct_passes(flags):
+    """G4_F_GRAPH: passes on known inputs replay a recorded graph.  Every replay
+    is checked, bit for bit, against a slice running the same passes directly,
+    with eager work, input changes, new weights and synchronizations between
+    replays, and across a plan change (which drops the recordings)."""
+    import torch
+    g4 = g4mod()
+    w = MULTI
+    gu, gd, s = host_inputs(w, 6)
+    du, dd = to_dev(gu, 1), to_dev(gd, 1)
+    base = dict(mode=1, prod=1, g_in=1, acc=1, batch=3)
+    hd = g4.g4_init_slice(config_for(w, flags=flags, **base))
+    hg = g4.g4_init_slice(config_for(w, flags=flags | g4.G4_F_GRAPH | g4.G4_F_KERNEL_TIMING, **base))
+    try:
+        # per input half: direct, recorded, replayed, replayed; then after the
+        # plan call: direct, recorded
+        for it in range(12):
+            half = slice(0, 3) if it % 2 == 0 else slice(3, 6)
+            sg = s[half] * (1.0 if it < 5 else -0.5)
+            if it == 6:
+                du.mul_(0.75)                      # the graph must read the current contents
+            if it == 8:
+                g4.g4_set_plan(hg, 0, 0, -1)       # a plan call drops the recordings
+                g4.g4_set_plan(hd, 0, 0, -1)
+            for h in (hd, hg):
+                g4.g4_accumulate(h, du[half], dd[half], sg)
+            torch.cuda.synchronize()
+            _ = (du.abs().sum() + dd.abs().sum()).item()    # eager work between replays
+            for ch in (1, 2, 4):
+                a = g4.g4_readback(hd, ch)
+                b = g4.g4_readback(hg, ch)
+                assert np.array_equal(a, b), (it, ch)
+        st = g4.g4_stats(hg)
+        assert st["launches"] == 12 and st["measurements"] == 36 and st["timed_launches"] == 12
+    finally:
+        g4.g4_destroy(hd)
+        g4.g4_destroy(hg)
+
+
 ONE_HOT = [(0, 0, 0), (0, 5, 7), (1, 31, 2), (0, 167, 0), (1, 100, 167), (0, 27, 28)]
 
 
