@@ -199,7 +199,7 @@ int validate(const g4_config *c, Plan *p) {
     if (packed) {
         const bool deep = P.variant == G4_VARIANT_PACKED_DEEP;
         const int T2 = std::min(P.tile, c->nw);
-        const PackedGeom g = packed_geom(c->nw, T2, P.mgroup, (int)c->channels);
+        const PackedGeom g = packed_geom(c->nw, T2, P.mgroup, (int)c->channels, deep);
         if (P.tile % 2 || T2 % 2) return fail(G4_E_UNSUPPORTED, "packed operands need an even tile (tile=%d)", P.tile);
         if (packed_slots(g, deep) > kPackedSlots)
             return fail(G4_E_UNSUPPORTED, "packed operands: %d staging chunks per tile above %d", g.nbuf,

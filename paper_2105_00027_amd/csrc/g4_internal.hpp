@@ -85,7 +85,9 @@ struct UpdateArgs {
 // LDS geometry of one staging buffer of the packed-operand kernel, in 16-byte
 // chunks (one chunk = one G element with both spins, or two direct-vector
 // values).  Exchange block rows are padded to an odd pitch so that lanes
-// walking K1 (one row apart) fall in distinct banks.
+// walking K1 (one row apart) fall in distinct banks.  The G(K2,K1) rows are
+// staged only when x_in_lds (the deep form); the two-buffer form reads them
+// into registers.
 struct PackedGeom {
     int ycs;        // exchange-block row pitch
     int nY, nZ, nX; // exchange block, PP block, G(K2,K1) rows
@@ -93,14 +95,14 @@ struct PackedGeom {
     int nA, nB;     // direct vectors a (planes x nw) and b (planes x T2), chunks
     int nbuf;       // chunks per buffer
 };
-__host__ __device__ inline PackedGeom packed_geom(int nw, int T2, int M, int channels) {
+__host__ __device__ inline PackedGeom packed_geom(int nw, int T2, int M, int channels, bool x_in_lds) {
     PackedGeom g;
     const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
     const int yc = T2 + M - 1;
     g.ycs = yc | 1;
     g.nY = nph ? (nw + M - 1) * g.ycs : 0;
     g.nZ = (channels & CH_PP) ? (T2 + M - 1) * (nw + M - 1) : 0;
-    g.nX = T2 * nw;
+    g.nX = x_in_lds ? T2 * nw : 0;
     g.nG = g.nY + g.nZ + g.nX;
     g.nA = nph * M * nw / 2;
     g.nB = nph * M * T2 / 2;

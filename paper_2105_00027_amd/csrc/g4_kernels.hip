@@ -201,7 +201,8 @@ G4_PDECL(1) G4_PDECL(2) G4_PDECL(4) G4_PDECL(8)
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant) {
     if (variant == 2 || variant == 3) {
         // staging buffers of 16-byte chunks, rotating by measurement
-        return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels), variant == 3);
+        const bool deep = variant == 3;
+        return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels, deep), deep);
     }
     // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct
     // vectors (two copies, by measurement parity, for the MFMA variant)

@@ -19,7 +19,9 @@
 //      lanes walk K1 down a column, one pitch apart, in distinct banks;
 //   Z  PP block G(q-k2 rows, q-k1 columns), row-major (lanes read a
 //      descending run of one row);
-//   X  G(K2, K1) rows of the tile, row-major (lanes read a row);
+//   X  G(K2, K1) rows of the tile, row-major (lanes read a row): deep form only;
+//      the two-buffer form reads them from the packed block into registers,
+//      one measurement ahead, which leaves room for three blocks per CU;
 //   A  a(Q, K1) per PH channel and plane, Bv b(Q, K2) per channel, plane, row
 //      (complex64 pairs).
 #include "g4_update.hpp"
@@ -48,7 +50,14 @@ __device__ __forceinline__ void dma16(const char *base, unsigned off, unsigned l
 }
 
 // Wait until at most n vector-memory operations of this wave are outstanding.
+// n = 0 goes through the builtin so that the compiler knows every load of its
+// own (the G(K2,K1) registers) has landed and adds no wait of its own later,
+// where one would also wait for copies issued after this point.
 __device__ __forceinline__ void wait_vm(int n) {
+    if (n == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        return;
+    }
     switch (n) {
 #define G4_W(k) case k: asm volatile("s_waitcnt vmcnt(" #k ")" ::: "memory"); break;
         G4_W(1) G4_W(2) G4_W(3) G4_W(4) G4_W(5) G4_W(6) G4_W(7) G4_W(8)
@@ -76,7 +85,8 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
     // the pass's weights as floats after the NB buffers (sized for a full
     // tile); the measurement loop then has no memory read of its own that the
     // compiler would wait for (and with it for the copies in flight)
-    const int S_full = (packed_geom(nw, min(a.tile, nw), MG, CH).nbuf + NTH - 1) / NTH;
+    constexpr bool XL = NB > 2;      // G(K2,K1) rows staged in LDS (deep form) or read into registers
+    const int S_full = (packed_geom(nw, min(a.tile, nw), MG, CH, XL).nbuf + NTH - 1) / NTH;
     float *sg = reinterpret_cast<float *>(smem_raw + NB * S_full * NTH * 16);
     if (tid < a.batch) sg[tid] = (float)a.sign[tid];
 
@@ -88,7 +98,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
         const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
         const int k1 = it.y, k2 = it.z, c0 = it.w;
         const int T2 = min(a.tile, nw - c0);
-        const PackedGeom pg = packed_geom(nw, T2, M, CH);
+        const PackedGeom pg = packed_geom(nw, T2, M, CH, XL);
         const int zc = nw + M - 1;
 
         // ---- per-thread copy slots ---------------------------------------------
@@ -96,7 +106,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
         // offset off[k] of the measurement's packed block (its G matrix followed by
         // its direct vectors, see pack_gather_kernel); chunks past the tile's end
         // take offset 0 and land in the padding.  S slots cover a full tile.
-        const int S = (packed_geom(nw, min(a.tile, nw), MG, CH).nbuf + NTH - 1) / NTH;
+        const int S = S_full;
         const int ldp = a.ldp;
         const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
         const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
@@ -161,12 +171,27 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
             });
         });
         const bool full = (T2 == a.tile) && (M == MG);
+        // two-buffer form: this thread's G(K2,K1) values straight from the packed
+        // block into registers, one measurement ahead (the loop waits for every
+        // outstanding load before its barrier, so these add no wait)
+        float4 xr[EPT], xn[EPT];
+        auto load_x = [&](int b, float4 *dst) __attribute__((always_inline)) {
+            const float4 *blk = reinterpret_cast<const float4 *>(static_cast<const char *>(a.pack) +
+                                                                 (int64_t)b * a.pack_stride);
+            static_for<0, EPT>([&](auto j) {
+                const int r = min(r0 + j * RP, T2 - 1);
+                dst[j] = blk[(int64_t)(rowX + r) * ldp + colX + i1];
+            });
+        };
+        static_for<0, EPT>([&](auto j) { xr[j] = xn[j] = float4{0.f, 0.f, 0.f, 0.f}; });
         for (int b = 0; b < NB - 1 && b < a.batch; ++b) issue(b);
+        if (!XL && act && a.batch > 0) load_x(0, xr);
         for (int b = 0; b < a.batch; ++b) {
             // copies issued after b's: those of b+1 .. b+NB-2 that exist
             wait_vm(S * (min(b + NB - 2, a.batch - 1) - b));
             __syncthreads();                 // b's copies landed everywhere; b-1's buffer is free
             if (b + NB - 1 < a.batch) issue(b + NB - 1);
+            if (!XL && act && b + 1 < a.batch) load_x(b + 1, xn);
             if (!act) continue;
             const float s = sg[b];
             const float4 *L = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
@@ -176,7 +201,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
             // G(K2,K1) times -s_b for the PH exchange (its minus folded in), +s_b for PP
             V xu[EPT], xd[EPT];
             static_for<0, EPT>([&](auto j) {
-                const float4 x = Lx[min(r0 + j * RP, T2 - 1) * nw + i1];
+                const float4 x = XL ? Lx[min(r0 + j * RP, T2 - 1) * nw + i1] : xr[j];
                 const float f = CI::ph ? -s : s;
                 xu[j] = V{x.x * f, x.y * f};
                 xd[j] = V{x.z * f, x.w * f};
@@ -241,6 +266,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
             };
             if (full && r0 + (EPT - 1) * RP < T2) run(std::true_type{});
             else run(std::false_type{});
+            if (!XL) static_for<0, EPT>([&](auto j) { xr[j] = xn[j]; });
         }
         if (!act) continue;
         const int64_t nn = (int64_t)n * n;
