@@ -1,7 +1,9 @@
 // Helper kernels of the G4 slice library for gfx950 (CDNA4): the direct-term
-// gather, precision staging, accumulator conversion for readback/load, a fill
-// kernel, and the dispatch to the slice-update kernel instantiations
-// (g4_update.hpp / g4_update_inst.hip).
+// gather, the pack of a pass for the packed-operand kernels (which builds the
+// direct vectors on the way), precision staging, accumulator conversion for
+// readback/load, a fill kernel, and the dispatch to the slice-update kernel
+// instantiations (g4_update.hpp, g4_update_inst.hip, g4_update_mfma.hip,
+// g4_update_packed.hip).
 //
 // The gather builds, for every plane Q of the slice and every K, the
 // direct-term vectors a_b(Q,K) = s_b D(K+Q,K) and b_b(Q,K) = D(K,K+Q) with

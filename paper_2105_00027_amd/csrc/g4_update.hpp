@@ -9,15 +9,17 @@
 // One work tile = (plane group {q, m-range}, k1, k2, K2-frequency rows
 // [c0, c0+tile)).  Per measurement the block stages into LDS, both spins side
 // by side, the G sub-blocks that hold the exchange operand (rows k1+q, columns
-// k2+q; column-major so that lanes walking K1 read consecutive words) and the
-// PP operand (rows q-k2, columns q-k1; row-major, lanes read a descending
-// run), plus the direct-term vector b(Q,K2) of the tile's rows.  G(K2,K1) and
-// a(Q,K1) are read straight from memory, coalesced along K1, and reused over
-// the tile's planes and rows.  The pass's measurements are summed in
-// registers; then every slice entry is read, updated and written exactly once
-// (no atomics, deterministic).  In the plain FP64 kind (one measurement per
-// pass) the accumulators are loaded before the tile is staged so that the
-// HBM reads overlap the staging and the arithmetic.
+// k2+q; column-major so that lanes walking K1 read consecutive words), the PP
+// operand (rows q-k2, columns q-k1; row-major, lanes read a descending run)
+// and the tile's G(K2,K1) rows, plus the direct-term vectors a(Q,K1) and
+// b(Q,K2); G(K2,K1) is reused from registers over the tile's planes, a over
+// its rows.  Loads for the next measurement are held in registers while the
+// current one is computed.  The pass's measurements are summed in registers;
+// then every slice entry is read, updated and written exactly once (no
+// atomics, deterministic).  In the plain FP64 kind (one measurement per pass)
+// the accumulators are loaded before the tile is staged so that the HBM reads
+// overlap the staging and the arithmetic.  The packed-operand kernel
+// (g4_update_packed.hip) and the MFMA kernel below share the arithmetic.
 // Lanes run along K1 frequencies, so each G4 access of a wavefront is one
 // contiguous run of nw complex values.
 #pragma once

@@ -4,15 +4,17 @@
 //
 // Same arithmetic, work tiles, thread mapping and accumulator epilogue as the
 // batched FP32 VALU kernel in g4_update.hpp; what differs is how a tile's
-// operands reach LDS.  Before the pass, pack_kernel rewrites the pass's G
-// matrices as one array of 16-byte elements {Re G_up, Im G_up, Re G_dn, Im G_dn}
-// with a padded row pitch.  Every operand a tile needs per measurement is then
-// a set of contiguous row runs of that array (the exchange block, the PP block,
-// the G(K2,K1) rows) or of the direct-vector buffer, and each 16-byte chunk is
-// moved by global_load_lds_dwordx4 straight from memory into LDS: no register
-// round trip, no LDS store instructions.  Two LDS buffers alternate by
-// measurement parity, so the copies for measurement b+1 are in flight while
-// measurement b is computed.
+// operands reach LDS.  Before the pass, pack_gather_kernel rewrites each of
+// the pass's G matrix pairs as one block of 16-byte elements
+// {Re G_up, Im G_up, Re G_dn, Im G_dn} with a padded row pitch, followed by
+// that measurement's direct vectors.  Every operand a tile needs per
+// measurement is then a set of contiguous row runs of that block (the
+// exchange block, the PP block, the G(K2,K1) rows, the direct vectors), and
+// each 16-byte chunk is moved by global_load_lds_dwordx4 straight from memory
+// into LDS: no register round trip, no LDS store instructions.  Two LDS
+// buffers alternate by measurement parity (three, two measurements ahead, in
+// the deep form), so the copies for the next measurement are in flight while
+// the current one is computed.
 //
 // LDS buffer (16-byte chunks, PackedGeom):
 //   Y  exchange block G(k1+q rows, k2+q columns), row-major, odd row pitch:
