@@ -192,6 +192,40 @@ def test_graph_replay_matches_direct_passes(flags):
         g4.g4_destroy(hg)
 
 
+EDGE = [Workload("1x1-nw2", lx=1, ly=1, nw=2, nwex=1, nq=1, q_begin=0, q_end=1, beta=3.0,
+                 seed=24, wid=24, channels=ALL),
+        Workload("nw256", lx=2, ly=1, nw=256, nwex=2, nq=2, q_begin=1, q_end=4, beta=20.0,
+                 seed=25, wid=25, channels=ALL),
+        Workload("1x5-nwex9", lx=1, ly=5, nw=6, nwex=9, nq=5, q_list=(3, 1, 4, 0, 2), q_begin=7,
+                 q_end=38, beta=4.0, seed=26, wid=26, channels=ALL)]
+
+
+@pytest.mark.parametrize("w", EDGE, ids=lambda w: w.name)
+def test_edge_shapes_every_variant(w):
+    """Degenerate and maximum shapes: a 1x1 cluster with two frequencies, the
+    largest frequency count (256, one K2 row per 256-thread sweep), a 1x5
+    cluster with more transfers than a plane group holds; plain FP64 and every
+    batched variant that accepts the shape, against the oracle."""
+    g4 = g4mod()
+    count = 3
+    gu, gd, s = host_inputs(w, count)
+    want = oracle_out(w, count, w.channels)
+    got, _ = run_slice(config_for(w, mode=0), to_dev(gu, 0), to_dev(gd, 0), s)
+    check(got, want, 1e-12)
+    ran = 0
+    for flags in (0, g4.G4_F_MFMA, g4.G4_F_PACKED, g4.G4_F_PACKED_DEEP):
+        cfg = config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=2, flags=flags)
+        try:
+            g4.g4_slice_size(cfg)
+        except g4.G4Error as e:
+            assert e.code == g4.G4_E_UNSUPPORTED, (flags, e)
+            continue
+        got, _ = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
+        check(got, want, 1e-6)
+        ran += 1
+    assert ran >= 2
+
+
 ONE_HOT = [(0, 0, 0), (0, 5, 7), (1, 31, 2), (0, 167, 0), (1, 100, 167), (0, 27, 28)]
 
 
