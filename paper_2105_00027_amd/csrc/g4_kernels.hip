@@ -60,56 +60,76 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
 }
 
 // Packing of one pass for the packed-operand kernel (see PackArgs).  Block
-// (row, b) handles row `row` of matrix b.  Element (R, C) of G lies in block
-// (kr, kc) = (R / nwg, C / nwg) at local (lr, lc); it is
-//   a direct-term operand a_b(Q,K) = s_b D(K+Q, K) when lc < nw and
-//   m = lr - lc is a bosonic index: K = kc*nw + lc, q = kr - kc;
-//   a direct-term operand b_b(Q,K) = D(K, K+Q) when lr < nw and
-//   m = lc - lr is a bosonic index: K = kr*nw + lr, q = kc - kr;
-// for the plane (q, m) when it lies in the slice.  Each (plane, K) pair is hit
-// exactly once for a and once for b.
+// (R, b) handles row R of matrix b: it copies the row into the packed layout
+// (element pairs, 16-byte loads, when Ng is even), zeroes the padding columns
+// [ng, ldp), and writes the direct-term vector elements that lie in the row.
+// Row R = kr*Nwg + rho holds
+//   a_b(Q, K) = s_b D(K+Q, K) at column k*Nwg + i, K = k*nw + i, q = kr - k,
+//                for every m = rho - i that is a bosonic index;
+//   b_b(Q, K) = D(K, K+Q) at column kq*Nwg + rho + m, K = kr*nw + rho (rho < nw),
+//                q = kq - kr, for every bosonic m;
+// for the planes (q, m) in the slice: one thread per (column block, m).  Each
+// (plane, K) pair is written exactly once for a and once for b.
 __global__ __launch_bounds__(256) void pack_gather_kernel(PackArgs pa) {
     const GatherArgs &a = pa.g;
-    const int64_t b = blockIdx.y, row = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int R = blockIdx.x;
     const int ng = a.d.ng, nwg = a.d.nwg, nw = a.d.nw, nwex = a.d.nwex, nc = a.d.nc, n = a.d.n;
-    const float2 *su = static_cast<const float2 *>(a.gu) + b * a.g_stride + row * ng;
-    const float2 *sd = static_cast<const float2 *>(a.gd) + b * a.g_stride + row * ng;
-    float4 *d = static_cast<float4 *>(pa.pack) + b * pa.pack_stride16 + row * pa.ldp;
-    const int kr = (int)row / nwg, lr = (int)row - kr * nwg;
+    const float2 *su = static_cast<const float2 *>(a.gu) + b * a.g_stride + (int64_t)R * ng;
+    const float2 *sd = static_cast<const float2 *>(a.gd) + b * a.g_stride + (int64_t)R * ng;
+    float4 *d = static_cast<float4 *>(pa.pack) + b * pa.pack_stride16 + (int64_t)R * pa.ldp;
+    if ((ng & 1) == 0) {
+        // rows start on an even element: pairs are 16-byte aligned
+        const float4 *pu = reinterpret_cast<const float4 *>(su);
+        const float4 *pd = reinterpret_cast<const float4 *>(sd);
+        for (int j = threadIdx.x; j < ng / 2; j += 256) {
+            const float4 u = pu[j], w = pd[j];
+            d[2 * j] = float4{u.x, u.y, w.x, w.y};
+            d[2 * j + 1] = float4{u.z, u.w, w.z, w.w};
+        }
+    } else {
+        for (int c = threadIdx.x; c < ng; c += 256) {
+            const float2 u = su[c], w = sd[c];
+            d[c] = float4{u.x, u.y, w.x, w.y};
+        }
+    }
+    for (int c = ng + threadIdx.x; c < pa.ldp; c += 256) d[c] = float4{0.f, 0.f, 0.f, 0.f};
+    if (!a.slots) return;
+    const int kr = R / nwg, rho = R - kr * nwg;
     const float s = (float)a.sign[b];
     float2 *da = static_cast<float2 *>(a.dir_a) + b * a.dir_b_stride;
     float2 *db = static_cast<float2 *>(a.dir_b) + b * a.dir_b_stride;
-    for (int c = threadIdx.x; c < pa.ldp; c += 256) {
-        float4 v{0.f, 0.f, 0.f, 0.f};
-        if (c < ng) {
-            const float2 u = su[c], w = sd[c];
-            v = float4{u.x, u.y, w.x, w.y};
-            if (a.slots) {
-                const int kc = c / nwg, lc = c - kc * nwg;
-                const float2 dm{u.x - w.x, u.y - w.y}, dp{u.x + w.x, u.y + w.y};
-                // kind 0: operand a (row block holds K+Q), kind 1: operand b
-                for (int kind = 0; kind < 2; ++kind) {
-                    const int i = kind == 0 ? lc : lr;
-                    const int m = kind == 0 ? lr - lc : lc - lr;
-                    if (i >= nw || m < 0 || m >= nwex) continue;
-                    const int kk = kind == 0 ? kc : kr;               // momentum of K
-                    const int q = kind == 0 ? a.t.ksub[kr * nc + kc] : a.t.ksub[kc * nc + kr];
-                    const int iq = a.t.qpos[q];
-                    if (iq < 0) continue;
-                    const int64_t p = (int64_t)iq * nwex + m - a.d.q_begin;
-                    if (p < 0 || p >= a.d.planes) continue;
-                    int64_t o = p * n + (int64_t)kk * nw + i;
-                    float2 *dst = kind == 0 ? da : db;
-                    const float f = kind == 0 ? s : 1.f;
-                    if (a.slots & 1) {
-                        dst[o] = float2{f * dm.x, f * dm.y};
-                        o += a.dir_slot_stride;
-                    }
-                    if (a.slots & 2) dst[o] = float2{f * dp.x, f * dp.y};
-                }
-            }
+    for (int e = threadIdx.x; e < 2 * nc * nwex; e += 256) {
+        const int kind = e >= nc * nwex;                 // 0: operand a, 1: operand b
+        const int f = e - kind * nc * nwex;
+        const int kb = f / nwex, m = f - kb * nwex;      // column block, bosonic index
+        int i, col, kk, q;
+        if (kind == 0) {
+            i = rho - m;
+            if (i < 0 || i >= nw) continue;
+            col = kb * nwg + i;
+            kk = kb;
+            q = a.t.ksub[kr * nc + kb];
+        } else {
+            if (rho >= nw) continue;
+            i = rho;
+            col = kb * nwg + rho + m;
+            kk = kr;
+            q = a.t.ksub[kb * nc + kr];
         }
-        d[c] = v;
+        const int iq = a.t.qpos[q];
+        if (iq < 0) continue;
+        const int64_t p = (int64_t)iq * nwex + m - a.d.q_begin;
+        if (p < 0 || p >= a.d.planes) continue;
+        const float2 u = su[col], w = sd[col];
+        const float g = kind == 0 ? s : 1.f;
+        float2 *out = kind == 0 ? da : db;
+        int64_t o = p * n + (int64_t)kk * nw + i;
+        if (a.slots & 1) {
+            out[o] = float2{g * (u.x - w.x), g * (u.y - w.y)};
+            o += a.dir_slot_stride;
+        }
+        if (a.slots & 2) out[o] = float2{g * (u.x + w.x), g * (u.y + w.y)};
     }
 }
 
