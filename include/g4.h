@@ -214,6 +214,17 @@ int g4_readback(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, d
  * value and its rounding remainder (compensated) or rounded (plain float). */
 int g4_load(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, const double *in_c128);
 
+/* Add src's accumulators into dst, entry by entry, and its measurement count
+ * and weight sum into dst's: the end-of-run reduction of same-index slices
+ * that replicas (the paper's sub-rings, Implementation section) accumulate
+ * separately.  Both slices must have the same shape, transfer list, plane
+ * range and channels (G4_E_ARG otherwise) and live on the same device
+ * (G4_E_UNSUPPORTED); their accumulator kinds may differ (each value is read
+ * in src's kind and added in dst's; a compensated dst adds the float part and
+ * its remainder).  Waits for src's stream, runs on dst's, and returns when
+ * done; src is left unchanged. */
+int g4_merge(g4_slice *dst, g4_slice *src);
+
 /* Set the measurement count and weight sum (restoring a checkpoint). */
 int g4_set_counts(g4_slice *h, uint64_t measurements, double sign_sum);
 

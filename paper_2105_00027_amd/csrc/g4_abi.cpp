@@ -934,6 +934,29 @@ int g4_load(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, const
     return G4_OK;
 }
 
+int g4_merge(g4_slice *dst, g4_slice *src) {
+    int rc = usable(dst);
+    if (rc) return rc;
+    rc = usable(src);
+    if (rc) return rc;
+    if (dst == src) return fail(G4_E_ARG, "a slice cannot be merged into itself");
+    const g4_config &a = dst->cfg, &b = src->cfg;
+    if (a.lx != b.lx || a.ly != b.ly || a.nw != b.nw || a.nwex != b.nwex || a.nq != b.nq ||
+        a.q_begin != b.q_begin || a.q_end != b.q_end || a.channels != b.channels ||
+        dst->P.qlist != src->P.qlist)
+        return fail(G4_E_ARG, "slices differ in shape, transfer list, plane range or channels");
+    if (dst->device != src->device) return fail(G4_E_UNSUPPORTED, "slices on different devices");
+    G4_HIP(dst, hipSetDevice(dst->device));
+    G4_HIP(src, hipStreamSynchronize(src->stream));
+    for (int c = 0; c < 3; ++c)
+        if (dst->acc[c])
+            G4_HIP(dst, launch_merge(a.acc, dst->acc[c], b.acc, src->acc[c], dst->P.entries, dst->stream));
+    G4_HIP(dst, hipStreamSynchronize(dst->stream));
+    dst->measurements += src->measurements;
+    dst->sign_sum += src->sign_sum;
+    return G4_OK;
+}
+
 int g4_set_counts(g4_slice *h, uint64_t measurements, double sign_sum) {
     int rc = usable(h);
     if (rc) return rc;

@@ -185,6 +185,8 @@ hipError_t launch_acc_to_c128(int acc_kind, const void *acc, uint64_t first, uin
 hipError_t launch_c128_to_acc(int acc_kind, const double *src, void *acc, uint64_t first,
                               uint64_t count, int nc, int nw, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// dst += src over `count` entries of one channel (same geometry; any two accumulator kinds)
+hipError_t launch_merge(int dkind, void *dst, int skind, const void *src, uint64_t count, hipStream_t s);
 
 // Synthetic-input generator (g4_synth.hip).
 hipError_t launch_synth(void *out, int dtype, int lx, int ly, int nw, int nwex, double beta,

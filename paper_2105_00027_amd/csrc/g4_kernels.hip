@@ -188,6 +188,47 @@ __global__ void c128_to_acc_kernel(int kind, const double2 *src, void *acc, uint
     }
 }
 
+// dst += src entry by entry (same slice geometry, so the same physical index);
+// each side in its own accumulator kind.  A compensated destination takes the
+// source value's float part and its remainder as two compensated additions.
+__device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
+    const float y = v - c, t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+__global__ void merge_kernel(int dkind, void *dst, int skind, const void *src, uint64_t count) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        double2 v;
+        if (skind == ACC_C128) {
+            v = static_cast<const double2 *>(src)[e];
+        } else if (skind == ACC_C64_KAHAN) {
+            const float4 x = static_cast<const float4 *>(src)[e];
+            v = double2{(double)x.x - (double)x.z, (double)x.y - (double)x.w};
+        } else {
+            const float2 x = static_cast<const float2 *>(src)[e];
+            v = double2{(double)x.x, (double)x.y};
+        }
+        if (dkind == ACC_C128) {
+            double2 &o = static_cast<double2 *>(dst)[e];
+            o.x += v.x;
+            o.y += v.y;
+        } else if (dkind == ACC_C64_KAHAN) {
+            float4 o = static_cast<float4 *>(dst)[e];
+            const float hx = (float)v.x, hy = (float)v.y;
+            kahan_add(o.x, o.z, hx);
+            kahan_add(o.x, o.z, (float)(v.x - (double)hx));
+            kahan_add(o.y, o.w, hy);
+            kahan_add(o.y, o.w, (float)(v.y - (double)hy));
+            static_cast<float4 *>(dst)[e] = o;
+        } else {
+            float2 &o = static_cast<float2 *>(dst)[e];
+            o.x = (float)((double)o.x + v.x);
+            o.y = (float)((double)o.y + v.y);
+        }
+    }
+}
+
 __global__ void fill_zero_kernel(uint4 *p, size_t n16, unsigned char *tail, size_t ntail) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -308,6 +349,13 @@ hipError_t launch_c128_to_acc(int acc_kind, const double *src, void *acc, uint64
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(c128_to_acc_kernel, dim3(grid_for((int64_t)count, 256)), dim3(256), 0, s,
                        acc_kind, reinterpret_cast<const double2 *>(src), acc, first, count, nc, nw);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(int dkind, void *dst, int skind, const void *src, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(merge_kernel, dim3(grid_for((int64_t)count, 256)), dim3(256), 0, s, dkind, dst, skind,
+                       src, count);
     return hipGetLastError();
 }
 

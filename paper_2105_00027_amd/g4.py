@@ -93,6 +93,7 @@ _sig = {
     "g4_readback": ([_vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, _dp], ctypes.c_int),
     "g4_load": ([_vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, _dp], ctypes.c_int),
     "g4_set_counts": ([_vp, ctypes.c_uint64, ctypes.c_double], ctypes.c_int),
+    "g4_merge": ([_vp, _vp], ctypes.c_int),
     "g4_reset": ([_vp], ctypes.c_int),
     "g4_stats": ([_vp, ctypes.POINTER(g4_stats_t)], ctypes.c_int),
     "g4_set_plan": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
@@ -242,6 +243,10 @@ def g4_load(h: Slice, channel: int, first: int, values) -> None:
 
 def g4_set_counts(h: Slice, measurements: int, sign_sum: float) -> None:
     _check(_L.g4_set_counts(h.ptr, measurements, sign_sum))
+
+
+def g4_merge(dst: Slice, src: Slice) -> None:
+    _check(_L.g4_merge(dst.ptr, src.ptr))
 
 
 def g4_reset(h: Slice) -> None:

@@ -140,6 +140,9 @@ def test_null_handle_calls():
     with pytest.raises(g4.G4Error) as e:
         g4._check(g4._L.g4_sync(None))
     assert e.value.code == g4.G4_E_ARG
+    with pytest.raises(g4.G4Error) as e:
+        g4._check(g4._L.g4_merge(None, None))
+    assert e.value.code == g4.G4_E_ARG
     g4._L.g4_destroy(None)
 
 

@@ -226,6 +226,55 @@ def test_edge_shapes_every_variant(w):
     assert ran >= 2
 
 
+@pytest.mark.parametrize("accs", [(0, 0), (1, 1), (0, 1), (1, 0)],
+                         ids=["c128+c128", "kahan+kahan", "c128+kahan", "kahan+c128"])
+def test_merge_of_replicas_and_slice_files(tmp_path, accs):
+    """Sub-ring reduction: two replicas of the same planes, each fed half of the
+    measurements, merged into one; and a slice written to a file in ranges and
+    read back into a fresh slice."""
+    from paper_2105_00027_amd import slice_io
+    g4 = g4mod()
+    w = RAGGED
+    gu, gd, s = host_inputs(w, 6)
+    want = oracle_out(w, 6, w.channels)
+    du, dd = to_dev(gu, 1), to_dev(gd, 1)
+    mk = lambda acc: g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=3,
+                                                 flags=g4.G4_F_PACKED))
+    a, b, c = mk(accs[0]), mk(accs[1]), mk(accs[0])
+    try:
+        g4.g4_accumulate(a, du[:3], dd[:3], s[:3])
+        g4.g4_accumulate(b, du[3:], dd[3:], s[3:])
+        slice_io.reduce_slices(a, b)
+        st = g4.g4_stats(a)
+        assert st["measurements"] == 6 and st["sign_sum"] == s.sum()
+        got = {ch: g4.g4_readback(a, ch).reshape(want[ch].shape) for ch in (1, 2, 4)}
+        check(got, want, 1e-6)
+        slice_io.save_slice(a, str(tmp_path / "slice"), chunk=1000)
+        slice_io.load_slice(c, str(tmp_path / "slice"), chunk=777)
+        assert g4.g4_stats(c)["measurements"] == 6
+        for ch in (1, 2, 4):
+            back = g4.g4_readback(c, ch)
+            if accs[0] == 0:
+                assert np.array_equal(back, got[ch].reshape(-1))
+            else:
+                assert rel_fro(back, got[ch].reshape(-1)) < 1e-12
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_merge(a, a)
+        assert e.value.code == g4.G4_E_ARG
+    finally:
+        for h in (a, b, c):
+            g4.g4_destroy(h)
+    other = g4.g4_init_slice(config_for(w.with_(q_begin=4), mode=1, prod=1, g_in=1, batch=3))
+    d = mk(0)
+    try:
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_merge(d, other)
+        assert e.value.code == g4.G4_E_ARG
+    finally:
+        g4.g4_destroy(other)
+        g4.g4_destroy(d)
+
+
 ONE_HOT = [(0, 0, 0), (0, 5, 7), (1, 31, 2), (0, 167, 0), (1, 100, 167), (0, 27, 28)]
 
 
