@@ -132,8 +132,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--batch", type=int, default=64,
-                    help="measurements per step (the slice's max_batch)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="measurements per step (the slice's max_batch); default 64, ring: 16 "
+                         "(one walker's buffer; a multiple of 16 takes that many buffers per pass)")
+    ap.add_argument("--workload", default="slice4x4", choices=["slice4x4", "ring6x6"],
+                    help="slice4x4: the 4x4-cluster slice (default); ring6x6: rank 3's 1/8 share "
+                         "of the 6x6, Nw=128 array, fed by 8 walkers' buffers of 16 measurements "
+                         "in ring order")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default plan instead of timing the candidates first")
     ap.add_argument("--tile", type=int, default=0)
@@ -164,9 +169,17 @@ def main():
 
     import torch
     from paper_2105_00027_amd import g4
-    from synth import C2_PLAIN, signs
+    from synth import C2_PLAIN, C4_RING, signs
 
-    w = C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC)
+    ring = args.workload == "ring6x6"
+    if ring:
+        # rank 3 of 8: planes [216, 288) of 6x6 x 128 frequencies x (36 x 16) transfers
+        w = C4_RING.with_(channels=g4.G4_PH_MAGNETIC, q_begin=3 * 72, q_end=4 * 72)
+        args.batch = args.batch or 16
+        args.no_cpu_baseline = True     # the oracle's full-slice array would be 24.5 GB of host memory
+    else:
+        w = C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC)
+        args.batch = args.batch or 64
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     # an explicit stream (default priority): the library enqueues on it and the
@@ -202,14 +215,29 @@ def main():
     total = (args.warmup + args.steps) * B
     pool = max(B, min(args.pool, total))
     pool -= pool % B
+    if ring:
+        # the 8 walkers' buffers of 16 measurements, laid out in the order rank 3
+        # receives them (its own walker's, then each from the left); a step takes
+        # B / 16 of them in that order
+        if B % 16 or 128 % B:
+            ap.error("ring6x6: --batch must be 16, 32, 64 or 128")
+        pool = 128
+        runs = [((3 - s) % 8 * 16, 16) for s in range(8)]
+    else:
+        runs = [(0, pool)]
     if args.no_batched:
         args.steps = 0
-        pool = B
+        pool, runs = B, [(0, B)]
+    # ids[p]: the measurement held at pool position p
+    ids = np.concatenate([np.arange(b0, b0 + n) for b0, n in runs])
     gu = torch.empty((pool, ng, ng), dtype=torch.complex64, device=dev)
     gd = torch.empty_like(gu)
-    fill(gu, g4.G4_IN_C64, 0, pool, 0)
-    fill(gd, g4.G4_IN_C64, 0, pool, 1)
-    sg = signs(w, 0, pool)
+    pos = 0
+    for b0, n in runs:
+        fill(gu[pos:pos + n], g4.G4_IN_C64, b0, n, 0)
+        fill(gd[pos:pos + n], g4.G4_IN_C64, b0, n, 1)
+        pos += n
+    sg = np.concatenate([signs(w, b0, n) for b0, n in runs])
     acc = g4.G4_ACC_C128 if args.acc == "c128" else g4.G4_ACC_C64_KAHAN
     h = g4.g4_init_slice(cfg(mode=g4.G4_MODE_BATCHED, prod=g4.G4_PROD_F32, g_in=g4.G4_IN_C64,
                              acc=acc, max_batch=B, tile=args.tile,
@@ -248,8 +276,12 @@ def main():
     value = E * args.steps * B / (ms / 1e3) if args.steps else 0.0
     out["value"] = value
     out["ms_per_step"] = ms / max(1, args.steps)
-    out["config"] = {"workload": "4x4 Hubbard cluster G4 slice: Nc=16, Nw=64, Nq=16, Nwex=8, "
-                                 "E=%d entries, PH magnetic, %d measurements per step in passes "
+    shape = ("%dx%d Hubbard cluster G4 slice: Nc=%d, Nw=%d, Nq=%d, Nwex=%d, planes [%d, %d)"
+             % (w.lx, w.ly, w.nc, w.nw, w.nq, w.nwex, w.q0, w.q1))
+    if ring:
+        shape += ", 8 walkers' buffers of 16 measurements in ring order"
+    out["config"] = {"workload": shape +
+                                 ", E=%d entries, PH magnetic, %d measurements per step in passes "
                                  "of %d, complex64 G, FP32 products, %s accumulator"
                                  % (E, B, st["batch"], args.acc),
                      "entries": E, "measurements_per_step": B, "pass_batch": st["batch"],
@@ -264,7 +296,7 @@ def main():
             {"mode": 1, "acc": acc, "batch": st["batch"], "tile": st["tile"],
              "variant": st["variant"], "channels": w.channels, "entries": E})
     if not args.no_check and args.steps:
-        err, ns = sampled_error(w, h, g4, 1, b_seq, sg[b_seq], 256)
+        err, ns = sampled_error(w, h, g4, 1, [int(ids[p]) for p in b_seq], sg[b_seq], 256)
         out["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-6}
     g4.g4_destroy(h)
     del gu, gd
