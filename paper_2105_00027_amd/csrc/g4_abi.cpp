@@ -57,6 +57,7 @@ struct Plan {
     int nslots;
     uint64_t entries;  // per channel
     int ldp;           // packed variant: row pitch of a packed G matrix (16-byte elements)
+    int pcb;           // packed variant: column pitch of one momentum block (Nwg rounded up to 8)
     uint64_t pack_stride;   // bytes per measurement of the packed buffer (G + direct vectors)
     uint64_t acc_bytes, dir_bytes, stage_bytes, sign_bytes, scratch_bytes, table_bytes, pack_bytes;
     uint64_t total_bytes;
@@ -192,8 +193,11 @@ int validate(const g4_config *c, Plan *p) {
     P.slots = c->channels & 3u;
     P.nslots = popcount3(P.slots);
     // packed operands: one block per measurement, [G rows of ldp 16-byte
-    // elements | direct vectors a | b]; every copy offset inside it is 32-bit
-    P.ldp = (int)((ng + 1 + 7) / 8 * 8);
+    // elements | direct vectors a | b]; every copy offset inside it is 32-bit.
+    // Momentum blocks of columns start on 128-byte boundaries; one zero
+    // column at least follows the last.
+    P.pcb = (d.nwg + 7) / 8 * 8;
+    P.ldp = (int)((d.nc * P.pcb + 1 + 7) / 8 * 8);
     P.pack_stride = ((uint64_t)ng * P.ldp * 16 + 2ull * P.nslots * d.planes * n * 8 + 255) / 256 * 256;
     P.pack_bytes = 0;
     if (packed) {
@@ -477,6 +481,7 @@ int ensure_pack(g4_slice *h, const Plan &P) {
                     (unsigned long long)P.pack_bytes, hipGetErrorString(e));
     }
     h->P.ldp = P.ldp;
+    h->P.pcb = P.pcb;
     h->P.pack_stride = P.pack_stride;
     h->P.pack_bytes = P.pack_bytes;
     return G4_OK;
@@ -590,6 +595,7 @@ int enqueue_pass(g4_slice *h, const void *pu, const void *pd, const double *ds, 
         pa.pack = h->pack;
         pa.pack_stride16 = (int64_t)(P.pack_stride / 16);
         pa.ldp = P.ldp;
+        pa.pcb = P.pcb;
         G4_HIP(h, launch_pack_gather(pa, h->stream));
     } else if (P.slots) {
         G4_HIP(h, launch_gather(P.prec, ga, h->stream));
@@ -605,6 +611,7 @@ int enqueue_pass(g4_slice *h, const void *pu, const void *pd, const double *ds, 
     ua.pack = packed ? h->pack : nullptr;
     ua.pack_stride = (int64_t)P.pack_stride;
     ua.ldp = P.ldp;
+    ua.pcb = P.pcb;
     ua.nitems = h->nitems;
     ua.skip_direct = P.split && P.slots ? 1 : 0;
     ua.sign = ds;

@@ -75,6 +75,7 @@ struct UpdateArgs {
     const void *pack;         // packed variant: spin-interleaved G of the pass (pack_kernel)
     int64_t pack_stride;      // bytes between consecutive packed matrices
     int ldp;                  // row pitch of a packed matrix, in 16-byte elements
+    int pcb;                  // packed column pitch of one momentum block (nwg rounded up to 8)
     int nitems;               // work tiles in the list (one block per tile)
     int skip_direct;          // packed kernel: 1 = the PH direct term is added by
                               // direct_split_kernel; the tile's direct vectors read as zeros
@@ -165,16 +166,20 @@ hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems
                          const UpdateArgs &a, hipStream_t s);
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant);
 // Packing of one pass for the packed-operand kernel, with the direct vectors
-// built on the way: every element (b, r, c) of the pass's complex64 G pairs
-// goes to pack[b*pack_stride16 + r*ldp + c] = {Re up, Im up, Re dn, Im dn}
-// (16-byte units; row pitch ldp >= ng + 1, padding columns written with
-// zeros), and the elements that are direct-term operands are also written,
-// combined over the spins, to the direct vectors of GatherArgs layout.
+// built on the way: every element (b, r, c) of the pass's complex64 G pairs,
+// column c = k*nwg + i, goes to pack[b*pack_stride16 + r*ldp + k*pcb + i] =
+// {Re up, Im up, Re dn, Im dn} (16-byte units).  Each momentum block's columns
+// start on a 128-byte boundary (pcb = nwg rounded up to 8), so the row runs the
+// update kernel copies start on a cache line; the padding columns (i >= nwg and
+// [nc*pcb, ldp), ldp >= nc*pcb + 1) hold zeros.  The elements that are
+// direct-term operands are also written, combined over the spins, to the direct
+// vectors of GatherArgs layout.
 struct PackArgs {
     GatherArgs g;            // source G, direct-vector layout, weights, slots, shapes, tables
     void *pack;
     int64_t pack_stride16;   // 16-byte elements between consecutive packed matrices
     int ldp;
+    int pcb;                 // column pitch of one momentum block, a multiple of 8 >= nwg
 };
 hipError_t launch_pack_gather(const PackArgs &a, hipStream_t s);
 hipError_t launch_convert_c128_to_c64(const void *src, void *dst, int64_t count, hipStream_t s);

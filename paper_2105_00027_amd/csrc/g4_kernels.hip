@@ -61,8 +61,9 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
 
 // Packing of one pass for the packed-operand kernel (see PackArgs).  Block
 // (R, b) handles row R of matrix b: it copies the row into the packed layout
-// (element pairs, 16-byte loads, when Ng is even), zeroes the padding columns
-// [ng, ldp), and writes the direct-term vector elements that lie in the row.
+// (element pairs, 16-byte loads, when Ng is even), zeroes its padding columns,
+// and writes the direct-term vector elements that lie in
+// the row.
 // Row R = kr*Nwg + rho holds
 //   a_b(Q, K) = s_b D(K+Q, K) at column k*Nwg + i, K = k*nw + i, q = kr - k,
 //                for every m = rho - i that is a bosonic index;
@@ -78,22 +79,30 @@ __global__ __launch_bounds__(256) void pack_gather_kernel(PackArgs pa) {
     const float2 *su = static_cast<const float2 *>(a.gu) + b * a.g_stride + (int64_t)R * ng;
     const float2 *sd = static_cast<const float2 *>(a.gd) + b * a.g_stride + (int64_t)R * ng;
     float4 *d = static_cast<float4 *>(pa.pack) + b * pa.pack_stride16 + (int64_t)R * pa.ldp;
+    const int pcb = pa.pcb, pad = pcb - nwg;
+    // source column c = k*nwg + i -> packed column k*pcb + i
+    auto dcol = [&](int c) { const int k = c / nwg; return c + k * pad; };
     if ((ng & 1) == 0) {
         // rows start on an even element: pairs are 16-byte aligned
         const float4 *pu = reinterpret_cast<const float4 *>(su);
         const float4 *pd = reinterpret_cast<const float4 *>(sd);
         for (int j = threadIdx.x; j < ng / 2; j += 256) {
             const float4 u = pu[j], w = pd[j];
-            d[2 * j] = float4{u.x, u.y, w.x, w.y};
-            d[2 * j + 1] = float4{u.z, u.w, w.z, w.w};
+            d[dcol(2 * j)] = float4{u.x, u.y, w.x, w.y};
+            d[dcol(2 * j + 1)] = float4{u.z, u.w, w.z, w.w};
         }
     } else {
         for (int c = threadIdx.x; c < ng; c += 256) {
             const float2 u = su[c], w = sd[c];
-            d[c] = float4{u.x, u.y, w.x, w.y};
+            d[dcol(c)] = float4{u.x, u.y, w.x, w.y};
         }
     }
-    for (int c = ng + threadIdx.x; c < pa.ldp; c += 256) d[c] = float4{0.f, 0.f, 0.f, 0.f};
+    // zeros: each block's padding columns, then the row's tail [nc*pcb, ldp)
+    for (int e = threadIdx.x; e < nc * pad; e += 256) {
+        const int k = e / pad;
+        d[k * pcb + nwg + (e - k * pad)] = float4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int c = nc * pcb + threadIdx.x; c < pa.ldp; c += 256) d[c] = float4{0.f, 0.f, 0.f, 0.f};
     if (!a.slots) return;
     const int kr = R / nwg, rho = R - kr * nwg;
     const float s = (float)a.sign[b];
@@ -324,7 +333,9 @@ hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems
 hipError_t launch_pack_gather(const PackArgs &a, hipStream_t s) {
     const int count = a.g.batch, ng = a.g.d.ng;
     if (count == 0) return hipSuccess;
-    if (a.ldp < ng + 1 || a.pack_stride16 < (int64_t)ng * a.ldp || count > 65535) return hipErrorInvalidValue;
+    if (a.pcb < a.g.d.nwg || a.pcb % 8 || a.ldp < a.g.d.nc * a.pcb + 1 || a.pack_stride16 < (int64_t)ng * a.ldp ||
+        count > 65535)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(pack_gather_kernel, dim3(ng, count), dim3(256), 0, s, a);
     return hipGetLastError();
 }

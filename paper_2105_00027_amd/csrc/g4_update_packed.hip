@@ -110,11 +110,13 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
         // take offset 0 and land in the padding.  S slots cover a full tile.
         const int S = S_full;
         const int ldp = a.ldp;
+        // rows: G row index k*nwg + i; columns: packed column k*pcb + i
+        const int pcb = a.pcb;
         const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
-        const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
+        const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * pcb + c0 + m_lo : 0;
         const int rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
-        const int colZ = CI::pp ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
-        const int rowX = k2 * nwg + c0, colX = k1 * nwg;
+        const int colZ = CI::pp ? a.t.ksub[q * nc + k1] * pcb + m_lo : 0;
+        const int rowX = k2 * nwg + c0, colX = k1 * pcb;
         const int64_t dslot = a.dir_slot_stride;                 // complex64 values
         const int64_t adelta = static_cast<const char *>(a.dir_a) - static_cast<const char *>(a.pack);
         const int64_t bdelta = static_cast<const char *>(a.dir_b) - static_cast<const char *>(a.pack);
@@ -134,9 +136,9 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
                 const int r = f / nw, c = f - r * nw;
                 o = ((int64_t)(rowX + r) * ldp + colX + c) * 16;
             } else if (e < pg.nbuf && a.skip_direct) {
-                // direct term added elsewhere: the vectors read as zeros (a padding
-                // element of row 0, which the pack fills with zeros)
-                o = (int64_t)a.d.ng * 16;
+                // direct term added elsewhere: the vectors read as zeros (the last
+                // padding element of row 0, which the pack fills with zeros)
+                o = (int64_t)(ldp - 1) * 16;
             } else if (e < pg.nG + pg.nA) {
                 const int f = e - pg.nG, hw = nw / 2;
                 const int sm = f / hw, cc = f - sm * hw;

@@ -77,7 +77,8 @@ def test_packed_plan_accepted_and_sized():
     e0, b0 = g4.g4_slice_size(plain)
     e1, b1 = g4.g4_slice_size(packed)
     ng = 16 * (64 + 8 - 1)
-    ldp = (ng + 1 + 7) // 8 * 8
+    pcb = (64 + 8 - 1 + 7) // 8 * 8                     # momentum blocks of columns on 128 bytes
+    ldp = (16 * pcb + 1 + 7) // 8 * 8
     per = ng * ldp * 16 + 2 * 128 * 1024 * 8          # G rows + direct vectors a, b
     assert e0 == e1 and b1 - b0 == 16 * ((per + 255) // 256 * 256)
 
