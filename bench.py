@@ -33,8 +33,9 @@ METRIC = "G4 entry-updates/s per GPU (plain FP64 vs batched mixed) at stated err
 HBM_PEAK = 8.0e12                                   # bytes/s, MI355X HBM3E
 ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9                 # FP32 or FP64 FMA, non-packed: 78.6 TFLOP/s
 FLOPS_PER_EU = {1: 24, 2: 24, 4: 16}                 # per channel: direct 8 + exchange 16; PP 16
-VARIANTS = ["valu", "mfma-direct", "packed-lds", "packed-lds-deep"]
-KERNELS = ["update_kernel", "update_mfma_kernel", "update_packed_kernel", "update_packed_kernel"]
+VARIANTS = ["valu", "mfma-direct", "packed-lds", "packed-lds-deep", "packed-lds-mfma-direct"]
+KERNELS = ["update_kernel", "update_mfma_kernel", "update_packed_kernel", "update_packed_kernel",
+           "update_packed_mfma_kernel"]
 
 
 def algorithmic(E, ng, B, g_bytes, acc_bytes, channels):

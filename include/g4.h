@@ -115,15 +115,18 @@ enum {
                                  each launch.  Up to 64 recordings per slice, dropped when the
                                  plan changes.  With G4_F_KERNEL_TIMING a replayed pass is timed
                                  as a whole.  The caller's stream must not be capturing already. */
-    G4_F_MFMA = 8u,           /* batched FP32: direct term on MFMA (nw = 64 or 128; 16-row tiles) */
+    G4_F_MFMA = 8u,           /* batched FP32: direct term on MFMA (nw = 64 or 128; 16-row tiles).
+                                 With G4_F_PACKED: the packed operands of G4_F_PACKED and the
+                                 direct term on MFMA in one kernel (nw = 64, 16-row tiles, PH
+                                 channels only, FP32 products). */
     G4_F_PACKED = 16u,        /* batched FP32: each pass first packs G_up and G_dn side by side
                                  (16 bytes per element, each momentum block of Nwg columns padded
                                  to a multiple of 8, with the pass's direct vectors) and the
                                  update kernel copies its operand blocks straight from that
                                  buffer into LDS; needs an even tile and max_batch * (Ng * ldp
                                  * 16 + direct vectors) more device bytes, ldp = Nc * pcb + 1
-                                 rounded up to 8, pcb = Nwg rounded up to 8.  Exclusive with
-                                 G4_F_MFMA. */
+                                 rounded up to 8, pcb = Nwg rounded up to 8.  Combines with
+                                 G4_F_MFMA only (see there). */
     G4_F_PACKED_DEEP = 32u    /* as G4_F_PACKED, with 512-thread blocks and three LDS buffers
                                  (copies run two measurements ahead); one or two K2 rows per
                                  thread, tile = 512/nw or 1024/nw.  Exclusive with the others. */
@@ -134,7 +137,8 @@ enum {
     G4_VARIANT_VALU = 0,      /* operands staged through registers, all terms on the VALU */
     G4_VARIANT_MFMA = 1,      /* G4_F_MFMA */
     G4_VARIANT_PACKED = 2,    /* G4_F_PACKED */
-    G4_VARIANT_PACKED_DEEP = 3  /* G4_F_PACKED_DEEP */
+    G4_VARIANT_PACKED_DEEP = 3, /* G4_F_PACKED_DEEP */
+    G4_VARIANT_PACKED_MFMA = 4  /* G4_F_PACKED | G4_F_MFMA */
 };
 
 typedef struct g4_config {

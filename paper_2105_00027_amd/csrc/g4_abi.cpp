@@ -47,7 +47,8 @@ struct Plan {
     Dims d;
     int prec;          // 0 FP64 products, 1 FP32
     int kind;          // update kernel: 0 plain FP64, 1 batched FP64, 2 batched FP32
-    int variant;       // 0 VALU kernel, 1 MFMA direct term, 2 packed operands (G4_VARIANT_*)
+    int variant;       // 0 VALU kernel, 1 MFMA direct term, 2 packed operands, 3 deep packed,
+                       // 4 packed with the direct term on MFMA (G4_VARIANT_*)
     int split;         // direct term from split operands on MFMA: 0 no, 1 bf16 hi+lo, 2 fp16 hi+lo
     int batch;         // measurements per pass
     int mgroup;        // transfer planes per work tile (compile-time bound)
@@ -63,6 +64,11 @@ struct Plan {
     uint64_t total_bytes;
     std::vector<int32_t> qlist;
 };
+
+// Variants whose pass packs G first (and need the packed buffer).
+bool uses_pack(int variant) {
+    return variant == G4_VARIANT_PACKED || variant == G4_VARIANT_PACKED_DEEP || variant == G4_VARIANT_PACKED_MFMA;
+}
 
 int choose_mgroup(int nwex) { return nwex == 1 ? 1 : (nwex <= 4 ? 4 : 8); }
 
@@ -148,16 +154,29 @@ int validate(const g4_config *c, Plan *p) {
     P.mgroup = choose_mgroup(c->nwex);
     const int nch = popcount3(c->channels);
     const int rp = 256 / c->nw;
-    if (popcount3((c->flags >> 3) & 7u) > 1)
-        return fail(G4_E_ARG, "G4_F_MFMA, G4_F_PACKED and G4_F_PACKED_DEEP are exclusive");
-    P.variant = (c->flags & G4_F_MFMA) ? G4_VARIANT_MFMA
+    const uint32_t vf = c->flags & (G4_F_MFMA | G4_F_PACKED | G4_F_PACKED_DEEP);
+    if (popcount3(vf >> 3) > 1 && vf != (G4_F_MFMA | G4_F_PACKED))
+        return fail(G4_E_ARG, "G4_F_MFMA, G4_F_PACKED and G4_F_PACKED_DEEP are exclusive "
+                              "(except G4_F_PACKED | G4_F_MFMA)");
+    P.variant = vf == (G4_F_MFMA | G4_F_PACKED) ? G4_VARIANT_PACKED_MFMA
+              : (c->flags & G4_F_MFMA) ? G4_VARIANT_MFMA
               : (c->flags & G4_F_PACKED) ? G4_VARIANT_PACKED
               : (c->flags & G4_F_PACKED_DEEP) ? G4_VARIANT_PACKED_DEEP : G4_VARIANT_VALU;
     // split-precision plans run the packed kernels (their direct vectors can be
     // read as zeros there, with no test in the arithmetic loop)
     if (P.split && P.variant == G4_VARIANT_VALU) P.variant = G4_VARIANT_PACKED;
-    const bool packed = P.variant == G4_VARIANT_PACKED || P.variant == G4_VARIANT_PACKED_DEEP;
+    const bool packed = uses_pack(P.variant);
     if (packed && P.kind != 2) return fail(G4_E_UNSUPPORTED, "packed operands need batched FP32 products");
+    if (P.variant == G4_VARIANT_PACKED_MFMA) {
+        // MFMA accumulator layout: 16 rows x 64 columns per 256-thread block
+        if (P.split) return fail(G4_E_UNSUPPORTED, "packed MFMA kernel: the split direct term runs separately");
+        if (c->nw != 64) return fail(G4_E_UNSUPPORTED, "packed MFMA kernel needs nw = 64");
+        if (c->channels & G4_PP_UPDOWN) return fail(G4_E_UNSUPPORTED, "packed MFMA kernel: PH channels only");
+        if (c->tile && c->tile != 16) return fail(G4_E_UNSUPPORTED, "packed MFMA kernel uses 16-row tiles");
+        if (nch * P.mgroup > 8)
+            return fail(G4_E_UNSUPPORTED, "packed MFMA kernel: %d channels x %d planes exceed the register budget",
+                        nch, P.mgroup);
+    }
     // K2 rows covered by one sweep of the block's threads
     const int rp_v = P.variant == G4_VARIANT_PACKED_DEEP ? 512 / c->nw : rp;
     if (P.variant == 1) {
@@ -172,6 +191,8 @@ int validate(const g4_config *c, Plan *p) {
     if (P.variant == 1) {
         P.ept = 0;
         P.tile = 16;
+    } else if (P.variant == G4_VARIANT_PACKED_MFMA) {
+        P.ept = 4;                    // tile 16 = 4 rows per thread x 4 row sweeps
     } else if (c->tile) {
         if (c->tile % rp_v || c->tile >= c->nw + rp_v)
             return fail(G4_E_UNSUPPORTED, "tile=%d: must be a multiple of %d below nw + %d", c->tile, rp_v, rp_v);
@@ -467,6 +488,7 @@ uint32_t with_variant(uint32_t flags, int variant) {
     if (variant == G4_VARIANT_MFMA) flags |= G4_F_MFMA;
     if (variant == G4_VARIANT_PACKED) flags |= G4_F_PACKED;
     if (variant == G4_VARIANT_PACKED_DEEP) flags |= G4_F_PACKED_DEEP;
+    if (variant == G4_VARIANT_PACKED_MFMA) flags |= G4_F_PACKED | G4_F_MFMA;
     return flags;
 }
 
@@ -529,7 +551,7 @@ int rebuild_work(g4_slice *h) {
     }
     std::vector<int4> groups, items;
     // default order: runs of constant k1 + q for the packed kernels, windows otherwise
-    const bool packed = h->P.variant == G4_VARIANT_PACKED || h->P.variant == G4_VARIANT_PACKED_DEEP;
+    const bool packed = uses_pack(h->P.variant);
     const int order = h->order >= 0 ? h->order : (packed ? 3 : 2);
     build_work(h->P, h->cfg.nwex, order, groups, items);
     if (items.size() > h->items_cap) {
@@ -565,7 +587,7 @@ int enqueue_pass(g4_slice *h, const void *pu, const void *pd, const double *ds, 
     const int64_t pn = (int64_t)P.d.planes * P.d.n;
     // direct vectors: [slot][b][p][K] in their own buffer, or, for packed
     // operands, inside each measurement's packed block after its G rows
-    const bool packed = P.variant == G4_VARIANT_PACKED || P.variant == G4_VARIANT_PACKED_DEEP;
+    const bool packed = uses_pack(P.variant);
     int64_t dir_slot = (int64_t)P.batch * pn, dir_bstride = pn;
     void *dir_a = h->dir;
     if (packed) {
@@ -1011,7 +1033,7 @@ int g4_stats(g4_slice *h, g4_stats_t *st) {
 int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     int rc = usable(h);
     if (rc) return rc;
-    if (tile < 0 || batch < 0 || variant < -1 || variant > G4_VARIANT_PACKED_DEEP) return fail(G4_E_ARG, "bad plan value");
+    if (tile < 0 || batch < 0 || variant < -1 || variant > G4_VARIANT_PACKED_MFMA) return fail(G4_E_ARG, "bad plan value");
     if (batch > 0 && (h->cfg.mode == G4_MODE_PLAIN ? batch != 1 : batch > h->cfg.max_batch))
         return fail(G4_E_UNSUPPORTED, "batch %d above the allocated max_batch", batch);
     g4_config c = h->cfg;
@@ -1142,11 +1164,11 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
             if (b >= 4 || b == maxb) bs.push_back(b);
         if (bs.empty() || bs.back() != maxb) bs.push_back(maxb);
         const int rp = 256 / h->cfg.nw;
-        for (int v = 0; v <= G4_VARIANT_PACKED_DEEP; ++v)
+        for (int v = 0; v <= G4_VARIANT_PACKED_MFMA; ++v)
             for (int b : bs)
                 for (int e : {1, 2, 4}) {
-                    if ((v == 1 && e > 1) || (v == 3 && e > 2)) continue;
-                    cands.push_back({b, v == 1 ? 16 : e * (v == 3 ? 512 / h->cfg.nw : rp), v});
+                    if (((v == 1 || v == 4) && e > 1) || (v == 3 && e > 2)) continue;
+                    cands.push_back({b, v == 1 || v == 4 ? 16 : e * (v == 3 ? 512 / h->cfg.nw : rp), v});
                 }
     }
     std::vector<double> ref, cur;

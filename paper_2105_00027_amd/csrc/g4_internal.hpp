@@ -96,8 +96,8 @@ struct PackedGeom {
     int nA, nB;     // direct vectors a (planes x nw) and b (planes x T2), chunks
     int nbuf;       // chunks per buffer
 };
-__host__ __device__ inline PackedGeom packed_geom(int nw, int T2, int M, int channels, bool x_in_lds) {
-    PackedGeom g;
+__host__ __device__ constexpr PackedGeom packed_geom(int nw, int T2, int M, int channels, bool x_in_lds) {
+    PackedGeom g{};
     const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
     const int yc = T2 + M - 1;
     g.ycs = yc | 1;
@@ -165,6 +165,9 @@ hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
 hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems, int variant,
                          const UpdateArgs &a, hipStream_t s);
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant);
+// Packed operands with the direct term on MFMA (variant 4): nw = 64, tile 16, PH channels.
+hipError_t launch_update_packed_mfma(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
+                                     hipStream_t s);
 // Packing of one pass for the packed-operand kernel, with the direct vectors
 // built on the way: every element (b, r, c) of the pass's complex64 G pairs,
 // column c = k*nwg + i, goes to pack[b*pack_stride16 + r*ldp + k*pcb + i] =

@@ -271,7 +271,7 @@ G4_PDECL(1) G4_PDECL(2) G4_PDECL(4) G4_PDECL(8)
 #undef G4_PDECL
 
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant) {
-    if (variant == 2 || variant == 3) {
+    if (variant == 2 || variant == 3 || variant == 4) {
         // staging buffers of 16-byte chunks, rotating by measurement
         const bool deep = variant == 3;
         return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels, deep), deep);
@@ -306,6 +306,10 @@ hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems
     if (variant == 1) {
         if (kind != 2 || a.tile != 16 || a.d.nw % 64) return hipErrorInvalidValue;
         return launch_update_mfma(channels, a.d.nw / 64, mgroup, nitems, lds, a, s);
+    }
+    if (variant == 4) {
+        if (kind != 2 || !a.pack) return hipErrorInvalidValue;
+        return launch_update_packed_mfma(channels, mgroup, nitems, lds, a, s);
     }
     if (variant == 2 || variant == 3) {
         if (kind != 2 || !a.pack) return hipErrorInvalidValue;

@@ -69,6 +69,60 @@ __device__ __forceinline__ void wait_vm(int n) {
     }
 }
 
+// Per-thread copy slots of a tile.  Chunk e = k*NTH + tid of the LDS buffer
+// [Y | Z | X | A | Bv] comes from byte offset off[k] of a measurement's packed
+// block (its G matrix followed by its direct vectors, see pack_gather_kernel);
+// chunks past the tile's end take offset 0 and land in the buffer's padding.
+// G rows are indexed k*nwg + i, packed columns k*pcb + i.
+template <int NTH, int CH>
+__device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const PackedGeom &pg, int tid, int q,
+                                               int k1, int k2, int c0, int T2, int M, int m_lo, int p0,
+                                               unsigned (&off)[kPackedSlots]) {
+    using CI = ChanInfo<CH>;
+    const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
+    const int zc = nw + M - 1;
+    const int ldp = a.ldp, pcb = a.pcb;
+    const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
+    const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * pcb + c0 + m_lo : 0;
+    const int rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
+    const int colZ = CI::pp ? a.t.ksub[q * nc + k1] * pcb + m_lo : 0;
+    const int rowX = k2 * nwg + c0, colX = k1 * pcb;
+    const int64_t dslot = a.dir_slot_stride;                 // complex64 values
+    const int64_t adelta = static_cast<const char *>(a.dir_a) - static_cast<const char *>(a.pack);
+    const int64_t bdelta = static_cast<const char *>(a.dir_b) - static_cast<const char *>(a.pack);
+    static_for<0, kPackedSlots>([&](auto k) {
+        const int e = k * NTH + tid;
+        int64_t o = 0;
+        if (e < pg.nY) {
+            const int r = e / pg.ycs, c = e - r * pg.ycs;
+            o = ((int64_t)(rowY + r) * ldp + colY + c) * 16;
+        } else if (e < pg.nY + pg.nZ) {
+            const int f = e - pg.nY;
+            const int r = f / zc, c = f - r * zc;
+            o = ((int64_t)(rowZ + r) * ldp + colZ + c) * 16;
+        } else if (e < pg.nG) {
+            const int f = e - pg.nY - pg.nZ;
+            const int r = f / nw, c = f - r * nw;
+            o = ((int64_t)(rowX + r) * ldp + colX + c) * 16;
+        } else if (e < pg.nbuf && a.skip_direct) {
+            // direct term added elsewhere: the vectors read as zeros (the last
+            // padding element of row 0, which the pack fills with zeros)
+            o = (int64_t)(ldp - 1) * 16;
+        } else if (e < pg.nG + pg.nA) {
+            const int f = e - pg.nG, hw = nw / 2;
+            const int sm = f / hw, cc = f - sm * hw;
+            const int sl = sm / M, m = sm - sl * M;
+            o = adelta + (sl * dslot + (int64_t)(p0 + m) * n + k1 * nw + 2 * cc) * 8;
+        } else if (e < pg.nbuf) {
+            const int f = e - pg.nG - pg.nA, ht = T2 / 2;
+            const int sm = f / ht, cc = f - sm * ht;
+            const int sl = sm / M, m = sm - sl * M;
+            o = bdelta + (sl * dslot + (int64_t)(p0 + m) * n + k2 * nw + c0 + 2 * cc) * 8;
+        }
+        off[k] = (unsigned)o;
+    });
+}
+
 // NTH threads per block, NB staging buffers (copies run NB-1 measurements
 // ahead).  Every wave issues the same number S of copy instructions per
 // measurement (lanes past the tile's chunks copy the block's first chunk into
@@ -103,55 +157,12 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
         const PackedGeom pg = packed_geom(nw, T2, M, CH, XL);
         const int zc = nw + M - 1;
 
-        // ---- per-thread copy slots ---------------------------------------------
-        // Chunk e = k*NTH + tid of the buffer [Y | Z | X | A | Bv] comes from byte
-        // offset off[k] of the measurement's packed block (its G matrix followed by
-        // its direct vectors, see pack_gather_kernel); chunks past the tile's end
-        // take offset 0 and land in the padding.  S slots cover a full tile.
+        // ---- per-thread copy slots (S cover a full tile) ------------------------
         const int S = S_full;
         const int ldp = a.ldp;
-        // rows: G row index k*nwg + i; columns: packed column k*pcb + i
-        const int pcb = a.pcb;
-        const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
-        const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * pcb + c0 + m_lo : 0;
-        const int rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
-        const int colZ = CI::pp ? a.t.ksub[q * nc + k1] * pcb + m_lo : 0;
-        const int rowX = k2 * nwg + c0, colX = k1 * pcb;
-        const int64_t dslot = a.dir_slot_stride;                 // complex64 values
-        const int64_t adelta = static_cast<const char *>(a.dir_a) - static_cast<const char *>(a.pack);
-        const int64_t bdelta = static_cast<const char *>(a.dir_b) - static_cast<const char *>(a.pack);
+        const int rowX = k2 * nwg + c0, colX = k1 * a.pcb;
         unsigned off[kPackedSlots];
-        static_for<0, kPackedSlots>([&](auto k) {
-            const int e = k * NTH + tid;
-            int64_t o = 0;
-            if (e < pg.nY) {
-                const int r = e / pg.ycs, c = e - r * pg.ycs;
-                o = ((int64_t)(rowY + r) * ldp + colY + c) * 16;
-            } else if (e < pg.nY + pg.nZ) {
-                const int f = e - pg.nY;
-                const int r = f / zc, c = f - r * zc;
-                o = ((int64_t)(rowZ + r) * ldp + colZ + c) * 16;
-            } else if (e < pg.nG) {
-                const int f = e - pg.nY - pg.nZ;
-                const int r = f / nw, c = f - r * nw;
-                o = ((int64_t)(rowX + r) * ldp + colX + c) * 16;
-            } else if (e < pg.nbuf && a.skip_direct) {
-                // direct term added elsewhere: the vectors read as zeros (the last
-                // padding element of row 0, which the pack fills with zeros)
-                o = (int64_t)(ldp - 1) * 16;
-            } else if (e < pg.nG + pg.nA) {
-                const int f = e - pg.nG, hw = nw / 2;
-                const int sm = f / hw, cc = f - sm * hw;
-                const int sl = sm / M, m = sm - sl * M;
-                o = adelta + (sl * dslot + (int64_t)(p0 + m) * n + k1 * nw + 2 * cc) * 8;
-            } else if (e < pg.nbuf) {
-                const int f = e - pg.nG - pg.nA, ht = T2 / 2;
-                const int sm = f / ht, cc = f - sm * ht;
-                const int sl = sm / M, m = sm - sl * M;
-                o = bdelta + (sl * dslot + (int64_t)(p0 + m) * n + k2 * nw + c0 + 2 * cc) * 8;
-            }
-            off[k] = (unsigned)o;
-        });
+        packed_offsets<NTH, CH>(a, pg, tid, q, k1, k2, c0, T2, M, m_lo, p0, off);
         const int bufb = S * NTH * 16;   // bytes per buffer
         const unsigned lds_base = (unsigned)(uintptr_t)(lds_t *)smem_raw;
         const unsigned lds0 = lds_base + wave * 64 * 16;
@@ -288,6 +299,180 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
     }
 }
 
+#if G4_EPT == 4
+// Packed operands with the direct term on the matrix cores (nw = 64, 16-row
+// tiles, PH channels).  The copies into LDS are those of the two-buffer packed
+// kernel (same buffer layout, same slot table, G(K2,K1) read into registers one
+// measurement ahead); the thread mapping is the MFMA accumulator layout of
+// v_mfma_f32_16x16x4f32: lane l of wave w holds rows 4*(l/16) + t (t < 4) of
+// column K1 = 16*w + l%16.  The direct term of plane m is the complex rank-B
+// update D(K2, K1) += a_b(Q, K1) b_b(Q, K2); one MFMA pair per measurement and
+// plane takes it with K = 4 = {re, im} of the measurement plus two zero slots:
+//   A[K2][k] from b: (Re b, -Im b) for Re D, (Re b, Im b) for Im D;
+//   B[k][K1] from a: (Re a, Im a) for Re D, (Im a, Re a) for Im D.
+// The exchange Hadamard sum is added into the same registers on the VALU.
+template <int MG, int CH>
+__global__ __launch_bounds__(256, 2) void update_packed_mfma_kernel(UpdateArgs a) {
+    using V = float2;
+    using CI = ChanInfo<CH>;
+    static_assert(CI::ph && !CI::pp, "PH channels only");
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int NTH = 256, NB = 2, TR = 16;     // threads, buffers, tile rows
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l = tid & 63, g4r = l >> 4, c16 = l & 15;
+    constexpr int nw = 64;
+    const int nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
+    const int i1 = 16 * wave + c16;               // this lane's K1 column
+    constexpr int S = (packed_geom(nw, TR, MG, CH, false).nbuf + NTH - 1) / NTH;   // copies per wave
+    static_assert(S <= kPackedSlots, "staging slots");
+    float *sg = reinterpret_cast<float *>(smem_raw + NB * S * NTH * 16);
+    if (tid < a.batch) sg[tid] = (float)a.sign[tid];
+
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        __syncthreads();   // a previous tile's LDS reads are done (the launch uses one block per tile)
+        const int4 it = a.t.items[item];
+        const int4 gr = a.t.groups[it.x];
+        const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
+        const int k1 = it.y, k2 = it.z, c0 = it.w;
+        const PackedGeom pg = packed_geom(nw, TR, M, CH, false);
+        const int ldp = a.ldp;
+        const int rowX = k2 * nwg + c0, colX = k1 * a.pcb;
+        unsigned off[kPackedSlots];
+        packed_offsets<NTH, CH>(a, pg, tid, q, k1, k2, c0, TR, M, m_lo, p0, off);
+        const int bufb = S * NTH * 16;
+        const unsigned lds0 = (unsigned)(uintptr_t)(lds_t *)smem_raw + wave * 64 * 16;
+        auto issue = [&](int b) __attribute__((always_inline)) {
+            const char *base = static_cast<const char *>(a.pack) + (int64_t)b * a.pack_stride;
+            const unsigned buf = lds0 + (b % NB) * bufb;
+            static_for<0, kPackedSlots>([&](auto k) {
+                if (k < S) dma16(base, off[k], buf + k * NTH * 16);
+            });
+        };
+        f4 re[CI::count][MG], im[CI::count][MG];
+        static_for<0, CI::count>([&](auto c) {
+            static_for<0, MG>([&](auto m) {
+                re[c][m] = f4{0.f, 0.f, 0.f, 0.f};
+                im[c][m] = f4{0.f, 0.f, 0.f, 0.f};
+            });
+        });
+        // G(K2,K1) at this lane's four rows, one measurement ahead
+        float4 xr[4], xn[4];
+        auto load_x = [&](int b, float4 *dst) __attribute__((always_inline)) {
+            const float4 *blk = reinterpret_cast<const float4 *>(static_cast<const char *>(a.pack) +
+                                                                 (int64_t)b * a.pack_stride);
+            static_for<0, 4>([&](auto tt) { dst[tt] = blk[(int64_t)(rowX + 4 * g4r + tt) * ldp + colX + i1]; });
+        };
+        if (a.batch > 0) {
+            issue(0);
+            load_x(0, xr);
+        }
+        for (int b = 0; b < a.batch; ++b) {
+            wait_vm(0);
+            __syncthreads();                 // b's copies landed everywhere; b-1's buffer is free
+            if (b + 1 < a.batch) {
+                issue(b + 1);
+                load_x(b + 1, xn);
+            }
+            const float s = sg[b];
+            const float4 *Ly = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
+            const V *At = reinterpret_cast<const V *>(Ly + pg.nG);
+            const V *Bt = At + 2 * pg.nA;
+            // G(K2,K1) times -s_b (the PH exchange's minus folded in)
+            V xu[4], xd[4];
+            static_for<0, 4>([&](auto tt) {
+                xu[tt] = V{-s * xr[tt].x, -s * xr[tt].y};
+                xd[tt] = V{-s * xr[tt].z, -s * xr[tt].w};
+            });
+            // direct operands: k slot g4r = {re, im} of measurement b for g4r < 2, zero above
+            const bool live = g4r < 2, comp = g4r & 1;
+            // One plane at a time, software-pipelined: plane m+1's LDS operands are
+            // read before plane m's arithmetic (partial groups clamp the reads).
+            struct Ops {
+                float4 y[4];
+                V a[CI::count], b[CI::count];
+            };
+            auto run = [&](auto FULL) __attribute__((always_inline)) {
+                constexpr bool F = decltype(FULL)::value;
+                auto load = [&](int m, Ops &o) __attribute__((always_inline)) {
+                    const int mm = F ? m : min(m, M - 1);
+                    static_for<0, 4>([&](auto tt) { o.y[tt] = Ly[(i1 + mm) * pg.ycs + 4 * g4r + tt + mm]; });
+                    static_for<0, CI::count>([&](auto c) {
+                        const int sm = c * M + mm;
+                        o.b[c] = live ? ld(Bt + sm * TR + c16) : V{0.f, 0.f};
+                        o.a[c] = live ? ld(At + sm * nw + i1) : V{0.f, 0.f};
+                    });
+                };
+                auto compute = [&](auto m, const Ops &o) __attribute__((always_inline)) {
+                    if (!F && !(m < M)) return;
+                    // exchange: sum over spins of G(K2,K1) G(K1+Q,K2+Q), on the VALU
+                    static_for<0, 4>([&](auto tt) {
+                        V ex = cmul(xu[tt], V{o.y[tt].x, o.y[tt].y});
+                        cmac(ex, xd[tt], V{o.y[tt].z, o.y[tt].w});
+                        static_for<0, CI::count>([&](auto c) {
+                            re[c][m][tt()] += ex.x;
+                            im[c][m][tt()] += ex.y;
+                        });
+                    });
+                    // direct: a_b(Q,K1) b_b(Q,K2) on the matrix cores
+                    static_for<0, CI::count>([&](auto c) {
+                        const V bv = o.b[c], av = o.a[c];
+                        const float ar = comp ? -bv.y : bv.x, ai = comp ? bv.y : bv.x;
+                        const float br = comp ? av.y : av.x, bi = comp ? av.x : av.y;
+                        re[c][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re[c][m], 0, 0, 0);
+                        im[c][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, im[c][m], 0, 0, 0);
+                    });
+                };
+                Ops o[2];
+                load(0, o[0]);
+                static_for<0, MG>([&](auto m) {
+                    if constexpr (m + 1 < MG) load(m + 1, o[(m + 1) & 1]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    compute(m, o[m & 1]);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            };
+            if (M == MG) run(std::true_type{});
+            else run(std::false_type{});
+            static_for<0, 4>([&](auto tt) { xr[tt] = xn[tt]; });
+        }
+        const int64_t nn = (int64_t)n * n;
+        const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * nw * nw + (int64_t)c0 * nw + i1;
+        // one plane at a time, so that the accumulator reads in flight stay few
+        static_for<0, MG>([&](auto m) {
+            if (m >= M) return;
+            static_for<0, 4>([&](auto tt) {
+                const int64_t e = ebase + m * nn + (int64_t)(4 * g4r + tt) * nw;
+                if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, V{re[0][m][tt()], im[0][m][tt()]});
+                if (CI::chg)
+                    acc_update(a.acc[1], a.acc_kind, e, V{re[CI::slot_chg][m][tt()], im[CI::slot_chg][m][tt()]});
+            });
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+}
+
+template <int MG>
+hipError_t launch_packed_mfma_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, hipStream_t s) {
+    const void *fn = nullptr;
+    switch (channels) {
+        case 1: fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 1>); break;
+        case 2: fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 2>); break;
+        case 3:   // both PH channels: register budget allows plane groups up to 4
+            if constexpr (MG <= 4) fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 3>);
+            else return hipErrorInvalidValue;
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
+    UpdateArgs arg = a;
+    arg.nitems = nitems;
+    void *params[] = {&arg};
+    return hipLaunchKernel(fn, dim3(nitems), dim3(256), params, lds, s);
+}
+#endif
+
 template <int MG, int NTH, int NB>
 hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, hipStream_t s) {
     const void *fn = nullptr;
@@ -336,5 +521,19 @@ hipError_t G4_PNAME(G4_EPT)(int channels, int mgroup, int nitems, size_t lds, co
     return hipErrorInvalidValue;
 #endif
 }
+
+#if G4_EPT == 4
+// packed operands, direct term on MFMA: nw = 64, 16-row tiles, PH channels
+hipError_t launch_update_packed_mfma(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
+                                     hipStream_t s) {
+    if (a.d.nw != 64 || a.tile != 16 || (channels & CH_PP)) return hipErrorInvalidValue;
+    switch (mgroup) {
+        case 1: return upd::launch_packed_mfma_ch<1>(channels, nitems, lds, a, s);
+        case 4: return upd::launch_packed_mfma_ch<4>(channels, nitems, lds, a, s);
+        case 8: return upd::launch_packed_mfma_ch<8>(channels, nitems, lds, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+#endif
 
 }  // namespace g4

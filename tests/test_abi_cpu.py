@@ -85,9 +85,10 @@ def test_packed_plan_accepted_and_sized():
 
 def test_packed_rejections():
     P = g4.G4_F_PACKED
-    for other in (g4.G4_F_MFMA, g4.G4_F_PACKED_DEEP):          # exclusive variants
+    for flags in (P | g4.G4_F_PACKED_DEEP, g4.G4_F_MFMA | g4.G4_F_PACKED_DEEP,
+                  P | g4.G4_F_MFMA | g4.G4_F_PACKED_DEEP):      # exclusive variants
         with pytest.raises(g4.G4Error) as e:
-            g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=P | other))
+            g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=flags))
         assert e.value.code == g4.G4_E_ARG
     D = g4.G4_F_PACKED_DEEP
     with pytest.raises(g4.G4Error) as e:                       # deep blocks: at most 2 rows/thread
@@ -164,3 +165,29 @@ def test_index_maps_bit_exact(w):
     iQ = np.arange(w.q0, w.q1)
     assert np.array_equal(pq, np.asarray(w.qs)[iQ // w.nwex])
     assert np.array_equal(pm, iQ % w.nwex)
+
+
+def test_packed_mfma_plan_accepted_and_bounded():
+    """G4_F_PACKED | G4_F_MFMA: packed operands with the direct term on MFMA;
+    nw = 64, 16-row tiles, PH channels, at most 8 channel-planes per thread
+    group; the packed buffer is sized as for G4_F_PACKED."""
+    PM = g4.G4_F_PACKED | g4.G4_F_MFMA
+    ok = base(mode=1, max_batch=16, prod=1, g_in=1, flags=PM)
+    packed = base(mode=1, max_batch=16, prod=1, g_in=1, flags=g4.G4_F_PACKED, tile=16)
+    assert g4.g4_slice_size(ok) == g4.g4_slice_size(packed)      # same buffers at the same tile
+    assert g4.g4_slice_size(base(mode=1, max_batch=16, prod=1, g_in=1, flags=PM, tile=16))[0] > 0
+    assert g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=PM, nwex=4, q_end=64,
+                                 channels=g4.G4_PH_MAGNETIC | g4.G4_PH_CHARGE))[0] > 0
+    for kw in (dict(nw=128),                                        # 64 columns per block
+               dict(nw=32),
+               dict(channels=g4.G4_PP_UPDOWN),                      # PH channels only
+               dict(channels=g4.G4_PH_MAGNETIC | g4.G4_PP_UPDOWN),
+               dict(tile=8),                                        # 16-row tiles
+               dict(prod=2),                                        # split direct term runs apart
+               dict(channels=g4.G4_PH_MAGNETIC | g4.G4_PH_CHARGE)):  # 2 channels x 8 planes
+        with pytest.raises(g4.G4Error) as e:
+            g4.g4_slice_size(base(**{**dict(mode=1, max_batch=8, prod=1, g_in=1, flags=PM), **kw}))
+        assert e.value.code == g4.G4_E_UNSUPPORTED, kw
+    with pytest.raises(g4.G4Error) as e:                            # batched FP32 only
+        g4.g4_slice_size(base(mode=1, max_batch=8, prod=0, g_in=0, flags=PM))
+    assert e.value.code == g4.G4_E_UNSUPPORTED

@@ -59,8 +59,9 @@ def test_plain_slice_full_size():
     assert rel_fro(got, want) <= 1e-12
 
 
-@pytest.mark.parametrize("acc,flags", [(0, 0), (1, 0), (0, 8), (0, 16), (1, 16), (0, 32)],
-                         ids=["acc-c128", "acc-kahan", "mfma", "packed", "packed-kahan", "deep"])
+@pytest.mark.parametrize("acc,flags", [(0, 0), (1, 0), (0, 8), (0, 16), (1, 16), (0, 32), (0, 24), (1, 24)],
+                         ids=["acc-c128", "acc-kahan", "mfma", "packed", "packed-kahan", "deep",
+                              "packed-mfma", "packed-mfma-kahan"])
 def test_batched_full_size(acc, flags):
     """The same slice, 4096 measurements in passes of 16, complex64 G, FP32 products."""
     g4 = g4mod()

@@ -112,6 +112,34 @@ def test_packed_channel_subsets(channels, flag, variant):
     check(got, oracle_out(w, 5, channels), 1e-6)
 
 
+# Packed operands with the direct term on the matrix cores: nw = 64, 16-row
+# tiles, PH channels; MULTI has plane groups of 3 (nwex = 3, partial groups of
+# the 4-plane kernel), W8 groups of 8 starting mid-group (m = 3) and ending
+# mid-group, over two lattice rows.
+W8 = Workload("w8", lx=2, ly=2, nw=64, nwex=8, nq=4, q_begin=3, q_end=29, beta=6.0, seed=27, wid=27,
+              channels=PH_MAGNETIC)
+
+
+@pytest.mark.parametrize("g_in", [0, 1], ids=["c128-in", "c64-in"])
+@pytest.mark.parametrize("acc", [0, 1, 2], ids=["acc-c128", "acc-kahan", "acc-c64"])
+@pytest.mark.parametrize("w,count,B", [(MULTI.with_(channels=PH_MAGNETIC), 7, 3),
+                                       (MULTI.with_(channels=PH_CHARGE), 4, 4),
+                                       (MULTI.with_(channels=PH_MAGNETIC | PH_CHARGE), 5, 2),
+                                       (W8, 9, 4), (W8.with_(channels=PH_CHARGE), 3, 3)],
+                         ids=["multi-mag", "multi-chg", "multi-mag+chg", "w8-mag", "w8-chg"])
+def test_batched_fp32_packed_mfma(w, count, B, g_in, acc):
+    """Packed operands, direct term on MFMA (one measurement per MFMA pair):
+    several passes with a ragged last one, every accumulator kind."""
+    g4 = g4mod()
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=1, g_in=g_in, acc=acc, batch=B,
+                     flags=g4.G4_F_PACKED | g4.G4_F_MFMA)
+    got, st = run_slice(cfg, to_dev(gu, g_in), to_dev(gd, g_in), s)
+    assert st["variant"] == g4.G4_VARIANT_PACKED_MFMA and st["tile"] == 16
+    assert st["launches"] == -(-count // B)
+    check(got, oracle_out(w, count, w.channels), 1e-6)
+
+
 def test_deep_long_pass():
     """Passes of 16 measurements: the three-buffer rotation wraps several times."""
     g4 = g4mod()
@@ -213,7 +241,7 @@ def test_edge_shapes_every_variant(w):
     got, _ = run_slice(config_for(w, mode=0), to_dev(gu, 0), to_dev(gd, 0), s)
     check(got, want, 1e-12)
     ran = 0
-    for flags in (0, g4.G4_F_MFMA, g4.G4_F_PACKED, g4.G4_F_PACKED_DEEP):
+    for flags in (0, g4.G4_F_MFMA, g4.G4_F_PACKED, g4.G4_F_PACKED_DEEP, g4.G4_F_PACKED | g4.G4_F_MFMA):
         cfg = config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=2, flags=flags)
         try:
             g4.g4_slice_size(cfg)
@@ -442,7 +470,11 @@ def test_set_plan_switches_variant_and_batch():
         g4.g4_accumulate(h, du[6:8], dd[6:8], s[6:8])
         g4.g4_set_plan(h, 0, 0, g4.G4_VARIANT_PACKED_DEEP)  # deep blocks, same pass size
         assert g4.g4_stats(h)["variant"] == 3
-        g4.g4_accumulate(h, du[8:], dd[8:], s[8:])
+        g4.g4_accumulate(h, du[8:9], dd[8:9], s[8:9])
+        g4.g4_set_plan(h, 0, 0, g4.G4_VARIANT_PACKED_MFMA)  # packed, direct term on MFMA
+        st = g4.g4_stats(h)
+        assert st["variant"] == 4 and st["tile"] == 16
+        g4.g4_accumulate(h, du[9:], dd[9:], s[9:])
         got = g4.g4_readback(h, 1).reshape(want[1].shape)
         with pytest.raises(g4.G4Error):
             g4.g4_set_plan(h, 0, 5, 0)                # above the allocated max_batch
