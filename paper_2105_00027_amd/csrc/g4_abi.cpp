@@ -224,9 +224,11 @@ int validate(const g4_config *c, Plan *p) {
     if (packed) {
         const bool deep = P.variant == G4_VARIANT_PACKED_DEEP;
         const int T2 = std::min(P.tile, c->nw);
-        const PackedGeom g = packed_geom(c->nw, T2, P.mgroup, (int)c->channels, deep);
+        const bool areg = P.variant == G4_VARIANT_PACKED &&
+                          packed_a_in_regs(c->nw, P.tile, P.mgroup, (int)c->channels, deep);
+        const PackedGeom g = packed_geom(c->nw, T2, P.mgroup, (int)c->channels, deep, areg);
         if (P.tile % 2 || T2 % 2) return fail(G4_E_UNSUPPORTED, "packed operands need an even tile (tile=%d)", P.tile);
-        if (packed_slots(g, deep) > kPackedSlots)
+        if (packed_slots(g, deep) > (areg ? kPackedSlotsAReg : kPackedSlots))
             return fail(G4_E_UNSUPPORTED, "packed operands: %d staging chunks per tile above %d", g.nbuf,
                         kPackedSlots * packed_threads(deep));
         if (P.pack_stride >= (1ull << 31))

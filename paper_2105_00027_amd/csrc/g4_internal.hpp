@@ -96,7 +96,8 @@ struct PackedGeom {
     int nA, nB;     // direct vectors a (planes x nw) and b (planes x T2), chunks
     int nbuf;       // chunks per buffer
 };
-__host__ __device__ constexpr PackedGeom packed_geom(int nw, int T2, int M, int channels, bool x_in_lds) {
+__host__ __device__ constexpr PackedGeom packed_geom(int nw, int T2, int M, int channels, bool x_in_lds,
+                                                     bool a_in_regs = false) {
     PackedGeom g{};
     const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
     const int yc = T2 + M - 1;
@@ -105,11 +106,21 @@ __host__ __device__ constexpr PackedGeom packed_geom(int nw, int T2, int M, int 
     g.nZ = (channels & CH_PP) ? (T2 + M - 1) * (nw + M - 1) : 0;
     g.nX = x_in_lds ? T2 * nw : 0;
     g.nG = g.nY + g.nZ + g.nX;
-    g.nA = nph * M * nw / 2;
+    g.nA = a_in_regs ? 0 : nph * M * nw / 2;
     g.nB = nph * M * T2 / 2;
     g.nbuf = g.nG + g.nA + g.nB;
     return g;
 }
+// Two-buffer packed kernel, one PH channel and no PP, plane groups of 8,
+// 128 <= nw <= 256 and at most two K2 rows per thread: the direct vector
+// a(Q, K1) (8 x nw complex64, a quarter of the staged chunks at nw = 128) goes
+// into registers one measurement ahead instead of LDS, so that three blocks
+// fit a CU.  Such a tile stages at most (nw+7) x 9 + 8 chunks: 10 copy slots.
+__host__ __device__ constexpr bool packed_a_in_regs(int nw, int tile, int mgroup, int channels, bool deep) {
+    return !deep && nw >= 128 && nw <= 256 && mgroup == 8 && tile <= 2 * (256 / nw) && !(channels & CH_PP) &&
+           ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0) == 1;
+}
+constexpr int kPackedSlotsAReg = 10;
 // per-thread staging slots of the packed kernel (256 threads, one chunk each)
 constexpr int kPackedSlots = 16;
 // measurements per pass at most (the packed kernel keeps the pass's weights in LDS)

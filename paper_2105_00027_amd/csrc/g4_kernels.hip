@@ -274,7 +274,8 @@ size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims
     if (variant == 2 || variant == 3 || variant == 4) {
         // staging buffers of 16-byte chunks, rotating by measurement
         const bool deep = variant == 3;
-        return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels, deep), deep);
+        const bool areg = variant == 2 && packed_a_in_regs(d.nw, tile, mgroup, channels, deep);
+        return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels, deep, areg), deep);
     }
     // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct
     // vectors (two copies, by measurement parity, for the MFMA variant)

@@ -74,10 +74,10 @@ __device__ __forceinline__ void wait_vm(int n) {
 // block (its G matrix followed by its direct vectors, see pack_gather_kernel);
 // chunks past the tile's end take offset 0 and land in the buffer's padding.
 // G rows are indexed k*nwg + i, packed columns k*pcb + i.
-template <int NTH, int CH>
+template <int NTH, int CH, int SLOTS>
 __device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const PackedGeom &pg, int tid, int q,
                                                int k1, int k2, int c0, int T2, int M, int m_lo, int p0,
-                                               unsigned (&off)[kPackedSlots]) {
+                                               unsigned (&off)[SLOTS]) {
     using CI = ChanInfo<CH>;
     const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
     const int zc = nw + M - 1;
@@ -90,7 +90,7 @@ __device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const Packed
     const int64_t dslot = a.dir_slot_stride;                 // complex64 values
     const int64_t adelta = static_cast<const char *>(a.dir_a) - static_cast<const char *>(a.pack);
     const int64_t bdelta = static_cast<const char *>(a.dir_b) - static_cast<const char *>(a.pack);
-    static_for<0, kPackedSlots>([&](auto k) {
+    static_for<0, SLOTS>([&](auto k) {
         const int e = k * NTH + tid;
         int64_t o = 0;
         if (e < pg.nY) {
@@ -128,9 +128,10 @@ __device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const Packed
 // measurement (lanes past the tile's chunks copy the block's first chunk into
 // the buffer's padding), and loads complete in issue order, so waiting until
 // S*(copies issued after measurement b's) are outstanding means b's copies
-// have landed.
-template <int EPT, int MG, int CH, int NTH, int NB>
-__global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
+// have landed.  AR: the direct vector a(Q, K1) is read into registers one
+// measurement ahead instead of being staged in LDS (packed_a_in_regs).
+template <int EPT, int MG, int CH, int NTH, int NB, bool AR = false>
+__global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateArgs a) {
     using V = float2;
     using CI = ChanInfo<CH>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -142,7 +143,8 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
     // tile); the measurement loop then has no memory read of its own that the
     // compiler would wait for (and with it for the copies in flight)
     constexpr bool XL = NB > 2;      // G(K2,K1) rows staged in LDS (deep form) or read into registers
-    const int S_full = (packed_geom(nw, min(a.tile, nw), MG, CH, XL).nbuf + NTH - 1) / NTH;
+    static_assert(!AR || (CI::nph == 1 && !XL), "a in registers: one PH channel, two-buffer form");
+    const int S_full = (packed_geom(nw, min(a.tile, nw), MG, CH, XL, AR).nbuf + NTH - 1) / NTH;
     float *sg = reinterpret_cast<float *>(smem_raw + NB * S_full * NTH * 16);
     if (tid < a.batch) sg[tid] = (float)a.sign[tid];
 
@@ -154,22 +156,23 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
         const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
         const int k1 = it.y, k2 = it.z, c0 = it.w;
         const int T2 = min(a.tile, nw - c0);
-        const PackedGeom pg = packed_geom(nw, T2, M, CH, XL);
+        const PackedGeom pg = packed_geom(nw, T2, M, CH, XL, AR);
         const int zc = nw + M - 1;
 
         // ---- per-thread copy slots (S cover a full tile) ------------------------
         const int S = S_full;
         const int ldp = a.ldp;
         const int rowX = k2 * nwg + c0, colX = k1 * a.pcb;
-        unsigned off[kPackedSlots];
-        packed_offsets<NTH, CH>(a, pg, tid, q, k1, k2, c0, T2, M, m_lo, p0, off);
+        constexpr int SLOTS = AR ? kPackedSlotsAReg : kPackedSlots;
+        unsigned off[SLOTS];
+        packed_offsets<NTH, CH, SLOTS>(a, pg, tid, q, k1, k2, c0, T2, M, m_lo, p0, off);
         const int bufb = S * NTH * 16;   // bytes per buffer
         const unsigned lds_base = (unsigned)(uintptr_t)(lds_t *)smem_raw;
         const unsigned lds0 = lds_base + wave * 64 * 16;
         auto issue = [&](int b) __attribute__((always_inline)) {
             const char *base = static_cast<const char *>(a.pack) + (int64_t)b * a.pack_stride;
             const unsigned buf = lds0 + (b % NB) * bufb;
-            static_for<0, kPackedSlots>([&](auto k) {
+            static_for<0, SLOTS>([&](auto k) {
                 if (k < S) dma16(base, off[k], buf + k * NTH * 16);
             });
         };
@@ -199,14 +202,28 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
             });
         };
         static_for<0, EPT>([&](auto j) { xr[j] = xn[j] = float4{0.f, 0.f, 0.f, 0.f}; });
+        // AR: this thread's a(Q, K1) for the group's planes (clamped to the
+        // group's last plane, whose values the partial path does not use)
+        V ar[AR ? MG : 1], an[AR ? MG : 1];
+        auto load_a = [&](int b, V *dst) __attribute__((always_inline)) {
+            const V *pa = reinterpret_cast<const V *>(static_cast<const char *>(a.dir_a) +
+                                                      (int64_t)b * a.pack_stride) + k1 * nw + i1;
+            static_for<0, MG>([&](auto m) { dst[m] = pa[(int64_t)(p0 + min((int)m, M - 1)) * n]; });
+        };
         for (int b = 0; b < NB - 1 && b < a.batch; ++b) issue(b);
         if (!XL && act && a.batch > 0) load_x(0, xr);
+        if constexpr (AR) {
+            if (act && a.batch > 0) load_a(0, ar);
+        }
         for (int b = 0; b < a.batch; ++b) {
             // copies issued after b's: those of b+1 .. b+NB-2 that exist
             wait_vm(S * (min(b + NB - 2, a.batch - 1) - b));
             __syncthreads();                 // b's copies landed everywhere; b-1's buffer is free
             if (b + NB - 1 < a.batch) issue(b + NB - 1);
             if (!XL && act && b + 1 < a.batch) load_x(b + 1, xn);
+            if constexpr (AR) {
+                if (act && b + 1 < a.batch) load_a(b + 1, an);
+            }
             if (!act) continue;
             const float s = sg[b];
             const float4 *L = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
@@ -240,7 +257,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
                         if (CI::pp) o.z[j] = Lz[(mm + T2 - 1 - i2l) * zc + mm + nw - 1 - i1];
                         static_for<0, CI::nph>([&](auto c) { o.bb[c][j] = ld(Bt + (c * M + mm) * T2 + i2l); });
                     });
-                    static_for<0, CI::nph>([&](auto c) { o.a[c] = ld(At + (c * M + mm) * nw + i1); });
+                    if constexpr (!AR) static_for<0, CI::nph>([&](auto c) { o.a[c] = ld(At + (c * M + mm) * nw + i1); });
                 };
                 auto compute = [&](auto m, const Ops &o) __attribute__((always_inline)) {
                     static_for<0, EPT>([&](auto j) {
@@ -249,7 +266,10 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
                             const V yu{o.y[j].x, o.y[j].y}, yd{o.y[j].z, o.y[j].w};
                             static_for<0, CI::nph>([&](auto c) {
                                 V &r = acc[c][j][m];
-                                cmac(r, o.a[c], o.bb[c][j]);
+                                V av;
+                                if constexpr (AR) av = ar[m];
+                                else av = o.a[c];
+                                cmac(r, av, o.bb[c][j]);
                                 cmac(r, xu[j], yu);
                                 cmac(r, xd[j], yd);
                             });
@@ -282,6 +302,7 @@ __global__ __launch_bounds__(NTH, 2) void update_packed_kernel(UpdateArgs a) {
             if (full && r0 + (EPT - 1) * RP < T2) run(std::true_type{});
             else run(std::false_type{});
             if (!XL) static_for<0, EPT>([&](auto j) { xr[j] = xn[j]; });
+            if constexpr (AR) static_for<0, MG>([&](auto m) { ar[m] = an[m]; });
         }
         if (!act) continue;
         const int64_t nn = (int64_t)n * n;
@@ -339,15 +360,15 @@ __global__ __launch_bounds__(256, 2) void update_packed_mfma_kernel(UpdateArgs a
         const PackedGeom pg = packed_geom(nw, TR, M, CH, false);
         const int ldp = a.ldp;
         const int rowX = k2 * nwg + c0, colX = k1 * a.pcb;
-        unsigned off[kPackedSlots];
-        packed_offsets<NTH, CH>(a, pg, tid, q, k1, k2, c0, TR, M, m_lo, p0, off);
+        unsigned off[S];
+        packed_offsets<NTH, CH, S>(a, pg, tid, q, k1, k2, c0, TR, M, m_lo, p0, off);
         const int bufb = S * NTH * 16;
         const unsigned lds0 = (unsigned)(uintptr_t)(lds_t *)smem_raw + wave * 64 * 16;
         auto issue = [&](int b) __attribute__((always_inline)) {
             const char *base = static_cast<const char *>(a.pack) + (int64_t)b * a.pack_stride;
             const unsigned buf = lds0 + (b % NB) * bufb;
-            static_for<0, kPackedSlots>([&](auto k) {
-                if (k < S) dma16(base, off[k], buf + k * NTH * 16);
+            static_for<0, S>([&](auto k) {
+                dma16(base, off[k], buf + k * NTH * 16);
             });
         };
         f4 re[CI::count][MG], im[CI::count][MG];
@@ -474,9 +495,22 @@ hipError_t launch_packed_mfma_ch(int channels, int nitems, size_t lds, const Upd
 #endif
 
 template <int MG, int NTH, int NB>
-hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, hipStream_t s) {
+hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, hipStream_t s,
+                            bool areg) {
     const void *fn = nullptr;
-    switch (channels) {
+#if G4_EPT <= 2
+    if constexpr (MG == 8 && NB == 2) {
+        if (areg) {
+            switch (channels) {
+                case 1: fn = reinterpret_cast<const void *>(&update_packed_kernel<G4_EPT, 8, 1, NTH, 2, true>); break;
+                case 2: fn = reinterpret_cast<const void *>(&update_packed_kernel<G4_EPT, 8, 2, NTH, 2, true>); break;
+                default: return hipErrorInvalidValue;
+            }
+        }
+    }
+#endif
+    if (areg && !fn) return hipErrorInvalidValue;
+    if (!fn) switch (channels) {
 #define G4_CASE(CHV)                                                                          \
     case CHV:                                                                                 \
         fn = reinterpret_cast<const void *>(&update_packed_kernel<G4_EPT, MG, CHV, NTH, NB>); \
@@ -495,11 +529,11 @@ hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateAr
 
 template <int NTH, int NB>
 hipError_t launch_packed_mg(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
-                            hipStream_t s) {
+                            hipStream_t s, bool areg) {
     switch (mgroup) {
-        case 1: return launch_packed_ch<1, NTH, NB>(channels, nitems, lds, a, s);
-        case 4: return launch_packed_ch<4, NTH, NB>(channels, nitems, lds, a, s);
-        case 8: return launch_packed_ch<8, NTH, NB>(channels, nitems, lds, a, s);
+        case 1: return launch_packed_ch<1, NTH, NB>(channels, nitems, lds, a, s, areg);
+        case 4: return launch_packed_ch<4, NTH, NB>(channels, nitems, lds, a, s, areg);
+        case 8: return launch_packed_ch<8, NTH, NB>(channels, nitems, lds, a, s, areg);
         default: return hipErrorInvalidValue;
     }
 }
@@ -514,9 +548,10 @@ hipError_t launch_packed_mg(int channels, int mgroup, int nitems, size_t lds, co
 // blocks, three buffers (built for one and two K2 rows per thread)
 hipError_t G4_PNAME(G4_EPT)(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
                             hipStream_t s, bool deep) {
-    if (!deep) return upd::launch_packed_mg<256, 2>(channels, mgroup, nitems, lds, a, s);
+    const bool areg = packed_a_in_regs(a.d.nw, a.tile, mgroup, channels, deep);
+    if (!deep) return upd::launch_packed_mg<256, 2>(channels, mgroup, nitems, lds, a, s, areg);
 #if G4_EPT <= 2
-    return upd::launch_packed_mg<512, 3>(channels, mgroup, nitems, lds, a, s);
+    return upd::launch_packed_mg<512, 3>(channels, mgroup, nitems, lds, a, s, false);
 #else
     return hipErrorInvalidValue;
 #endif

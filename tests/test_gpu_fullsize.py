@@ -83,14 +83,16 @@ def test_batched_full_size(acc, flags):
     assert rel_fro(got, want) <= 1e-6
 
 
-def test_ring_share_slice():
+@pytest.mark.parametrize("flags", [0, 16], ids=["valu", "packed"])
+def test_ring_share_slice(flags):
     """6x6, Nw 128, Nq 36, Nwex 16, rank 3's 1/8 slice (24.5 GB): 8 walkers' buffers
-    of 16 measurements applied in ring order 3, 2, 1, 0, 7, 6, 5, 4."""
+    of 16 measurements applied in ring order 3, 2, 1, 0, 7, 6, 5, 4 (packed: 4-row
+    tiles, the direct vector a read into registers)."""
     g4 = g4mod()
     S, rank = 8, 3
     per = C4_RING.measurements // S
     w = C4_RING.with_(q_begin=rank * 72, q_end=(rank + 1) * 72)
-    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=per))
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=per, flags=flags))
     order = [(rank - j) % S for j in range(S)]
     try:
         for walker in order:

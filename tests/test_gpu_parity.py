@@ -112,6 +112,30 @@ def test_packed_channel_subsets(channels, flag, variant):
     check(got, oracle_out(w, 5, channels), 1e-6)
 
 
+# Packed kernel with the direct vector a(Q, K1) read into registers instead of
+# LDS: one PH channel, no PP, plane groups of 8, nw 128..256, at most two K2
+# rows per thread.  NW128's groups start mid-transfer (m = 4) and end with one
+# plane; NW256A has groups of 6 (nwex = 6): partial groups of the 8-plane kernel.
+NW256A = Workload("nw256a", lx=2, ly=1, nw=256, nwex=6, nq=2, q_begin=2, q_end=11, beta=12.0,
+                  seed=28, wid=28, channels=PH_MAGNETIC)
+
+
+@pytest.mark.parametrize("g_in", [0, 1], ids=["c128-in", "c64-in"])
+@pytest.mark.parametrize("acc", [0, 1, 2], ids=["acc-c128", "acc-kahan", "acc-c64"])
+@pytest.mark.parametrize("w,count,B,tile", [(NW128.with_(channels=PH_MAGNETIC), 5, 2, 4),
+                                            (NW128.with_(channels=PH_MAGNETIC), 4, 4, 2),
+                                            (NW128.with_(channels=PH_CHARGE), 3, 2, 0),
+                                            (NW256A, 3, 2, 0), (NW256A.with_(channels=PH_CHARGE), 4, 3, 2)],
+                         ids=["nw128-mag-t4", "nw128-mag-t2", "nw128-chg", "nw256-mag", "nw256-chg-t2"])
+def test_packed_direct_vector_in_registers(w, count, B, tile, g_in, acc):
+    g4 = g4mod()
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=1, g_in=g_in, acc=acc, batch=B, tile=tile, flags=g4.G4_F_PACKED)
+    got, st = run_slice(cfg, to_dev(gu, g_in), to_dev(gd, g_in), s)
+    assert st["variant"] == 2 and st["launches"] == -(-count // B)
+    check(got, oracle_out(w, count, w.channels), 1e-6)
+
+
 # Packed operands with the direct term on the matrix cores: nw = 64, 16-row
 # tiles, PH channels; MULTI has plane groups of 3 (nwex = 3, partial groups of
 # the 4-plane kernel), W8 groups of 8 starting mid-group (m = 3) and ending
