@@ -144,7 +144,8 @@ def main():
                     help="keep the default plan instead of timing the candidates first")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--acc", default="c128", choices=["c128", "kahan"])
-    ap.add_argument("--mfma", action="store_true", help="direct term on the matrix cores")
+    ap.add_argument("--mfma", action="store_true",
+                    help="direct term on the matrix cores (with --packed: the packed MFMA-direct kernel)")
     ap.add_argument("--packed", action="store_true",
                     help="packed operands copied straight into LDS (the autotuner may switch)")
     ap.add_argument("--deep", action="store_true",

@@ -183,11 +183,14 @@ SPLIT_BAR = {2: 2.0 ** -15 + 1e-6, 3: 1e-6}
 
 @pytest.mark.parametrize("prod", [2, 3], ids=["bf16x2", "f16x2"])
 @pytest.mark.parametrize("flags", [0, 16], ids=["valu", "packed"])
-@pytest.mark.parametrize("w,count,B", [(RAGGED, 11, 9), (MULTI, 4, 4), (NW128, 5, 4)],
-                         ids=lambda x: getattr(x, "name", str(x)))
+@pytest.mark.parametrize("w,count,B", [(RAGGED, 11, 9), (MULTI, 4, 4), (NW128, 5, 4),
+                                       (NW128.with_(channels=PH_MAGNETIC), 5, 4)],
+                         ids=["ragged", "multi-tile", "nw128", "nw128-mag"])
 def test_split_precision_direct_term(w, count, B, flags, prod):
     """Direct term as a GEMM over the pass on MFMA from hi+lo split operands;
-    B = 9 leaves a partial chunk of 8 measurements in every pass."""
+    B = 9 leaves a partial chunk of 8 measurements in every pass.  nw128-mag
+    runs the packed kernel form that reads the direct vector a into registers,
+    with its direct term switched off (b read as zeros)."""
     gu, gd, s = host_inputs(w, count)
     cfg = config_for(w, mode=1, prod=prod, g_in=1, acc=1, batch=B, flags=flags)
     got, _ = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
