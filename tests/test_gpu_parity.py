@@ -353,11 +353,16 @@ def test_one_hot_support(mode, prod, flags):
 
 
 def test_determinism_bitwise():
-    w = MULTI
-    gu, gd, s = host_inputs(w, 3)
-    for kw in (dict(mode=0), dict(mode=1, prod=1, g_in=1, acc=1, batch=3),
-               dict(mode=1, prod=1, g_in=1, acc=0, batch=2, flags=16),
-               dict(mode=1, prod=1, g_in=1, acc=0, batch=3, flags=32)):
+    """Every slice entry is written by one thread, no atomics: two runs agree
+    bit for bit (also a race check of the LDS staging)."""
+    mag = MULTI.with_(channels=PH_MAGNETIC)
+    for w, kw in ((MULTI, dict(mode=0)), (MULTI, dict(mode=1, prod=1, g_in=1, acc=1, batch=3)),
+                  (MULTI, dict(mode=1, prod=1, g_in=1, acc=0, batch=2, flags=16)),
+                  (MULTI, dict(mode=1, prod=1, g_in=1, acc=0, batch=3, flags=32)),
+                  (mag, dict(mode=1, prod=1, g_in=1, acc=0, batch=3, flags=24)),       # packed, MFMA direct
+                  (NW128.with_(channels=PH_MAGNETIC),
+                   dict(mode=1, prod=1, g_in=1, acc=0, batch=2, flags=16))):            # a in registers
+        gu, gd, s = host_inputs(w, 3)
         cfg = config_for(w, **kw)
         a, _ = run_slice(cfg, to_dev(gu, cfg.c.g_in), to_dev(gd, cfg.c.g_in), s)
         b, _ = run_slice(cfg, to_dev(gu, cfg.c.g_in), to_dev(gd, cfg.c.g_in), s)
