@@ -129,22 +129,27 @@ __device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const Packed
 // the buffer's padding), and loads complete in issue order, so waiting until
 // S*(copies issued after measurement b's) are outstanding means b's copies
 // have landed.  AR: the direct vector a(Q, K1) is read into registers one
-// measurement ahead instead of being staged in LDS (packed_a_in_regs).
-template <int EPT, int MG, int CH, int NTH, int NB, bool AR = false>
+// measurement ahead instead of being staged in LDS (packed_a_in_regs).  NWC:
+// nw fixed at compile time (0: taken from the arguments); the tile is then
+// EPT * NTH / NWC rows, and a full tile's LDS operand addresses are one
+// per-thread base plus constant offsets.
+template <int EPT, int MG, int CH, int NTH, int NB, bool AR = false, int NWC = 0>
 __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateArgs a) {
     using V = float2;
     using CI = ChanInfo<CH>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
+    const int nw = NWC ? NWC : a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
+    const int tile = NWC ? EPT * (NTH / NWC) : a.tile;
 
     // the pass's weights as floats after the NB buffers (sized for a full
     // tile); the measurement loop then has no memory read of its own that the
     // compiler would wait for (and with it for the copies in flight)
     constexpr bool XL = NB > 2;      // G(K2,K1) rows staged in LDS (deep form) or read into registers
     static_assert(!AR || (CI::nph == 1 && !XL), "a in registers: one PH channel, two-buffer form");
-    const int S_full = (packed_geom(nw, min(a.tile, nw), MG, CH, XL, AR).nbuf + NTH - 1) / NTH;
+    const PackedGeom pgf = packed_geom(nw, min(tile, nw), MG, CH, XL, AR);   // a full tile
+    const int S_full = (pgf.nbuf + NTH - 1) / NTH;
     float *sg = reinterpret_cast<float *>(smem_raw + NB * S_full * NTH * 16);
     if (tid < a.batch) sg[tid] = (float)a.sign[tid];
 
@@ -155,9 +160,8 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         const int4 gr = a.t.groups[it.x];
         const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
         const int k1 = it.y, k2 = it.z, c0 = it.w;
-        const int T2 = min(a.tile, nw - c0);
+        const int T2 = min(tile, nw - c0);
         const PackedGeom pg = packed_geom(nw, T2, M, CH, XL, AR);
-        const int zc = nw + M - 1;
 
         // ---- per-thread copy slots (S cover a full tile) ------------------------
         const int S = S_full;
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
                 static_for<0, MG>([&](auto m) { acc[c][j][m] = V{0.f, 0.f}; });
             });
         });
-        const bool full = (T2 == a.tile) && (M == MG);
+        const bool full = (T2 == tile) && (M == MG);
         // two-buffer form: this thread's G(K2,K1) values straight from the packed
         // block into registers, one measurement ahead (the loop waits for every
         // outstanding load before its barrier, so these add no wait)
@@ -227,9 +231,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
             if (!act) continue;
             const float s = sg[b];
             const float4 *L = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
-            const float4 *Ly = L, *Lz = L + pg.nY, *Lx = L + pg.nY + pg.nZ;
-            const V *At = reinterpret_cast<const V *>(L + pg.nG);
-            const V *Bt = At + 2 * pg.nA;
+            const float4 *Lx = L + pg.nY + pg.nZ;
             // G(K2,K1) times -s_b for the PH exchange (its minus folded in), +s_b for PP
             V xu[EPT], xd[EPT];
             static_for<0, EPT>([&](auto j) {
@@ -249,15 +251,21 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
             };
             auto run = [&](auto FULL) __attribute__((always_inline)) {
                 constexpr bool F = decltype(FULL)::value;
+                // a full tile's geometry is pgf (compile-time when nw is)
+                const PackedGeom &g = F ? pgf : pg;
+                const int Mx = F ? MG : M, T2x = F ? tile : T2, zcx = nw + Mx - 1;
+                const float4 *Ly = L, *Lz = L + g.nY;
+                const V *At = reinterpret_cast<const V *>(L + g.nG);
+                const V *Bt = At + 2 * g.nA;
                 auto load = [&](int m, Ops &o) __attribute__((always_inline)) {
                     const int mm = F ? m : min(m, M - 1);
                     static_for<0, EPT>([&](auto j) {
                         const int i2l = F ? r0 + j * RP : min(r0 + j * RP, T2 - 1);
-                        if (CI::ph) o.y[j] = Ly[(i1 + mm) * pg.ycs + i2l + mm];
-                        if (CI::pp) o.z[j] = Lz[(mm + T2 - 1 - i2l) * zc + mm + nw - 1 - i1];
-                        static_for<0, CI::nph>([&](auto c) { o.bb[c][j] = ld(Bt + (c * M + mm) * T2 + i2l); });
+                        if (CI::ph) o.y[j] = Ly[(i1 + mm) * g.ycs + i2l + mm];
+                        if (CI::pp) o.z[j] = Lz[(mm + T2x - 1 - i2l) * zcx + mm + nw - 1 - i1];
+                        static_for<0, CI::nph>([&](auto c) { o.bb[c][j] = ld(Bt + (c * Mx + mm) * T2x + i2l); });
                     });
-                    if constexpr (!AR) static_for<0, CI::nph>([&](auto c) { o.a[c] = ld(At + (c * M + mm) * nw + i1); });
+                    if constexpr (!AR) static_for<0, CI::nph>([&](auto c) { o.a[c] = ld(At + (c * Mx + mm) * nw + i1); });
                 };
                 auto compute = [&](auto m, const Ops &o) __attribute__((always_inline)) {
                     static_for<0, EPT>([&](auto j) {
@@ -505,6 +513,19 @@ hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateAr
                 case 1: fn = reinterpret_cast<const void *>(&update_packed_kernel<G4_EPT, 8, 1, NTH, 2, true>); break;
                 case 2: fn = reinterpret_cast<const void *>(&update_packed_kernel<G4_EPT, 8, 2, NTH, 2, true>); break;
                 default: return hipErrorInvalidValue;
+            }
+        }
+    }
+#endif
+#if G4_EPT == 2
+    // nw = 64, 8-row tiles, plane groups of 8, PH channels: the compile-time-nw copy
+    if constexpr (MG == 8 && NTH == 256 && NB == 2) {
+        if (!areg && a.d.nw == 64 && a.tile == 8) {
+            switch (channels) {
+                case 1: fn = reinterpret_cast<const void *>(&update_packed_kernel<2, 8, 1, 256, 2, false, 64>); break;
+                case 2: fn = reinterpret_cast<const void *>(&update_packed_kernel<2, 8, 2, 256, 2, false, 64>); break;
+                case 3: fn = reinterpret_cast<const void *>(&update_packed_kernel<2, 8, 3, 256, 2, false, 64>); break;
+                default: break;
             }
         }
     }

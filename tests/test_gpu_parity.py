@@ -164,6 +164,23 @@ def test_batched_fp32_packed_mfma(w, count, B, g_in, acc):
     check(got, oracle_out(w, count, w.channels), 1e-6)
 
 
+@pytest.mark.parametrize("g_in", [0, 1], ids=["c128-in", "c64-in"])
+@pytest.mark.parametrize("acc", [0, 1, 2], ids=["acc-c128", "acc-kahan", "acc-c64"])
+@pytest.mark.parametrize("channels", [PH_MAGNETIC, PH_CHARGE, PH_MAGNETIC | PH_CHARGE],
+                         ids=["mag", "chg", "mag+chg"])
+def test_packed_nw64_tile8(channels, g_in, acc):
+    """The packed kernel's compile-time copy for nw = 64, 8-row tiles and plane
+    groups of 8 (W8: a partial group at each end of the slice, full ones
+    between), three passes with a ragged last one."""
+    g4 = g4mod()
+    w = W8.with_(channels=channels)
+    gu, gd, s = host_inputs(w, 7)
+    cfg = config_for(w, mode=1, prod=1, g_in=g_in, acc=acc, batch=3, tile=8, flags=g4.G4_F_PACKED)
+    got, st = run_slice(cfg, to_dev(gu, g_in), to_dev(gd, g_in), s)
+    assert st["variant"] == 2 and st["tile"] == 8
+    check(got, oracle_out(w, 7, channels), 1e-6)
+
+
 def test_deep_long_pass():
     """Passes of 16 measurements: the three-buffer rotation wraps several times."""
     g4 = g4mod()
