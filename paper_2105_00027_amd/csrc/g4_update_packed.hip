@@ -1,6 +1,9 @@
-// Slice-update kernel with packed operands (batched FP32), for gfx950.
+// Slice-update kernels with packed operands (batched FP32), for gfx950.
 // Compiled once per G4_EPT (K2 rows per thread), for every channel
-// combination and plane-group bound.
+// combination and plane-group bound; with G4_EPT = 2 also the copies with the
+// direct vector in registers (one PH channel, nw >= 128) and the copy for
+// nw = 64 with 8-row tiles, and with G4_EPT = 4 the variant whose direct term
+// runs on the matrix cores (update_packed_mfma_kernel).
 //
 // Same arithmetic, work tiles, thread mapping and accumulator epilogue as the
 // batched FP32 VALU kernel in g4_update.hpp; what differs is how a tile's
