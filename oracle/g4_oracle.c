@@ -154,6 +154,8 @@ static int check_shape(const oracle_shape *s, int channel) {
  * (q_end-q_begin)*N*N values).  g_up/g_dn hold batch matrices of Ng x Ng.
  * If comp is non-NULL the sums are Neumaier-compensated per real component and
  * comp (same size as g4) holds the running compensation; value = g4 + comp.
+ * (Pinned against exact rational sums of inputs whose plain FP64 sum loses
+ * whole terms.)
  * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on a bad shape.
  */
 int oracle_accumulate(const oracle_shape *s, int channel, const double *g_up, const double *g_dn,

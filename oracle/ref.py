@@ -25,11 +25,14 @@ _lib = None
 
 
 def lib():
+    """The compiled oracle.  G4_ORACLE_LIB may name another build of the same
+    source (the mutation tests load copies with a planted mistake this way)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("G4_ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.oracle_accumulate.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, dp, dp, dp,
                                         ctypes.c_int, dp, dp, ctypes.c_int]

@@ -1,0 +1,104 @@
+"""Planted mistakes in the oracle: each must fail at least one pin.
+
+A pin that a plausible mistake passes pins nothing.  Each case below copies
+oracle/g4_oracle.c, plants one mistake by exact text substitution, builds the
+copy with the oracle's own compiler flags into a temporary directory, and
+runs the oracle's pin tests against it (G4_ORACLE_LIB points the oracle's
+loader at the copy) in a child process, which must fail.  The pins are the
+closed forms, the brute-force Wick contraction, the array formulation, the
+invariants and the exact compensated sums; the numpy per-entry oracle's
+comparison with the C oracle is left out, so that only the pins count.
+
+Everything runs on the CPU; the HIP library is not involved.
+"""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+from oracle import build as oracle_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_wick.py",
+        "tests/test_oracle_arrays.py", "tests/test_oracle_invariants.py",
+        "tests/test_oracle_compensated.py"]
+
+# name -> (text in the oracle source, replacement)
+MUTANTS = {
+    # compensated accumulation
+    "compensation dropped": (
+        "cc[j] += (sum - tt) + x[j];\n                        else\n"
+        "                            cc[j] += (x[j] - tt) + sum;",
+        "(void)0;\n                        else\n                            (void)0;"),
+    "compensation sign flipped": (
+        "cc[j] += (sum - tt) + x[j];", "cc[j] -= (sum - tt) + x[j];"),
+    "compensation without the magnitude test": (
+        "if (fabs(sum) >= fabs(x[j]))", "if (1)"),
+    # particle-hole terms
+    "exchange sign": (
+        "t = c_sub(direct, c_add(ex_u, ex_d));", "t = c_add(direct, c_add(ex_u, ex_d));"),
+    "k1-q for k1+q": (
+        "g_index(s, mom_add(s, k1, q), n1 + m);", "g_index(s, mom_sub(s, k1, q), n1 + m);"),
+    "transposed exchange operand": (
+        "g_at(gu, ng, r_k1q, r_k2q)", "g_at(gu, ng, r_k2q, r_k1q)"),
+    "transposed direct operand": (
+        "cplx u1 = g_at(gu, ng, r_k1q, r_k1), d1 = g_at(gd, ng, r_k1q, r_k1);",
+        "cplx u1 = g_at(gu, ng, r_k1, r_k1q), d1 = g_at(gd, ng, r_k1, r_k1q);"),
+    "charge and magnetic spin weights swapped": (
+        "cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);",
+        "cplx a = channel == ORACLE_PH_MAGNETIC ? c_add(u1, d1) : c_sub(u1, d1);"),
+    # particle-particle term, Eq. (1)
+    "transposed PP operand": (
+        "cplx up = c_mul(g_at(gu, ng, r_qk2, r_qk1)", "cplx up = c_mul(g_at(gu, ng, r_qk1, r_qk2)"),
+    "PP same spin for the opposite spin": (
+        "g_at(gd, ng, r_k2, r_k1));\n        cplx dn", "g_at(gu, ng, r_k2, r_k1));\n        cplx dn"),
+    "PP frequency n2 for n1 in Q-K1": (
+        "mom_sub(s, q, k1), m - n1 - 1)", "mom_sub(s, q, k1), m - n2 - 1)"),
+    "PP frequency off by one": (
+        "mom_sub(s, q, k2), m - n2 - 1)", "mom_sub(s, q, k2), m - n2)"),
+}
+
+
+def _build_mutant(tmp, name, old, new):
+    with open(oracle_build.SRC) as f:
+        src = f.read()
+    assert src.count(old) == 1, "mutation site not found once for %r" % name
+    path = os.path.join(tmp, "mutant_%d.c" % abs(hash(name)))
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    lib = path[:-2] + ".so"
+    subprocess.run(["gcc", *oracle_build.CFLAGS, path, "-o", lib, "-lm"], check=True)
+    return lib
+
+
+def _run_pins(lib):
+    env = dict(os.environ, G4_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "--capture=sys",
+                        "-k", "not sampled", *PINS], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout[-2000:] + r.stderr[-2000:]
+
+
+def test_unmutated_copy_passes_the_pins():
+    """The harness itself: an unchanged copy built the same way passes."""
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _build_mutant(tmp, "none", "int oracle_max_threads(void)", "int oracle_max_threads(void)")
+        rc, out = _run_pins(lib)
+    assert rc == 0, out
+
+
+def test_every_planted_mistake_fails_a_pin():
+    with tempfile.TemporaryDirectory() as tmp:
+        libs = {name: _build_mutant(tmp, name, old, new) for name, (old, new) in MUTANTS.items()}
+        with cf.ThreadPoolExecutor(max_workers=4) as ex:
+            results = dict(zip(libs, ex.map(_run_pins, libs.values())))
+    survivors = [name for name, (rc, _) in results.items() if rc == 0]
+    assert not survivors, "planted mistakes that pass every pin: %s" % survivors
+    # a mutant fails by a failed assertion, or by the oracle's own check that
+    # every frequency it reads lies in the G window (an abort); nothing else
+    for name, (rc, out) in results.items():
+        window = rc in (-6, 134) and "outside the G window" in out
+        assert rc == 1 or window, "%s: pytest exit %d\n%s" % (name, rc, out)
