@@ -1,26 +1,41 @@
 """Benchmark of the G4 slice accumulation on one MI355X.
 
-Workload: the 4x4-cluster slice (Nc=16, Nw=64 fermionic frequencies, Nq=16
-momentum transfers, Nwex=8 bosonic transfers; 134,217,728 entries of the
+Headline workload: the 4x4-cluster slice (Nc=16, Nw=64 fermionic frequencies,
+Nq=16 momentum transfers, Nwex=8 bosonic transfers; 134,217,728 entries of the
 particle-hole magnetic channel), seeded synthetic Hubbard-shaped G.
 
 A step is one g4_accumulate call of B measurements through the batched
 mixed-precision path (G in complex64, FP32 products, complex128 accumulator):
-direct-term gather plus the fused slice-update pass.  The plain FP64
-per-measurement path (complex128 G and accumulator, one pass per measurement)
-is timed on the same slice for comparison.  Inputs are resident in HBM before
-the timed region; the slice is zeroed after the warm-up steps.
+the pass's staging kernel plus the fused slice-update kernel.  The timed
+region is K steps; it is repeated three times and the median is reported.
+The plain FP64 per-measurement path (complex128 G and accumulator, one pass
+per measurement) is timed on the same slice for comparison.  Inputs are
+resident in HBM before the timed region; the slice is zeroed after the
+warm-up steps.
+
+Further legs in the same JSON line (each with its rate, roofline and error):
+  ring_share       one rank's 1/8 share of the 6x6, Nw=128, Nq=36, Nwex=16
+                   array, fed by 8 walkers' buffers of 16 measurements in the
+                   order the ring delivers them (batched FP32 and plain FP64);
+  split_precision  a 1/4 slice of the 8x8, Nw=64, Nq=64, Nwex=4 array with PH
+                   magnetic, PH charge and PP in one pass, compensated
+                   complex64 accumulators, FP32 products and the fp16 / bf16
+                   hi+lo split direct term.
 
 Printed: one JSON line with the entry-update rate (entries x measurements per
 second), the dominant kernel's roofline position (its average launch time from
 HIP events recorded around each launch on the stream it runs on), the sampled
-error against the FP64 oracle, and the oracle's own rate on the host cores.
+errors against the FP64 oracle (relative Frobenius and the paper's Eq. (2)
+and (3) on real and imaginary parts), and the oracle's own rate on the host
+cores (all of them, and one).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
+import subprocess
 import sys
 import time
 
@@ -32,10 +47,14 @@ sys.path.insert(0, ROOT)
 METRIC = "G4 entry-updates/s per GPU (plain FP64 vs batched mixed) at stated error; % HBM/MFMA peak"
 HBM_PEAK = 8.0e12                                   # bytes/s, MI355X HBM3E
 ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9                 # FP32 or FP64 FMA, non-packed: 78.6 TFLOP/s
+MFMA_F32_PEAK = 157.3e12                            # dense FP32 MFMA
+MFMA_F16_PEAK = 2.5e15                              # dense fp16 / bf16 MFMA
 FLOPS_PER_EU = {1: 24, 2: 24, 4: 16}                 # per channel: direct 8 + exchange 16; PP 16
+DIRECT_FLOPS = 8                                     # the PH direct term's share
 VARIANTS = ["valu", "mfma-direct", "packed-lds", "packed-lds-deep", "packed-lds-mfma-direct"]
 KERNELS = ["update_kernel", "update_mfma_kernel", "update_packed_kernel", "update_packed_kernel",
            "update_packed_mfma_kernel"]
+REPS = 3
 
 
 def algorithmic(E, ng, B, g_bytes, acc_bytes, channels):
@@ -48,18 +67,34 @@ def algorithmic(E, ng, B, g_bytes, acc_bytes, channels):
     return bytes_, flops
 
 
-def roofline(E, ng, B, g_bytes, acc_bytes, channels, launch_s):
+def roofline(E, ng, B, g_bytes, acc_bytes, channels, launch_s, variant=0, direct_elsewhere=False):
+    """Position of one update launch against its binding roof.  For plans whose
+    PH direct term runs on the matrix cores (in the kernel, or in a separate
+    GEMM pass) the VALU carries only the exchange and PP sums: the ALU figure
+    counts those, and the direct term's flops are reported against the MFMA
+    peak beside it."""
     by, fl = algorithmic(E, ng, B, g_bytes, acc_bytes, channels)
+    nph = bin(channels & 3).count("1")
+    mfma_direct = variant in (1, 4) or direct_elsewhere
+    fl_direct = DIRECT_FLOPS * nph * E * B if mfma_direct else 0
+    fl_valu = fl - fl_direct
     t_hbm = by / HBM_PEAK
-    t_alu = fl / ALU_PEAK
+    t_alu = fl_valu / ALU_PEAK
     if t_hbm >= t_alu:
         ach = by / launch_s / 1e9
-        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": ach / (HBM_PEAK / 1e9), "traffic": None,
-                "algorithmic_bytes_per_launch": by}
-    ach = fl / launch_s / 1e12
-    return {"bound": "alu", "achieved": ach, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": ach / (ALU_PEAK / 1e12), "traffic": None, "algorithmic_flops_per_launch": fl}
+        out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+               "frac": ach / (HBM_PEAK / 1e9), "traffic": None,
+               "algorithmic_bytes_per_launch": by}
+    else:
+        ach = fl_valu / launch_s / 1e12
+        out = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s",
+               "frac": ach / (ALU_PEAK / 1e12), "traffic": None,
+               "algorithmic_flops_per_launch": fl_valu}
+    if fl_direct and not direct_elsewhere:
+        a = fl_direct / launch_s / 1e12
+        out["mfma_direct"] = {"achieved": a, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s",
+                              "frac": a / (MFMA_F32_PEAK / 1e12), "flops_per_launch": fl_direct}
+    return out
 
 
 def measured_traffic(plan):
@@ -86,13 +121,27 @@ def measured_traffic(plan):
     return None
 
 
-def sampled_error(w, h, g4, channel, b_seq, sign_seq, nsample):
-    """Relative Frobenius error of sampled slice entries against the oracle."""
+def paper_errors(got, want):
+    """Relative Frobenius error and the paper's normalized L1 / L2 errors
+    (Results section, "Accuracy Analysis", Eq. (2) and Eq. (3)) on the real
+    and imaginary parts, as its Table 1 reports them."""
+    def l1(a, b):
+        return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+    def l2(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {"rel_fro_vs_fp64_oracle": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            "eq2_l1_re": l1(got.real, want.real), "eq2_l1_im": l1(got.imag, want.imag),
+            "eq3_l2_re": l2(got.real, want.real), "eq3_l2_im": l2(got.imag, want.imag)}
+
+
+def sampled_error(w, h, g4, channel, b_seq, sign_seq, nsample, gate):
+    """Errors of sampled slice entries against the oracle, which sums the same
+    measurement sequence in order."""
     from oracle import sampled
     idx = sampled.sample_indices(w, nsample, seed=777)
     got = np.array([g4.g4_readback(h, channel, int(i), 1)[0] for i in idx])
     want = np.zeros(len(idx), dtype=np.complex128)
-    # the oracle sums in measurement order over the same sequence
     start = 0
     while start < len(b_seq):
         b0 = b_seq[start]
@@ -101,12 +150,25 @@ def sampled_error(w, h, g4, channel, b_seq, sign_seq, nsample):
             run += 1
         want += sampled.entries(w, channel, idx, b0=b0, count=run, sign=sign_seq[start:start + run])
         start += run
-    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
-    return err, len(idx)
+    out = paper_errors(got, want)
+    out.update({"sampled_entries": int(len(idx)), "gate": gate})
+    return out
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return None
 
 
 def cpu_baseline(w, seconds):
-    """The oracle, as it stands, on the host cores over a bounded sample."""
+    """The oracle, as it stands, on the host cores over a bounded sample: all
+    threads OpenMP gives it, then one thread."""
     from oracle import ref
     from synth import g_matrices, signs
     nd = 2
@@ -114,18 +176,186 @@ def cpu_baseline(w, seconds):
     gd = g_matrices(w, 0, nd, 1)
     s = signs(w, 0, nd)
     g4 = np.zeros((w.planes, w.n, w.n), dtype=np.complex128)
-    t0 = time.perf_counter()
-    ref.accumulate(w, 1, gu[:1], gd[:1], s[:1], g4=g4)
-    t1 = time.perf_counter() - t0
-    m = max(1, int(seconds / max(t1, 1e-3)))
-    t0 = time.perf_counter()
-    for j in range(m):
-        ref.accumulate(w, 1, gu[j % nd:j % nd + 1], gd[j % nd:j % nd + 1], s[j % nd:j % nd + 1], g4=g4)
-    t = time.perf_counter() - t0
-    return {"value": w.entries * m / t, "unit": "entry-updates/s", "cores": ref.max_threads(),
-            "kind": "oracle",
+
+    def rate(nthreads, budget):
+        t0 = time.perf_counter()
+        ref.accumulate(w, 1, gu[:1], gd[:1], s[:1], g4=g4, nthreads=nthreads)
+        t1 = time.perf_counter() - t0
+        m = max(1, int(budget / max(t1, 1e-3)))
+        t0 = time.perf_counter()
+        for j in range(m):
+            ref.accumulate(w, 1, gu[j % nd:j % nd + 1], gd[j % nd:j % nd + 1], s[j % nd:j % nd + 1],
+                           g4=g4, nthreads=nthreads)
+        return w.entries * m / (time.perf_counter() - t0), m
+
+    cores = ref.max_threads()
+    v_all, m_all = rate(cores, seconds)
+    v_one, m_one = rate(1, seconds / 4)
+    ref.accumulate(w, 1, gu[:0], gd[:0], s[:0], g4=g4, nthreads=cores)   # restore the thread count
+    return {"value": v_all, "unit": "entry-updates/s", "cores": cores, "kind": "oracle",
             "sample": "%d measurements (PH magnetic) over the whole %d-entry slice, C oracle, "
-                      "OpenMP over slice rows" % (m, w.entries)}
+                      "OpenMP over slice rows, %d threads" % (m_all, w.entries, cores),
+            "single_thread": {"value": v_one, "unit": "entry-updates/s", "cores": 1,
+                              "sample": "%d measurement(s), same slice" % m_one},
+            "cpu_model": cpu_model()}
+
+
+class Bench:
+    def __init__(self, args):
+        import torch
+        from paper_2105_00027_amd import g4
+        self.torch, self.g4, self.args = torch, g4, args
+        self.dev = torch.device("cuda:0")
+        torch.cuda.set_device(self.dev)
+        # an explicit stream (default priority): the library enqueues on it and
+        # the timing events are recorded on it
+        self.stream = torch.cuda.Stream(device=self.dev)
+        torch.cuda.set_stream(self.stream)
+        self.sptr = self.stream.cuda_stream
+
+    def fill(self, w, buf, dtype, b0, count, spin):
+        self.g4.g4_synth_fill(buf, dtype, w.lx, w.ly, w.nw, w.nwex, w.beta, w.t, w.mu, w.h, w.noise,
+                              w.seed, w.wid, b0, count, spin, self.sptr)
+
+    def cfg(self, w, flags=0, **kw):
+        g4 = self.g4
+        return g4.Config(lx=w.lx, ly=w.ly, nw=w.nw, nwex=w.nwex, nq=w.nq, q_begin=w.q0, q_end=w.q1,
+                         channels=w.channels, beta=w.beta, stream=self.sptr,
+                         flags=g4.G4_F_KERNEL_TIMING | flags, **kw)
+
+    def timed(self, fn, steps):
+        torch = self.torch
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        for i in range(steps):
+            fn(i)
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    def batched(self, w, B, runs, steps, warmup, prod=1, acc=0, flags=0, tile=0, autotune=False,
+                err_channels=(1,), nsample=256, gate=1e-6, reps=REPS):
+        """Batched leg: the pool of measurements given by runs [(b0, n), ...]
+        resident in HBM, steps of B measurements taken in pool order.  Returns
+        the per-repetition times, statistics, errors and the roofline."""
+        g4, torch = self.g4, self.torch
+        pool = sum(n for _, n in runs)
+        ids = np.concatenate([np.arange(b0, b0 + n) for b0, n in runs])
+        gu = torch.empty((pool, w.ng, w.ng), dtype=torch.complex64, device=self.dev)
+        gd = torch.empty_like(gu)
+        pos = 0
+        from synth import signs
+        for b0, n in runs:
+            self.fill(w, gu[pos:pos + n], g4.G4_IN_C64, b0, n, 0)
+            self.fill(w, gd[pos:pos + n], g4.G4_IN_C64, b0, n, 1)
+            pos += n
+        sg = np.concatenate([signs(w, b0, n) for b0, n in runs])
+        h = g4.g4_init_slice(self.cfg(w, mode=g4.G4_MODE_BATCHED, prod=prod, g_in=g4.G4_IN_C64, acc=acc,
+                                      max_batch=B, tile=tile, flags=flags))
+        out = {}
+        try:
+            if autotune:
+                out["autotune"] = g4.g4_autotune(h, gu[:B], gd[:B], sg[:B], B, gate)
+            nblk = pool // B
+
+            def step(i):
+                j = i % nblk
+                g4.g4_accumulate(h, gu[j * B:(j + 1) * B], gd[j * B:(j + 1) * B], sg[j * B:(j + 1) * B])
+
+            graph = bool(flags & g4.G4_F_GRAPH)
+            for i in range(max(warmup, 2 * nblk if graph else 0)):
+                step(i)
+            g4.g4_sync(h)
+            g4.g4_reset(h)
+            torch.cuda.synchronize()
+            b_seq, rep_ms = [], []
+            i0 = warmup
+            for _ in range(reps):
+                rep_ms.append(self.timed(lambda i: step(i0 + i), steps))
+                for i in range(steps):
+                    j = (i0 + i) % nblk
+                    b_seq.extend(range(j * B, (j + 1) * B))
+                i0 += steps
+            st = g4.g4_stats(h)
+            out["rep_ms"] = rep_ms
+            out["stats"] = st
+            if not self.args.no_check and steps:
+                out["errors"] = {ch: sampled_error(w, h, g4, ch, [int(ids[p]) for p in b_seq], sg[b_seq],
+                                                   nsample, gate) for ch in err_channels}
+        finally:
+            g4.g4_destroy(h)
+            del gu, gd
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        return out
+
+    def plain(self, w, M, tile=0, reps=REPS):
+        """Plain FP64 leg: M measurements, one pass each, timed `reps` times."""
+        g4, torch = self.g4, self.torch
+        from synth import signs
+        pu = torch.empty((M, w.ng, w.ng), dtype=torch.complex128, device=self.dev)
+        pd = torch.empty_like(pu)
+        self.fill(w, pu, g4.G4_IN_C128, 0, M, 0)
+        self.fill(w, pd, g4.G4_IN_C128, 0, M, 1)
+        ps = signs(w, 0, M)
+        hp = g4.g4_init_slice(self.cfg(w, mode=g4.G4_MODE_PLAIN, tile=tile))
+        out = {}
+        try:
+            g4.g4_accumulate(hp, pu[:2], pd[:2], ps[:2])      # warm-up
+            g4.g4_sync(hp)
+            g4.g4_reset(hp)
+            torch.cuda.synchronize()
+            out["rep_ms"] = [self.timed(lambda i: g4.g4_accumulate(hp, pu, pd, ps), 1) for _ in range(reps)]
+            out["stats"] = g4.g4_stats(hp)
+            if not self.args.no_check:
+                out["errors"] = {1: sampled_error(w, hp, g4, 1, list(range(M)) * reps, np.tile(ps, reps),
+                                                  256, 1e-12)}
+        finally:
+            g4.g4_destroy(hp)
+            del pu, pd
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        return out
+
+
+def leg_line(w, res, B, steps, g_bytes, acc_bytes, plan_acc, direct_elsewhere=False):
+    """Summary of a batched leg: median rate over the repetitions, kernel
+    timing, roofline with measured traffic when a counter run covers the plan."""
+    st = res["stats"]
+    med = statistics.median(res["rep_ms"])
+    nch = bin(w.channels).count("1")
+    launch_s = st["kernel_ms"] / max(1, st["timed_launches"]) / 1e3
+    line = {"value": w.entries * nch * steps * B / (med / 1e3), "unit": "entry-updates/s",
+            "ms_per_step": med / max(1, steps), "rep_ms": res["rep_ms"],
+            "pass_batch": st["batch"], "tile": st["tile"], "kernel_variant": VARIANTS[st["variant"]],
+            "kernel": {"name": KERNELS[st["variant"]], "avg_launch_ms": launch_s * 1e3,
+                       "launches": st["timed_launches"]}}
+    line["roofline"] = roofline(w.entries, w.ng, st["batch"], g_bytes, acc_bytes, w.channels, launch_s,
+                                st["variant"], direct_elsewhere)
+    line["roofline"]["traffic"] = measured_traffic(
+        {"mode": 1, "acc": plan_acc, "batch": st["batch"], "tile": st["tile"], "variant": st["variant"],
+         "channels": w.channels, "entries": w.entries})
+    if "errors" in res:
+        line["error"] = res["errors"][1] if list(res["errors"]) == [1] else \
+            {"channel_%d" % ch: e for ch, e in res["errors"].items()}
+    return line
+
+
+def plain_line(w, res, M, nch=1):
+    st = res["stats"]
+    med = statistics.median(res["rep_ms"])
+    plaunch = st["kernel_ms"] / max(1, st["timed_launches"]) / 1e3
+    line = {"value": w.entries * nch * M / (med / 1e3), "unit": "entry-updates/s", "measurements": M,
+            "ms_per_measurement": med / M, "rep_ms": res["rep_ms"], "dtype": "f64", "tile": st["tile"],
+            "kernel_avg_launch_ms": plaunch * 1e3,
+            "roofline": roofline(w.entries, w.ng, 1, 16, 16, w.channels, plaunch)}
+    line["roofline"]["traffic"] = measured_traffic(
+        {"mode": 0, "acc": 0, "batch": 1, "tile": st["tile"], "variant": 0, "channels": w.channels,
+         "entries": w.entries})
+    if "errors" in res:
+        line["error"] = res["errors"][1]
+    return line
 
 
 def main():
@@ -137,9 +367,8 @@ def main():
                     help="measurements per step (the slice's max_batch); default 64, ring: 16 "
                          "(one walker's buffer; a multiple of 16 takes that many buffers per pass)")
     ap.add_argument("--workload", default="slice4x4", choices=["slice4x4", "ring6x6"],
-                    help="slice4x4: the 4x4-cluster slice (default); ring6x6: rank 3's 1/8 share "
-                         "of the 6x6, Nw=128 array, fed by 8 walkers' buffers of 16 measurements "
-                         "in ring order")
+                    help="headline: slice4x4 (default) or ring6x6 (rank 3's 1/8 share of the 6x6, "
+                         "Nw=128 array as the headline, for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default plan instead of timing the candidates first")
     ap.add_argument("--tile", type=int, default=0)
@@ -157,6 +386,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ring", action="store_true", help="skip the ring-share leg")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision leg")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="run only the ring-share and split-precision legs (profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--pool", type=int, default=1024, help="distinct measurements resident in HBM")
     ap.add_argument("--no-batched", action="store_true")
@@ -169,36 +402,9 @@ def main():
               "multi-GPU path is built (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2105_00027_amd import g4
-    from synth import C2_PLAIN, C4_RING, signs
-
-    ring = args.workload == "ring6x6"
-    if ring:
-        # rank 3 of 8: planes [216, 288) of 6x6 x 128 frequencies x (36 x 16) transfers
-        w = C4_RING.with_(channels=g4.G4_PH_MAGNETIC, q_begin=3 * 72, q_end=4 * 72)
-        args.batch = args.batch or 16
-        args.no_cpu_baseline = True     # the oracle's full-slice array would be 24.5 GB of host memory
-    else:
-        w = C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC)
-        args.batch = args.batch or 64
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    # an explicit stream (default priority): the library enqueues on it and the
-    # timing events are recorded on it
-    stream = torch.cuda.Stream(device=dev)
-    torch.cuda.set_stream(stream)
-    sptr = stream.cuda_stream
-    E, ng, B = w.entries, w.ng, args.batch
-
-    def fill(buf, dtype, b0, count, spin):
-        g4.g4_synth_fill(buf, dtype, w.lx, w.ly, w.nw, w.nwex, w.beta, w.t, w.mu, w.h, w.noise,
-                         w.seed, w.wid, b0, count, spin, sptr)
-
-    def cfg(flags=0, **kw):
-        return g4.Config(lx=w.lx, ly=w.ly, nw=w.nw, nwex=w.nwex, nq=w.nq, q_begin=w.q0, q_end=w.q1,
-                         channels=w.channels, beta=w.beta, stream=sptr,
-                         flags=g4.G4_F_KERNEL_TIMING | flags, **kw)
+    bench = Bench(args)
+    g4, torch = bench.g4, bench.torch
+    from synth import C2_PLAIN, C4_RING, C5_SPLIT
 
     out = {"metric": METRIC, "unit": "entry-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
@@ -206,143 +412,105 @@ def main():
 
     if args.calibrate_copy:
         nb = args.calibrate_copy << 20
-        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        src = torch.ones(nb // 8, dtype=torch.float64, device=bench.dev)
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)          # reads nb bytes, writes nb bytes
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = nb
         del src, dst
 
-    # ---- batched mixed precision (the headline) -------------------------------
-    total = (args.warmup + args.steps) * B
-    pool = max(B, min(args.pool, total))
-    pool -= pool % B
-    if ring:
-        # the 8 walkers' buffers of 16 measurements, laid out in the order rank 3
-        # receives them (its own walker's, then each from the left); a step takes
-        # B / 16 of them in that order
-        if B % 16 or 128 % B:
-            ap.error("ring6x6: --batch must be 16, 32, 64 or 128")
-        pool = 128
-        runs = [((3 - s) % 8 * 16, 16) for s in range(8)]
-    else:
-        runs = [(0, pool)]
-    if args.no_batched:
-        args.steps = 0
-        pool, runs = B, [(0, B)]
-    # ids[p]: the measurement held at pool position p
-    ids = np.concatenate([np.arange(b0, b0 + n) for b0, n in runs])
-    gu = torch.empty((pool, ng, ng), dtype=torch.complex64, device=dev)
-    gd = torch.empty_like(gu)
-    pos = 0
-    for b0, n in runs:
-        fill(gu[pos:pos + n], g4.G4_IN_C64, b0, n, 0)
-        fill(gd[pos:pos + n], g4.G4_IN_C64, b0, n, 1)
-        pos += n
-    sg = np.concatenate([signs(w, b0, n) for b0, n in runs])
+    ring = args.workload == "ring6x6"
     acc = g4.G4_ACC_C128 if args.acc == "c128" else g4.G4_ACC_C64_KAHAN
-    h = g4.g4_init_slice(cfg(mode=g4.G4_MODE_BATCHED, prod=g4.G4_PROD_F32, g_in=g4.G4_IN_C64,
-                             acc=acc, max_batch=B, tile=args.tile,
-                             flags=(g4.G4_F_GRAPH if args.graph else 0) |
-                                   (g4.G4_F_MFMA if args.mfma else 0) |
-                                   (g4.G4_F_PACKED if args.packed else 0) |
-                                   (g4.G4_F_PACKED_DEEP if args.deep else 0)))
-    nblk = pool // B
-    if not args.no_autotune:
-        tune = g4.g4_autotune(h, gu[:B], gd[:B], sg[:B], B, 1e-6)
-        out["autotune"] = tune
+    vflags = ((g4.G4_F_GRAPH if args.graph else 0) | (g4.G4_F_MFMA if args.mfma else 0) |
+              (g4.G4_F_PACKED if args.packed else 0) | (g4.G4_F_PACKED_DEEP if args.deep else 0))
+    ring_w = C4_RING.with_(channels=g4.G4_PH_MAGNETIC, q_begin=3 * 72, q_end=4 * 72)
+    ring_runs = [((3 - s) % 8 * 16, 16) for s in range(8)]   # rank 3's order: own, then from the left
 
-    def step(i):
-        j = i % nblk
-        g4.g4_accumulate(h, gu[j * B:(j + 1) * B], gd[j * B:(j + 1) * B], sg[j * B:(j + 1) * B])
+    # ---- the headline: batched mixed precision ------------------------------
+    if not args.legs_only:
+        if ring:
+            # rank 3 of 8: planes [216, 288) of 6x6 x 128 frequencies x (36 x 16) transfers
+            w = ring_w
+            B = args.batch or 16
+            if B % 16 or 128 % B:
+                ap.error("ring6x6: --batch must be 16, 32, 64 or 128")
+            runs = ring_runs
+            args.no_cpu_baseline = True   # the oracle's full-slice array would be 24.5 GB of host memory
+        else:
+            w = C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC)
+            B = args.batch or 64
+            total = (args.warmup + REPS * args.steps) * B
+            pool = max(B, min(args.pool, total))
+            pool -= pool % B
+            runs = [(0, pool)]
+        steps = 0 if args.no_batched else args.steps
+        res = bench.batched(w, B, runs if not args.no_batched else [(0, B)], steps, args.warmup, acc=acc,
+                            flags=vflags, tile=args.tile, autotune=not args.no_autotune and steps > 0)
+        head = leg_line(w, res, B, steps, 8, 16, acc)
+        if "autotune" in res:
+            out["autotune"] = res["autotune"]
+        out["value"] = head["value"] if steps else 0.0
+        out["ms_per_step"] = head["ms_per_step"]
+        out["rep_ms_per_step"] = [t / max(1, steps) for t in head["rep_ms"]]
+        shape = ("%dx%d Hubbard cluster G4 slice: Nc=%d, Nw=%d, Nq=%d, Nwex=%d, planes [%d, %d)"
+                 % (w.lx, w.ly, w.nc, w.nw, w.nq, w.nwex, w.q0, w.q1))
+        if ring:
+            shape += ", 8 walkers' buffers of 16 measurements in ring order"
+        out["config"] = {"workload": shape +
+                                     ", E=%d entries, PH magnetic, %d measurements per step in passes "
+                                     "of %d, complex64 G, FP32 products, %s accumulator"
+                                     % (w.entries, B, head["pass_batch"], args.acc),
+                         "entries": w.entries, "measurements_per_step": B, "pass_batch": head["pass_batch"],
+                         "tile": head["tile"], "accumulator": args.acc,
+                         "kernel_variant": head["kernel_variant"],
+                         "measurements_timed": REPS * steps * B, "timed_repetitions": REPS,
+                         "value_is": "median of the repetitions"}
+        out["kernel"] = head["kernel"]
+        out["roofline"] = head["roofline"] if steps else None
+        if "error" in head:
+            out["error"] = head["error"]
 
-    # with graphs every pool block is used twice before timing (run, then record)
-    for i in range(max(args.warmup, 2 * nblk if args.graph else 0)):
-        step(i)
-    g4.g4_sync(h)
-    g4.g4_reset(h)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    b_seq = []
-    e0.record(stream)
-    for i in range(args.steps):
-        step(args.warmup + i)
-        j = (args.warmup + i) % nblk
-        b_seq.extend(range(j * B, (j + 1) * B))
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    st = g4.g4_stats(h)
-    launch_s = st["kernel_ms"] / max(1, st["timed_launches"]) / 1e3
-    value = E * args.steps * B / (ms / 1e3) if args.steps else 0.0
-    out["value"] = value
-    out["ms_per_step"] = ms / max(1, args.steps)
-    shape = ("%dx%d Hubbard cluster G4 slice: Nc=%d, Nw=%d, Nq=%d, Nwex=%d, planes [%d, %d)"
-             % (w.lx, w.ly, w.nc, w.nw, w.nq, w.nwex, w.q0, w.q1))
-    if ring:
-        shape += ", 8 walkers' buffers of 16 measurements in ring order"
-    out["config"] = {"workload": shape +
-                                 ", E=%d entries, PH magnetic, %d measurements per step in passes "
-                                 "of %d, complex64 G, FP32 products, %s accumulator"
-                                 % (E, B, st["batch"], args.acc),
-                     "entries": E, "measurements_per_step": B, "pass_batch": st["batch"],
-                     "tile": st["tile"], "accumulator": args.acc,
-                     "kernel_variant": VARIANTS[st["variant"]],
-                     "measurements_timed": args.steps * B}
-    out["kernel"] = {"name": KERNELS[st["variant"]],
-                     "avg_launch_ms": launch_s * 1e3, "launches": st["timed_launches"]}
-    out["roofline"] = roofline(E, ng, st["batch"], 8, 16, w.channels, launch_s) if args.steps else None
-    if out["roofline"]:
-        out["roofline"]["traffic"] = measured_traffic(
-            {"mode": 1, "acc": acc, "batch": st["batch"], "tile": st["tile"],
-             "variant": st["variant"], "channels": w.channels, "entries": E})
-    if not args.no_check and args.steps:
-        err, ns = sampled_error(w, h, g4, 1, [int(ids[p]) for p in b_seq], sg[b_seq], 256)
-        out["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-6}
-    g4.g4_destroy(h)
-    del gu, gd
-    torch.cuda.empty_cache()
+        # ---- plain FP64, one pass per measurement ----------------------------
+        if not args.no_plain:
+            pw = w if not ring else ring_w
+            M = args.plain_measurements if not ring else 8
+            out["plain_fp64"] = plain_line(pw, bench.plain(pw, M, args.plain_tile), M)
+            out["speedup_vs_plain_fp64"] = out["value"] / out["plain_fp64"]["value"] if out["value"] else None
 
-    # ---- plain FP64, one pass per measurement ------------------------------
-    if not args.no_plain:
-        M = args.plain_measurements
-        pu = torch.empty((M, ng, ng), dtype=torch.complex128, device=dev)
-        pd = torch.empty_like(pu)
-        fill(pu, g4.G4_IN_C128, 0, M, 0)
-        fill(pd, g4.G4_IN_C128, 0, M, 1)
-        ps = signs(w, 0, M)
-        hp = g4.g4_init_slice(cfg(mode=g4.G4_MODE_PLAIN, tile=args.plain_tile))
-        g4.g4_accumulate(hp, pu[:2], pd[:2], ps[:2])      # warm-up
-        g4.g4_sync(hp)
-        g4.g4_reset(hp)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        g4.g4_accumulate(hp, pu, pd, ps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1)
-        pst = g4.g4_stats(hp)
-        plaunch = pst["kernel_ms"] / max(1, pst["timed_launches"]) / 1e3
-        pval = E * M / (pms / 1e3)
-        plain = {"value": pval, "unit": "entry-updates/s", "measurements": M,
-                 "ms_per_measurement": pms / M, "dtype": "f64", "tile": pst["tile"],
-                 "kernel_avg_launch_ms": plaunch * 1e3,
-                 "roofline": roofline(E, ng, 1, 16, 16, w.channels, plaunch)}
-        plain["roofline"]["traffic"] = measured_traffic(
-            {"mode": 0, "acc": 0, "batch": 1, "tile": pst["tile"], "variant": 0,
-             "channels": w.channels, "entries": E})
-        if not args.no_check:
-            err, ns = sampled_error(w, hp, g4, 1, list(range(M)), ps, 256)
-            plain["error"] = {"rel_fro_vs_fp64_oracle": err, "sampled_entries": ns, "gate": 1e-12}
-        g4.g4_destroy(hp)
-        del pu, pd
-        torch.cuda.empty_cache()
-        out["plain_fp64"] = plain
-        out["speedup_vs_plain_fp64"] = value / pval if value else None
+    # ---- ring share: 8 walkers' buffers in ring order -------------------------
+    if not args.no_ring and not ring:
+        leg = {"workload": "6x6 Hubbard cluster, Nw=128, Nq=36, Nwex=16: rank 3's 1/8 slice, planes "
+                           "[216, 288), E=%d entries, PH magnetic; 8 walkers' buffers of 16 measurements "
+                           "in the ring's order (3, 2, 1, 0, 7, 6, 5, 4), one buffer per pass, complex64 G, "
+                           "FP32 products, packed operands (4-row tiles, direct vector a in registers), "
+                           "complex128 accumulator" % ring_w.entries}
+        res = bench.batched(ring_w, 16, ring_runs, 8, 2, acc=0, flags=g4.G4_F_PACKED, tile=4,
+                            nsample=96, reps=REPS)
+        leg["batched"] = leg_line(ring_w, res, 16, 8, 8, 16, 0)
+        if not args.no_plain:
+            leg["plain_fp64"] = plain_line(ring_w, bench.plain(ring_w, 8), 8)
+            leg["speedup_vs_plain_fp64"] = leg["batched"]["value"] / leg["plain_fp64"]["value"]
+        out["ring_share"] = leg
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    # ---- split precision: 8x8, three channels in one pass ----------------------
+    if not args.no_split and not ring:
+        sw = C5_SPLIT.with_(q_begin=64, q_end=128)
+        leg = {"workload": "8x8 Hubbard cluster, Nw=64, Nq=64, Nwex=4: a 1/4 slice, planes [64, 128), "
+                           "E=%d entries per channel, PH magnetic + PH charge + PP in one pass, 64 "
+                           "measurements in passes of 32, complex64 G, compensated complex64 "
+                           "accumulators" % sw.entries}
+        for name, prod, gate in (("f32", g4.G4_PROD_F32, 1e-6), ("f16x2", g4.G4_PROD_F16X2, 1e-6),
+                                 ("bf16x2", g4.G4_PROD_BF16X2, 2.0 ** -15 + 1e-6)):
+            res = bench.batched(sw, 32, [(0, 64)], 2, 1, prod=prod, acc=g4.G4_ACC_C64_KAHAN,
+                                err_channels=(1, 2, 4), nsample=64, gate=gate)
+            line = leg_line(sw, res, 32, 2, 8, 16, g4.G4_ACC_C64_KAHAN,
+                            direct_elsewhere=prod in (g4.G4_PROD_F16X2, g4.G4_PROD_BF16X2))
+            line["products"] = name
+            leg[name] = line
+        out["split_precision"] = leg
+
+    if not args.no_cpu_baseline and not args.legs_only:
+        out["cpu_baseline"] = cpu_baseline(C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -107,7 +107,10 @@ enum {
 
 /* flags */
 enum {
-    G4_F_CHECK_FINITE = 1u,   /* g4_accumulate rejects signs that are not finite */
+    G4_F_CHECK_FINITE = 1u,   /* g4_accumulate rejects (G4_E_ARG, nothing accumulated) a call whose
+                                 signs or G_up/G_dn elements are not all finite; G is screened by
+                                 a device pass over both buffers followed by a wait, so the call
+                                 returns only after the stream's earlier work has finished */
     G4_F_KERNEL_TIMING = 2u,  /* time every slice-update kernel with HIP events (see g4_stats) */
     G4_F_GRAPH = 4u,          /* batched: a pass on input pointers (and pass size) seen before is
                                  replayed as a HIP graph of its kernels, recorded on the second
@@ -180,20 +183,33 @@ typedef struct g4_stats_t {
 } g4_stats_t;
 
 /* Fill *cfg with defaults (magnetic channel, c128, FP64, plain, whole
- * slice of a 1x1 cluster).  Returns G4_E_ARG for NULL. */
+ * slice of a 1x1 cluster).  Returns G4_E_ARG for NULL.
+ * Paper: Implementation section, "Distributed G_t in QMC Solver" (the slice a
+ * rank owns, which the configuration describes). */
 int g4_config_init(g4_config *cfg);
 
 /* Validate cfg and report entries per channel and the device bytes that
- * g4_init_slice would allocate.  No HIP call.  Either output may be NULL. */
+ * g4_init_slice would allocate.  No HIP call.  Either output may be NULL.
+ * Paper: Results section, "Memory Analysis" (the G_t sizes it prints: the full array and its 1/p
+ * part per rank, Implementation section, "Distributed G_t in QMC Solver"). */
 int g4_slice_size(const g4_config *cfg, uint64_t *entries_per_channel, uint64_t *device_bytes);
 
 /* Create a slice: validate, check device memory (also against the optional
  * cap G4_TEST_DEVICE_MEM_LIMIT, in bytes, from the environment), build and
  * upload the index tables, allocate and zero the accumulators.  Synchronous.
- * On success *out owns all device memory until g4_destroy. */
+ * On success *out owns all device memory until g4_destroy.
+ * Paper: Implementation section, "Distributed G_t in QMC Solver" (each rank
+ * allocates an even 1/p part of G_t, a contiguous range of transfer planes
+ * here); Background section, the solver workflow (G_t is allocated before the
+ * measurements and kept for the whole run). */
 int g4_init_slice(const g4_config *cfg, g4_slice **out);
 
 /* Enqueue the accumulation of `batch` measurements.
+ * Paper: Background section, "Memory-Bound Issue in DCA++", Eq. (1) (the
+ * update of G_t by one G_sigma pair; PH channels by the same Wick rule, see the
+ * top of this header); Implementation section, Algorithm 1 ("Pipeline Ring
+ * Algorithm": a rank applies its own G_sigma, then each buffer that reaches it
+ * from its left neighbour; here the buffers arrive as device pointers).
  * G_up, G_dn: DEVICE pointers to batch consecutive Ng x Ng row-major matrices
  *   of element type cfg.g_in (Ng = lx*ly*(nw+nwex-1)), one per spin.
  *   Borrowed: they must stay alive and unchanged until g4_sync returns (or
@@ -206,18 +222,27 @@ int g4_accumulate(g4_slice *h, const void *G_up, const void *G_dn, const double 
                   int32_t batch);
 
 /* Wait for all enqueued work on the handle's stream; folds event timings
- * into the statistics. */
+ * into the statistics.
+ * Paper: Implementation section, Algorithm 1 (the wait on the outstanding
+ * transfers before a buffer is reused). */
 int g4_sync(g4_slice *h);
 
 /* Synchronous copy of entries [first, first+count) of one channel (a single
  * G4_* bit present in cfg.channels) into out_c128 (HOST, 2*count doubles,
- * interleaved).  Compensated accumulators are returned as value +
- * compensation in double. */
+ * interleaved).  A compensated accumulator entry is returned as its value in
+ * double: the float sum minus the stored compensation term (which holds the
+ * negated rounding remainder of the float sum).
+ * Paper: Background section, the solver workflow (the accumulated G_t is
+ * reduced or written out after the last measurement); Implementation section,
+ * "Pipeline Ring Algorithm" (the optional write of each rank's part to a
+ * file). */
 int g4_readback(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, double *out_c128);
 
 /* Synchronous overwrite of entries [first, first+count) of one channel from
  * in_c128 (HOST).  For float accumulators each value is split into a rounded
- * value and its rounding remainder (compensated) or rounded (plain float). */
+ * value and its rounding remainder (compensated) or rounded (plain float).
+ * Paper: Implementation section, "Pipeline Ring Algorithm" (the inverse of the
+ * per-rank file write: restoring a slice, e.g. to resume a run). */
 int g4_load(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, const double *in_c128);
 
 /* Add src's accumulators into dst, entry by entry, and its measurement count
@@ -228,16 +253,24 @@ int g4_load(g4_slice *h, uint32_t channel, uint64_t first, uint64_t count, const
  * (G4_E_UNSUPPORTED); their accumulator kinds may differ (each value is read
  * in src's kind and added in dst's; a compensated dst adds the float part and
  * its remainder).  Waits for src's stream, runs on dst's, and returns when
- * done; src is left unchanged. */
+ * done; src is left unchanged.
+ * Paper: Implementation section, "Sub-Ring Optimization" (ranks of different sub-rings hold
+ * the same part of G_t; those parts are reduced at the end of the run). */
 int g4_merge(g4_slice *dst, g4_slice *src);
 
-/* Set the measurement count and weight sum (restoring a checkpoint). */
+/* Set the measurement count and weight sum (restoring a checkpoint).
+ * Paper: Background section, the solver workflow (G_t is normalised by the
+ * measurements taken; with g4_load, a resumed run continues that sum). */
 int g4_set_counts(g4_slice *h, uint64_t measurements, double sign_sum);
 
-/* Zero every accumulator and the statistics.  Enqueued. */
+/* Zero every accumulator and the statistics.  Enqueued.
+ * Paper: Background section, the solver workflow (G_t starts from zero before
+ * the measurement phase). */
 int g4_reset(g4_slice *h);
 
-/* Current statistics (synchronous: waits for the stream first). */
+/* Current statistics (synchronous: waits for the stream first).
+ * Paper: Results section (measurement counts and timing of the runs it
+ * reports); no interface is given there. */
 int g4_stats(g4_slice *h, g4_stats_t *st);
 
 /* Override the work tile (K2 rows; 0 keeps it, or takes the variant's default
@@ -245,35 +278,46 @@ int g4_stats(g4_slice *h, g4_stats_t *st);
  * allocated max_batch; 0 keeps it) and the kernel variant (G4_VARIANT_*, -1
  * keeps it).  Selecting G4_VARIANT_PACKED allocates its buffer on first use
  * (G4_E_OOM if it does not fit).  G4_E_UNSUPPORTED if the combination cannot
- * run for this slice.  Waits for the handle's stream. */
+ * run for this slice.  Waits for the handle's stream.
+ * Paper: no passage (the paper gives no kernel design for the G_t update; the
+ * plans are this library's own, all computing Eq. (1) and its PH analogues). */
 int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant);
 
 typedef struct g4_tune_result {
     int32_t batch;               /* measurements per pass chosen */
     int32_t tile;                /* K2 rows per work tile chosen */
     int32_t variant;             /* G4_VARIANT_* */
-    int32_t candidates;          /* plans timed (0 when taken from the cache) */
-    double ms_per_measurement;   /* pass time per measurement of the chosen plan */
-    double rel_err;              /* its relative difference from the first plan tried, on a
-                                    sample of entries */
+    int32_t candidates;          /* plans timed (0 when a stored choice passed the gate) */
+    double ms_per_measurement;   /* pass time per measurement of the chosen plan, as measured here */
+    double rel_err_fp64;         /* its largest relative Frobenius difference, over the channels, from
+                                    an FP64 evaluation of the same measurements at up to 16384 slice
+                                    entries spread over the slice */
 } g4_tune_result;
 
 /* Choose the plan (pass size up to min(max_batch, batch), work-tile height,
- * kernel variant) with the shortest pass time per measurement on `batch`
- * caller-supplied measurements (same layout and ownership as g4_accumulate),
- * among those whose sampled result differs from the first plan tried by at
- * most tol (relative Frobenius), and install it.  With G4_AUTOTUNE_CACHE
- * naming a file in the environment, a choice stored there for the same GPU
- * architecture and slice shape is reused and new choices are appended.
- * Requires a fresh or reset slice (G4_E_STATE otherwise); leaves the
- * accumulators and statistics zeroed.  Synchronous. */
+ * kernel variant) with the shortest pass time per measurement on the first
+ * min(batch, max_batch) of `batch` caller-supplied measurements (same layout
+ * and ownership as g4_accumulate), among those whose result at up to 16384
+ * sampled slice entries differs from an FP64 evaluation of the same
+ * measurements (computed on the device straight from G, per entry) by at most
+ * tol (relative Frobenius, per channel), and install it.  With
+ * G4_AUTOTUNE_CACHE naming a file in the environment, a choice stored there
+ * for the same library build, GPU architecture and slice shape is installed
+ * after one timed pass passes the same gate (else every plan is timed), and
+ * new choices are appended.  G4_E_UNSUPPORTED if no plan meets tol.  Requires
+ * a fresh or reset slice (G4_E_STATE otherwise); leaves the accumulators and
+ * statistics zeroed.  Synchronous; allocates a few small work buffers.
+ * Paper: no passage (as g4_set_plan). */
 int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *sign, int32_t batch,
                 double tol, g4_tune_result *out);
 
-/* Release everything owned by h (waits for its stream).  NULL is a no-op. */
+/* Release everything owned by h (waits for its stream).  NULL is a no-op.
+ * Paper: Background section, the solver workflow (G_t is freed at the end of
+ * the run). */
 void g4_destroy(g4_slice *h);
 
-/* Message of the last failing call on this host thread ("" if none). */
+/* Message of the last failing call on this host thread ("" if none).
+ * Paper: no passage (error reporting of this interface only). */
 const char *g4_last_error(void);
 
 /* ---- synthetic inputs (not part of the method) -------------------------
@@ -283,7 +327,9 @@ const char *g4_last_error(void);
  *   eps_k = -2t(cos kx + cos ky),  x, y ~ N(0,1) from Philox4x32-10 with
  *   key (seed, wid) and counter (r*Ng + c, b, spin, 0), Box-Muller in double.
  * dtype: G4_IN_C128 or G4_IN_C64 (rounded).  stream: hipStream_t or NULL
- * (the null stream).  Asynchronous. */
+ * (the null stream).  Asynchronous.
+ * Paper: Results section (the 6x6 single-band Hubbard runs whose G_sigma these
+ * synthetic matrices stand in for; the QMC walker itself is not built). */
 int g4_synth_fill(void *out, int32_t dtype, int32_t lx, int32_t ly, int32_t nw, int32_t nwex,
                   double beta, double t, double mu, double h, double noise, uint32_t seed,
                   uint32_t wid, int64_t b0, int32_t count, int32_t spin, void *stream);
@@ -291,7 +337,9 @@ int g4_synth_fill(void *out, int32_t dtype, int32_t lx, int32_t ly, int32_t nw, 
 /* ---- debug export of the integer index maps (no HIP call) --------------
  * kadd[k*Nc+q] = k+q, ksub[q*Nc+k] = q-k (Nc*Nc int32 each, HOST).
  * plane_q[i], plane_m[i] for the slice's planes i = 0..q_end-q_begin-1.
- * Any output may be NULL. */
+ * Any output may be NULL.
+ * Paper: Background section, "Memory-Bound Issue in DCA++" (the combined
+ * momentum-frequency indices K and the transfer K3 of Eq. (1)). */
 int g4_index_maps(const g4_config *cfg, int32_t *kadd, int32_t *ksub, int32_t *plane_q,
                   int32_t *plane_m);
 

@@ -32,6 +32,21 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+def build_id() -> str:
+    """SHA-1 (first 16 hex digits) over the library's sources and its header:
+    compiled into the library so that autotuner choices stored by another
+    build of the kernels are not reused."""
+    import hashlib
+    h = hashlib.sha1()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp", ".cpp")))
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "g4.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _stale(src: str, obj: str) -> bool:
     """True when obj is missing or older than its source or any header."""
     if not os.path.exists(obj):
@@ -44,10 +59,13 @@ def _stale(src: str, obj: str) -> bool:
 def _compile(spec, verbose: bool, incremental: bool = False) -> str:
     src, name, defs = spec
     obj = os.path.join(BUILD, name + ".o")
-    if incremental and not _stale(src, obj):
+    if incremental and not src.endswith(".cpp") and not _stale(src, obj):
         return obj
     cmd = ["hipcc", *COMMON, *DEVICE, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
+        # the host code carries the build id (always recompiled: it changes
+        # with any source)
+        defs = defs + ['-DG4_BUILD_ID="%s"' % build_id()]
         cmd = ["hipcc", *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -79,6 +79,8 @@ struct UpdateArgs {
     int nitems;               // work tiles in the list (one block per tile)
     int skip_direct;          // packed kernel: 1 = the PH direct term is added by
                               // direct_split_kernel; the tile's direct vectors read as zeros
+    int phase_r;              // packed kernel: tiles resident at once per XCD (0: every tile
+                              // takes the pass's measurements in order; see measurement_phase)
     Dims d;
     Tables t;
 };
@@ -176,7 +178,8 @@ hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
 hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems, int variant,
                          const UpdateArgs &a, hipStream_t s);
 size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant);
-// Packed operands with the direct term on MFMA (variant 4): nw = 64, tile 16, PH channels.
+// Packed operands with the direct term on MFMA (variant 4): nw = 64, tile 8, plane groups of
+// 4 or 8, PH channels.
 hipError_t launch_update_packed_mfma(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
                                      hipStream_t s);
 // Packing of one pass for the packed-operand kernel, with the direct vectors
@@ -204,8 +207,34 @@ hipError_t launch_acc_to_c128(int acc_kind, const void *acc, uint64_t first, uin
 hipError_t launch_c128_to_acc(int acc_kind, const double *src, void *acc, uint64_t first,
                               uint64_t count, int nc, int nw, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// *flag = 1 if any float (dbl = 0) or double (dbl = 1) in [p, p + bytes) is not
+// finite; p and bytes aligned to the value size; *flag is not cleared
+hipError_t launch_finite_check(const void *p, size_t bytes, int dbl, int *flag, hipStream_t s);
 // dst += src over `count` entries of one channel (same geometry; any two accumulator kinds)
 hipError_t launch_merge(int dkind, void *dst, int skind, const void *src, uint64_t count, hipStream_t s);
+
+// FP64 evaluation, straight from the G matrices, of sum_b s_b T_ch at listed
+// slice entries (documented [plane][K2][K1] order): the reference of the
+// autotuner's accuracy gate.  G elements complex128 (g_in 0) or complex64
+// (g_in 1, widened); `channel` one of CH_MAG, CH_CHG, CH_PP.
+struct RefArgs {
+    const void *gu, *gd;
+    int g_in;
+    int64_t g_stride;        // elements between consecutive matrices
+    const double *sign;      // device, batch weights
+    int batch;
+    int channel;
+    const uint64_t *idx;     // device, count entry indices
+    int64_t count;
+    double *out;             // device, count complex128 values
+    Dims d;
+    Tables t;
+};
+hipError_t launch_ref_entries(const RefArgs &a, hipStream_t s);
+// out[j] = accumulator value at documented entry idx[j] (complex128; a
+// compensated entry as sum - comp)
+hipError_t launch_acc_gather(int acc_kind, const void *acc, const uint64_t *idx, int64_t count, double *out,
+                             int nc, int nw, hipStream_t s);
 
 // Synthetic-input generator (g4_synth.hip).
 hipError_t launch_synth(void *out, int dtype, int lx, int ly, int nw, int nwex, double beta,

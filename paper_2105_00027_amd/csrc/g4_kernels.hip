@@ -238,6 +238,94 @@ __global__ void merge_kernel(int dkind, void *dst, int skind, const void *src, u
     }
 }
 
+// Accumulator values at listed entries of the documented order.
+__global__ void acc_gather_kernel(int kind, const void *acc, const uint64_t *idx, int64_t count, double2 *out,
+                                  int nc, int nw) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = phys_index(idx[j], nc, nw);
+        if (kind == ACC_C128) {
+            out[j] = static_cast<const double2 *>(acc)[e];
+        } else if (kind == ACC_C64_KAHAN) {
+            const float4 v = static_cast<const float4 *>(acc)[e];
+            out[j] = double2{(double)v.x - (double)v.z, (double)v.y - (double)v.w};
+        } else {
+            const float2 v = static_cast<const float2 *>(acc)[e];
+            out[j] = double2{(double)v.x, (double)v.y};
+        }
+    }
+}
+
+// Reference values for the autotuner: one thread per listed entry sums
+// s_b T_ch over the pass in FP64, reading the G elements it needs directly
+// (no staging, no tables beyond the momentum maps and the plane decode).
+__device__ __forceinline__ double2 ref_g(const void *g, int g_in, int64_t off) {
+    if (g_in == 0) return static_cast<const double2 *>(g)[off];
+    const float2 v = static_cast<const float2 *>(g)[off];
+    return double2{(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__global__ void ref_entries_kernel(RefArgs a) {
+    const int n = a.d.n, nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc;
+    const int64_t ng = a.d.ng;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.count;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = a.idx[j];
+        const int K1 = (int)(e % (uint64_t)n), K2 = (int)((e / (uint64_t)n) % (uint64_t)n);
+        const int p = (int)(e / ((uint64_t)n * n));
+        const int2 qm = a.t.plane_qm[p];
+        const int q = qm.x, m = qm.y;
+        const int k1 = K1 / nw, i1 = K1 % nw, k2 = K2 / nw, i2 = K2 % nw;
+        const int64_t r1 = (int64_t)k1 * nwg + i1, r2 = (int64_t)k2 * nwg + i2;
+        double2 acc{0.0, 0.0};
+        for (int b = 0; b < a.batch; ++b) {
+            const int64_t base = (int64_t)b * a.g_stride;
+            double2 t;
+            if (a.channel == CH_PP) {
+                // Q-K: momentum q-k, local frequency m + nw - 1 - i
+                const int64_t s1 = (int64_t)a.t.ksub[q * nc + k1] * nwg + (m + nw - 1 - i1);
+                const int64_t s2 = (int64_t)a.t.ksub[q * nc + k2] * nwg + (m + nw - 1 - i2);
+                const double2 up = zmul(ref_g(a.gu, a.g_in, base + s2 * ng + s1), ref_g(a.gd, a.g_in, base + r2 * ng + r1));
+                const double2 dn = zmul(ref_g(a.gd, a.g_in, base + s2 * ng + s1), ref_g(a.gu, a.g_in, base + r2 * ng + r1));
+                t = double2{up.x + dn.x, up.y + dn.y};
+            } else {
+                // K+Q: momentum k+q, local frequency i + m
+                const int64_t p1 = (int64_t)a.t.kadd[k1 * nc + q] * nwg + i1 + m;
+                const int64_t p2 = (int64_t)a.t.kadd[k2 * nc + q] * nwg + i2 + m;
+                const double sg = a.channel == CH_MAG ? -1.0 : 1.0;
+                const double2 u1 = ref_g(a.gu, a.g_in, base + p1 * ng + r1), d1 = ref_g(a.gd, a.g_in, base + p1 * ng + r1);
+                const double2 u2 = ref_g(a.gu, a.g_in, base + r2 * ng + p2), d2 = ref_g(a.gd, a.g_in, base + r2 * ng + p2);
+                const double2 dir = zmul(double2{u1.x + sg * d1.x, u1.y + sg * d1.y},
+                                         double2{u2.x + sg * d2.x, u2.y + sg * d2.y});
+                const double2 eu = zmul(ref_g(a.gu, a.g_in, base + r2 * ng + r1), ref_g(a.gu, a.g_in, base + p1 * ng + p2));
+                const double2 ed = zmul(ref_g(a.gd, a.g_in, base + r2 * ng + r1), ref_g(a.gd, a.g_in, base + p1 * ng + p2));
+                t = double2{dir.x - eu.x - ed.x, dir.y - eu.y - ed.y};
+            }
+            const double s = a.sign[b];
+            acc.x += s * t.x;
+            acc.y += s * t.y;
+        }
+        reinterpret_cast<double2 *>(a.out)[j] = acc;
+    }
+}
+
+// Sets *flag when any value in the `nwords` 32-bit words is not finite (all
+// exponent bits set): every word is an fp32 value (dbl = 0), or the words pair
+// up into doubles whose odd words hold sign and exponent (dbl = 1).  Lanes that
+// find one store 1; nothing clears the flag here.
+__global__ void finite_check_kernel(const uint32_t *p, size_t nwords, int dbl, int *flag) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const uint32_t mask = dbl ? 0x7ff00000u : 0x7f800000u;
+    const size_t step = dbl ? 2 : 1;
+    bool bad = false;
+    for (size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * step + (dbl ? 1 : 0); i < nwords;
+         i += stride * step)
+        bad |= (p[i] & mask) == mask;
+    if (bad) *flag = 1;
+}
+
 __global__ void fill_zero_kernel(uint4 *p, size_t n16, unsigned char *tail, size_t ntail) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -372,6 +460,29 @@ hipError_t launch_merge(int dkind, void *dst, int skind, const void *src, uint64
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(merge_kernel, dim3(grid_for((int64_t)count, 256)), dim3(256), 0, s, dkind, dst, skind,
                        src, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_ref_entries(const RefArgs &a, hipStream_t s) {
+    if (a.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(ref_entries_kernel, dim3(grid_for(a.count, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_acc_gather(int acc_kind, const void *acc, const uint64_t *idx, int64_t count, double *out,
+                             int nc, int nw, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(acc_gather_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, acc_kind, acc, idx, count,
+                       reinterpret_cast<double2 *>(out), nc, nw);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite_check(const void *p, size_t bytes, int dbl, int *flag, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % (dbl ? 8 : 4) || reinterpret_cast<uintptr_t>(p) % (dbl ? 8 : 4)) return hipErrorInvalidValue;
+    const size_t nwords = bytes / 4;
+    hipLaunchKernelGGL(finite_check_kernel, dim3(grid_for((int64_t)(nwords / (dbl ? 2 : 1)), 256)), dim3(256), 0, s,
+                       static_cast<const uint32_t *>(p), nwords, dbl, flag);
     return hipGetLastError();
 }
 

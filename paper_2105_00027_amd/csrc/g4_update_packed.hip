@@ -31,6 +31,8 @@
 //      (complex64 pairs).
 #include "g4_update.hpp"
 
+#include <cstdlib>
+
 #if !defined(G4_EPT)
 #error "G4_EPT must be defined"
 #endif
@@ -70,6 +72,26 @@ __device__ __forceinline__ void wait_vm(int n) {
 #undef G4_W
         default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
     }
+}
+
+// One block per tile; phase_r (tiles resident per XCD) from the kernel's
+// occupancy, for measurement_phase.
+hipError_t launch_phased(const void *fn, int nitems, int nth, size_t lds, const UpdateArgs &a, hipStream_t s) {
+    if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
+    UpdateArgs arg = a;
+    arg.nitems = nitems;
+    arg.phase_r = 0;
+    if (!std::getenv("G4_NO_PHASE")) {
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) return e;
+        if (hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev); e != hipSuccess)
+            return e;
+        if (hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nth, lds); e != hipSuccess)
+            return e;
+        arg.phase_r = per_cu * cus / kXcds;
+    }
+    void *params[] = {&arg};
+    return hipLaunchKernel(fn, dim3(nitems), dim3(nth), params, lds, s);
 }
 
 // Per-thread copy slots of a tile.  Chunk e = k*NTH + tid of the LDS buffer
@@ -126,6 +148,43 @@ __device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const Packed
     });
 }
 
+// Copy slots of a PH tile in the full group's buffer layout g (MG planes,
+// T2 rows) also when the group has only M < MG planes: rows, columns and
+// planes past the group's end repeat its last one, so every copy stays inside
+// the group's G window and the kernel reads a full tile's layout; entries of
+// the absent planes are computed from those repeats and never stored.
+template <int NTH, int CH, int SLOTS>
+__device__ __forceinline__ void packed_offsets_full(const UpdateArgs &a, const PackedGeom &g, int tid, int q,
+                                                    int k1, int k2, int c0, int T2, int M, int MG, int m_lo,
+                                                    int p0, unsigned (&off)[SLOTS]) {
+    const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
+    const int ldp = a.ldp, pcb = a.pcb;
+    const int rowY = a.t.kadd[k1 * nc + q] * nwg + m_lo;
+    const int colY = a.t.kadd[k2 * nc + q] * pcb + c0 + m_lo;
+    const int64_t dslot = a.dir_slot_stride;
+    const int64_t adelta = static_cast<const char *>(a.dir_a) - static_cast<const char *>(a.pack);
+    const int64_t bdelta = static_cast<const char *>(a.dir_b) - static_cast<const char *>(a.pack);
+    static_for<0, SLOTS>([&](auto k) {
+        const int e = k * NTH + tid;
+        int64_t o = 0;
+        if (e < g.nY) {
+            const int r = min(e / g.ycs, nw + M - 2), c = min(e % g.ycs, T2 + M - 2);
+            o = ((int64_t)(rowY + r) * ldp + colY + c) * 16;
+        } else if (e < g.nG + g.nA) {
+            const int f = e - g.nG, hw = nw / 2;
+            const int sm = f / hw, cc = f - sm * hw;
+            const int sl = sm / MG, m = min(sm - sl * MG, M - 1);
+            o = adelta + (sl * dslot + (int64_t)(p0 + m) * n + k1 * nw + 2 * cc) * 8;
+        } else if (e < g.nbuf) {
+            const int f = e - g.nG - g.nA, ht = T2 / 2;
+            const int sm = f / ht, cc = f - sm * ht;
+            const int sl = sm / MG, m = min(sm - sl * MG, M - 1);
+            o = bdelta + (sl * dslot + (int64_t)(p0 + m) * n + k2 * nw + c0 + 2 * cc) * 8;
+        }
+        off[k] = (unsigned)o;
+    });
+}
+
 // NTH threads per block, NB staging buffers (copies run NB-1 measurements
 // ahead).  Every wave issues the same number S of copy instructions per
 // measurement (lanes past the tile's chunks copy the block's first chunk into
@@ -176,9 +235,15 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         const int bufb = S * NTH * 16;   // bytes per buffer
         const unsigned lds_base = (unsigned)(uintptr_t)(lds_t *)smem_raw;
         const unsigned lds0 = lds_base + wave * 64 * 16;
-        auto issue = [&](int b) __attribute__((always_inline)) {
-            const char *base = static_cast<const char *>(a.pack) + (int64_t)b * a.pack_stride;
-            const unsigned buf = lds0 + (b % NB) * bufb;
+        // measurement phase: step j of the loop takes measurement mb(j)
+        const int b0 = measurement_phase(a, item);
+        auto mb = [&](int j) __attribute__((always_inline)) {
+            const int b = j + b0;
+            return b >= a.batch ? b - a.batch : b;
+        };
+        auto issue = [&](int j) __attribute__((always_inline)) {
+            const char *base = static_cast<const char *>(a.pack) + (int64_t)mb(j) * a.pack_stride;
+            const unsigned buf = lds0 + (j % NB) * bufb;
             static_for<0, SLOTS>([&](auto k) {
                 if (k < S) dma16(base, off[k], buf + k * NTH * 16);
             });
@@ -200,9 +265,9 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         // block into registers, one measurement ahead (the loop waits for every
         // outstanding load before its barrier, so these add no wait)
         float4 xr[EPT], xn[EPT];
-        auto load_x = [&](int b, float4 *dst) __attribute__((always_inline)) {
+        auto load_x = [&](int jb, float4 *dst) __attribute__((always_inline)) {
             const float4 *blk = reinterpret_cast<const float4 *>(static_cast<const char *>(a.pack) +
-                                                                 (int64_t)b * a.pack_stride);
+                                                                 (int64_t)mb(jb) * a.pack_stride);
             static_for<0, EPT>([&](auto j) {
                 const int r = min(r0 + j * RP, T2 - 1);
                 dst[j] = blk[(int64_t)(rowX + r) * ldp + colX + i1];
@@ -212,9 +277,9 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         // AR: this thread's a(Q, K1) for the group's planes (clamped to the
         // group's last plane, whose values the partial path does not use)
         V ar[AR ? MG : 1], an[AR ? MG : 1];
-        auto load_a = [&](int b, V *dst) __attribute__((always_inline)) {
+        auto load_a = [&](int jb, V *dst) __attribute__((always_inline)) {
             const V *pa = reinterpret_cast<const V *>(static_cast<const char *>(a.dir_a) +
-                                                      (int64_t)b * a.pack_stride) + k1 * nw + i1;
+                                                      (int64_t)mb(jb) * a.pack_stride) + k1 * nw + i1;
             static_for<0, MG>([&](auto m) { dst[m] = pa[(int64_t)(p0 + min((int)m, M - 1)) * n]; });
         };
         for (int b = 0; b < NB - 1 && b < a.batch; ++b) issue(b);
@@ -232,7 +297,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
                 if (act && b + 1 < a.batch) load_a(b + 1, an);
             }
             if (!act) continue;
-            const float s = sg[b];
+            const float s = sg[mb(b)];
             const float4 *L = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
             const float4 *Lx = L + pg.nY + pg.nZ;
             // G(K2,K1) times -s_b for the PH exchange (its minus folded in), +s_b for PP
@@ -331,36 +396,47 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
     }
 }
 
-#if G4_EPT == 4
-// Packed operands with the direct term on the matrix cores (nw = 64, 16-row
-// tiles, PH channels).  The copies into LDS are those of the two-buffer packed
-// kernel (same buffer layout, same slot table, G(K2,K1) read into registers one
-// measurement ahead); the thread mapping is the MFMA accumulator layout of
-// v_mfma_f32_16x16x4f32: lane l of wave w holds rows 4*(l/16) + t (t < 4) of
-// column K1 = 16*w + l%16.  The direct term of plane m is the complex rank-B
-// update D(K2, K1) += a_b(Q, K1) b_b(Q, K2); one MFMA pair per measurement and
-// plane takes it with K = 4 = {re, im} of the measurement plus two zero slots:
-//   A[K2][k] from b: (Re b, -Im b) for Re D, (Re b, Im b) for Im D;
-//   B[k][K1] from a: (Re a, Im a) for Re D, (Im a, Re a) for Im D.
-// The exchange Hadamard sum is added into the same registers on the VALU.
+#if G4_EPT == 2
+// Packed operands with the PH direct term on the matrix cores: nw = 64, 8-row
+// tiles, plane groups of MG = 4 or 8, PH channels.  Same copies into LDS as
+// the packed kernel (buffer layout, copy-slot table, G(K2,K1) read into
+// registers one measurement ahead, three blocks per CU), different thread
+// mapping: wave w owns K1 columns 16w..16w+15 of the tile; in lane l (group
+// g = l/16, column cc = l%16) it holds K2 rows 4(g%2)..4(g%2)+3 of plane
+// 2p + g/2 for every plane pair p, which is the output layout of
+// v_mfma_f32_16x16x4f32 when its 16 rows are (8 K2 rows) x (2 planes of a
+// pair).  Per pair and measurement two MFMAs add the complex rank-1 update
+// D(K2, K1) += b(Q, K2) a(Q, K1) of both planes (sign folded into a):
+//   k slot (member, component) of A row (row, member'): b_component(plane of
+//   member, row) when member == member', else 0 (block diagonal);
+//   Re: B = (Re a, -Im a) by component, Im: B = (Im a, Re a);
+// so no k slot holds padding and the VALU only does the exchange Hadamard
+// sum, added into the same registers.  With both PH channels the exchange is
+// computed once and added to each.
 template <int MG, int CH>
-__global__ __launch_bounds__(256, 2) void update_packed_mfma_kernel(UpdateArgs a) {
+__global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kernel(UpdateArgs a) {
     using V = float2;
     using CI = ChanInfo<CH>;
     static_assert(CI::ph && !CI::pp, "PH channels only");
+    static_assert(MG == 4 || MG == 8, "plane pairs");
     typedef float f4 __attribute__((ext_vector_type(4)));
-    constexpr int NTH = 256, NB = 2, TR = 16;     // threads, buffers, tile rows
+    constexpr int NTH = 256, NB = 2, TR = 8, NW = 64, NP = MG / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int l = tid & 63, g4r = l >> 4, c16 = l & 15;
-    constexpr int nw = 64;
+    const int l = tid & 63, g = l >> 4, cc = l & 15;
     const int nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
-    const int i1 = 16 * wave + c16;               // this lane's K1 column
-    constexpr int S = (packed_geom(nw, TR, MG, CH, false).nbuf + NTH - 1) / NTH;   // copies per wave
+    const int i1 = 16 * wave + cc;        // K1 column of this lane (local frequency)
+    const int h = g >> 1;                 // pair member of this lane's outputs
+    const int rb = 4 * (g & 1);           // first of its four K2 rows
+    const int a_row = cc & 7, a_mem = cc >> 3;   // MFMA A row (cc): K2 row, pair member
+    const int k_mem = g >> 1, k_c = g & 1;       // MFMA k slot (g): pair member, component
+    constexpr PackedGeom pgf = packed_geom(NW, TR, MG, CH, false);
+    constexpr int S = (pgf.nbuf + NTH - 1) / NTH;
     static_assert(S <= kPackedSlots, "staging slots");
     float *sg = reinterpret_cast<float *>(smem_raw + NB * S * NTH * 16);
     if (tid < a.batch) sg[tid] = (float)a.sign[tid];
+    const float bsign = k_c ? -1.f : 1.f;
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         __syncthreads();   // a previous tile's LDS reads are done (the launch uses one block per tile)
@@ -368,118 +444,134 @@ __global__ __launch_bounds__(256, 2) void update_packed_mfma_kernel(UpdateArgs a
         const int4 gr = a.t.groups[it.x];
         const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
         const int k1 = it.y, k2 = it.z, c0 = it.w;
-        const PackedGeom pg = packed_geom(nw, TR, M, CH, false);
         const int ldp = a.ldp;
         const int rowX = k2 * nwg + c0, colX = k1 * a.pcb;
         unsigned off[S];
-        packed_offsets<NTH, CH, S>(a, pg, tid, q, k1, k2, c0, TR, M, m_lo, p0, off);
+        packed_offsets_full<NTH, CH, S>(a, pgf, tid, q, k1, k2, c0, TR, M, MG, m_lo, p0, off);
         const int bufb = S * NTH * 16;
         const unsigned lds0 = (unsigned)(uintptr_t)(lds_t *)smem_raw + wave * 64 * 16;
-        auto issue = [&](int b) __attribute__((always_inline)) {
-            const char *base = static_cast<const char *>(a.pack) + (int64_t)b * a.pack_stride;
-            const unsigned buf = lds0 + (b % NB) * bufb;
-            static_for<0, S>([&](auto k) {
-                dma16(base, off[k], buf + k * NTH * 16);
-            });
+        const int b0 = measurement_phase(a, item);
+        auto mb = [&](int j) __attribute__((always_inline)) {
+            const int b = j + b0;
+            return b >= a.batch ? b - a.batch : b;
         };
-        f4 re[CI::count][MG], im[CI::count][MG];
-        static_for<0, CI::count>([&](auto c) {
-            static_for<0, MG>([&](auto m) {
-                re[c][m] = f4{0.f, 0.f, 0.f, 0.f};
-                im[c][m] = f4{0.f, 0.f, 0.f, 0.f};
+        auto issue = [&](int j) __attribute__((always_inline)) {
+            const char *base = static_cast<const char *>(a.pack) + (int64_t)mb(j) * a.pack_stride;
+            const unsigned buf = lds0 + (j % NB) * bufb;
+            static_for<0, S>([&](auto k) { dma16(base, off[k], buf + k * NTH * 16); });
+        };
+        f4 re[CI::nph][NP], im[CI::nph][NP];
+        static_for<0, CI::nph>([&](auto c) {
+            static_for<0, NP>([&](auto p) {
+                re[c][p] = f4{0.f, 0.f, 0.f, 0.f};
+                im[c][p] = f4{0.f, 0.f, 0.f, 0.f};
             });
         });
-        // G(K2,K1) at this lane's four rows, one measurement ahead
+        // G(K2,K1) at this lane's four rows, one measurement ahead: a block base
+        // common to the wave plus this lane's fixed byte offsets
         float4 xr[4], xn[4];
-        auto load_x = [&](int b, float4 *dst) __attribute__((always_inline)) {
-            const float4 *blk = reinterpret_cast<const float4 *>(static_cast<const char *>(a.pack) +
-                                                                 (int64_t)b * a.pack_stride);
-            static_for<0, 4>([&](auto tt) { dst[tt] = blk[(int64_t)(rowX + 4 * g4r + tt) * ldp + colX + i1]; });
+        unsigned xoff[4];
+        static_for<0, 4>([&](auto t) { xoff[t] = (unsigned)(((rowX + rb + t) * ldp + colX + i1) * 16); });
+        auto load_x = [&](int jb, float4 *dst) __attribute__((always_inline)) {
+            const char *blk = static_cast<const char *>(a.pack) + (int64_t)mb(jb) * a.pack_stride;
+            static_for<0, 4>([&](auto t) { dst[t] = *reinterpret_cast<const float4 *>(blk + xoff[t]); });
         };
         if (a.batch > 0) {
             issue(0);
             load_x(0, xr);
         }
-        for (int b = 0; b < a.batch; ++b) {
+        // one measurement: its X values in cur, the next one's loaded into nxt
+        auto step = [&](int j, float4 (&cur)[4], float4 (&nxt)[4]) __attribute__((always_inline)) {
             wait_vm(0);
-            __syncthreads();                 // b's copies landed everywhere; b-1's buffer is free
-            if (b + 1 < a.batch) {
-                issue(b + 1);
-                load_x(b + 1, xn);
+            __syncthreads();                 // j's copies landed everywhere; j-1's buffer is free
+            if (j + 1 < a.batch) {
+                issue(j + 1);
+                load_x(j + 1, nxt);
             }
-            const float s = sg[b];
-            const float4 *Ly = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
-            const V *At = reinterpret_cast<const V *>(Ly + pg.nG);
-            const V *Bt = At + 2 * pg.nA;
-            // G(K2,K1) times -s_b (the PH exchange's minus folded in)
-            V xu[4], xd[4];
-            static_for<0, 4>([&](auto tt) {
-                xu[tt] = V{-s * xr[tt].x, -s * xr[tt].y};
-                xd[tt] = V{-s * xr[tt].z, -s * xr[tt].w};
+            const float s = sg[mb(j)];
+            const unsigned char *L = smem_raw + (j % NB) * bufb;
+            // G(K2,K1) times -s_b in place (the PH exchange's minus folded in)
+            static_for<0, 4>([&](auto t) {
+                cur[t].x *= -s;
+                cur[t].y *= -s;
+                cur[t].z *= -s;
+                cur[t].w *= -s;
             });
-            // direct operands: k slot g4r = {re, im} of measurement b for g4r < 2, zero above
-            const bool live = g4r < 2, comp = g4r & 1;
-            // One plane at a time, software-pipelined: plane m+1's LDS operands are
-            // read before plane m's arithmetic (partial groups clamp the reads).
+            // a partial group was staged in the full layout (see packed_offsets_full)
+            const float4 *Ly = reinterpret_cast<const float4 *>(L);
+            const float *Af = reinterpret_cast<const float *>(L + pgf.nG * 16);   // a: [slot][plane][K1] complex
+            const float *Bf = Af + 4 * pgf.nA;                                     // b: [slot][plane][row] complex
             struct Ops {
                 float4 y[4];
-                V a[CI::count], b[CI::count];
+                float av[CI::nph], br[CI::nph], bi[CI::nph];
             };
-            auto run = [&](auto FULL) __attribute__((always_inline)) {
-                constexpr bool F = decltype(FULL)::value;
-                auto load = [&](int m, Ops &o) __attribute__((always_inline)) {
-                    const int mm = F ? m : min(m, M - 1);
-                    static_for<0, 4>([&](auto tt) { o.y[tt] = Ly[(i1 + mm) * pg.ycs + 4 * g4r + tt + mm]; });
-                    static_for<0, CI::count>([&](auto c) {
-                        const int sm = c * M + mm;
-                        o.b[c] = live ? ld(Bt + sm * TR + c16) : V{0.f, 0.f};
-                        o.a[c] = live ? ld(At + sm * nw + i1) : V{0.f, 0.f};
-                    });
-                };
-                auto compute = [&](auto m, const Ops &o) __attribute__((always_inline)) {
-                    if (!F && !(m < M)) return;
-                    // exchange: sum over spins of G(K2,K1) G(K1+Q,K2+Q), on the VALU
-                    static_for<0, 4>([&](auto tt) {
-                        V ex = cmul(xu[tt], V{o.y[tt].x, o.y[tt].y});
-                        cmac(ex, xd[tt], V{o.y[tt].z, o.y[tt].w});
-                        static_for<0, CI::count>([&](auto c) {
-                            re[c][m][tt()] += ex.x;
-                            im[c][m][tt()] += ex.y;
-                        });
-                    });
-                    // direct: a_b(Q,K1) b_b(Q,K2) on the matrix cores
-                    static_for<0, CI::count>([&](auto c) {
-                        const V bv = o.b[c], av = o.a[c];
-                        const float ar = comp ? -bv.y : bv.x, ai = comp ? bv.y : bv.x;
-                        const float br = comp ? av.y : av.x, bi = comp ? av.x : av.y;
-                        re[c][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re[c][m], 0, 0, 0);
-                        im[c][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, im[c][m], 0, 0, 0);
-                    });
-                };
-                Ops o[2];
-                load(0, o[0]);
-                static_for<0, MG>([&](auto m) {
-                    if constexpr (m + 1 < MG) load(m + 1, o[(m + 1) & 1]);
-                    __builtin_amdgcn_sched_barrier(0);
-                    compute(m, o[m & 1]);
-                    __builtin_amdgcn_sched_barrier(0);
+            auto load = [&](int p, Ops &o) __attribute__((always_inline)) {
+                const int m = 2 * p + h;                 // this lane's output plane
+                static_for<0, 4>([&](auto t) { o.y[t] = Ly[(i1 + m) * pgf.ycs + rb + t + m]; });
+                static_for<0, CI::nph>([&](auto c) {
+                    const float *pbv = Bf + ((c * MG + 2 * p + a_mem) * TR + a_row) * 2 + k_c;
+                    o.av[c] = k_mem == a_mem ? *pbv : 0.f;     // block-diagonal A
+                    const float *pav = Af + ((c * MG + 2 * p + k_mem) * NW + i1) * 2;
+                    o.br[c] = pav[k_c];
+                    o.bi[c] = pav[1 - k_c];
                 });
             };
-            if (M == MG) run(std::true_type{});
-            else run(std::false_type{});
-            static_for<0, 4>([&](auto tt) { xr[tt] = xn[tt]; });
-        }
-        const int64_t nn = (int64_t)n * n;
-        const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * nw * nw + (int64_t)c0 * nw + i1;
-        // one plane at a time, so that the accumulator reads in flight stay few
-        static_for<0, MG>([&](auto m) {
-            if (m >= M) return;
-            static_for<0, 4>([&](auto tt) {
-                const int64_t e = ebase + m * nn + (int64_t)(4 * g4r + tt) * nw;
-                if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, V{re[0][m][tt()], im[0][m][tt()]});
-                if (CI::chg)
-                    acc_update(a.acc[1], a.acc_kind, e, V{re[CI::slot_chg][m][tt()], im[CI::slot_chg][m][tt()]});
+            auto compute = [&](auto p, const Ops &o) __attribute__((always_inline)) {
+                // exchange: sum over spins of G(K2,K1) G(K1+Q,K2+Q), on the VALU;
+                // straight into the accumulator of one channel, or once for both
+                static_for<0, 4>([&](auto t) {
+                    const V xu{cur[t].x, cur[t].y}, xd{cur[t].z, cur[t].w};
+                    if constexpr (CI::nph == 1) {
+                        V acc{re[0][p][t()], im[0][p][t()]};
+                        cmac(acc, xu, V{o.y[t].x, o.y[t].y});
+                        cmac(acc, xd, V{o.y[t].z, o.y[t].w});
+                        re[0][p][t()] = acc.x;
+                        im[0][p][t()] = acc.y;
+                    } else {
+                        V ex = cmul(xu, V{o.y[t].x, o.y[t].y});
+                        cmac(ex, xd, V{o.y[t].z, o.y[t].w});
+                        static_for<0, CI::nph>([&](auto c) {
+                            re[c][p][t()] += ex.x;
+                            im[c][p][t()] += ex.y;
+                        });
+                    }
+                });
+                // direct: b(Q,K2) a(Q,K1) of both planes of the pair on the matrix cores
+                static_for<0, CI::nph>([&](auto c) {
+                    re[c][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.av[c], bsign * o.br[c], re[c][p], 0, 0, 0);
+                    im[c][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.av[c], o.bi[c], im[c][p], 0, 0, 0);
+                });
+            };
+            // pair p+1's LDS operands are read before pair p's arithmetic
+            Ops o[2];
+            load(0, o[0]);
+            static_for<0, NP>([&](auto p) {
+                if constexpr (p + 1 < NP) load(p + 1, o[(p + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(p, o[p & 1]);
+                __builtin_amdgcn_sched_barrier(0);
             });
+        };
+        // X registers alternate between xr and xn (no copies between steps)
+        int j = 0;
+        for (; j + 1 < a.batch; j += 2) {
+            step(j, xr, xn);
+            step(j + 1, xn, xr);
+        }
+        if (j < a.batch) step(j, xr, xn);
+        const int64_t nn = (int64_t)n * n;
+        const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * NW * NW + (int64_t)(c0 + rb) * NW + i1;
+        // one pair at a time, so that the accumulator reads in flight stay few
+        static_for<0, NP>([&](auto p) {
+            const int m = 2 * p + h;
+            if (m < M) {
+                static_for<0, 4>([&](auto t) {
+                    const int64_t e = ebase + m * nn + (int64_t)t * NW;
+                    if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, V{re[0][p][t()], im[0][p][t()]});
+                    if (CI::chg)
+                        acc_update(a.acc[1], a.acc_kind, e, V{re[CI::slot_chg][p][t()], im[CI::slot_chg][p][t()]});
+                });
+            }
             __builtin_amdgcn_sched_barrier(0);
         });
     }
@@ -491,17 +583,10 @@ hipError_t launch_packed_mfma_ch(int channels, int nitems, size_t lds, const Upd
     switch (channels) {
         case 1: fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 1>); break;
         case 2: fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 2>); break;
-        case 3:   // both PH channels: register budget allows plane groups up to 4
-            if constexpr (MG <= 4) fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 3>);
-            else return hipErrorInvalidValue;
-            break;
+        case 3: fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 3>); break;
         default: return hipErrorInvalidValue;
     }
-    if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
-    UpdateArgs arg = a;
-    arg.nitems = nitems;
-    void *params[] = {&arg};
-    return hipLaunchKernel(fn, dim3(nitems), dim3(256), params, lds, s);
+    return launch_phased(fn, nitems, 256, lds, a, s);
 }
 #endif
 
@@ -544,11 +629,7 @@ hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateAr
         default:
             return hipErrorInvalidValue;
     }
-    if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
-    UpdateArgs arg = a;
-    arg.nitems = nitems;
-    void *params[] = {&arg};
-    return hipLaunchKernel(fn, dim3(nitems), dim3(NTH), params, lds, s);
+    return launch_phased(fn, nitems, NTH, lds, a, s);
 }
 
 template <int NTH, int NB>
@@ -581,13 +662,12 @@ hipError_t G4_PNAME(G4_EPT)(int channels, int mgroup, int nitems, size_t lds, co
 #endif
 }
 
-#if G4_EPT == 4
-// packed operands, direct term on MFMA: nw = 64, 16-row tiles, PH channels
+#if G4_EPT == 2
+// packed operands, direct term on MFMA: nw = 64, 8-row tiles, PH channels
 hipError_t launch_update_packed_mfma(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,
                                      hipStream_t s) {
-    if (a.d.nw != 64 || a.tile != 16 || (channels & CH_PP)) return hipErrorInvalidValue;
+    if (a.d.nw != 64 || a.tile != 8 || (channels & CH_PP)) return hipErrorInvalidValue;
     switch (mgroup) {
-        case 1: return upd::launch_packed_mfma_ch<1>(channels, nitems, lds, a, s);
         case 4: return upd::launch_packed_mfma_ch<4>(channels, nitems, lds, a, s);
         case 8: return upd::launch_packed_mfma_ch<8>(channels, nitems, lds, a, s);
         default: return hipErrorInvalidValue;

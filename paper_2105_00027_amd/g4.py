@@ -57,7 +57,7 @@ class g4_config(ctypes.Structure):
 class g4_tune_result(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("tile", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("ms_per_measurement", ctypes.c_double),
-                ("rel_err", ctypes.c_double)]
+                ("rel_err_fp64", ctypes.c_double)]
 
 
 class g4_stats_t(ctypes.Structure):

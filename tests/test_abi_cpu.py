@@ -28,6 +28,21 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(g4.EXPORTS)
 
 
+def test_every_declaration_names_its_passage():
+    """Each entry point's comment names the passage of the paper it implements
+    (a section, an equation or an algorithm), or says that none exists."""
+    with open(os.path.join(ROOT, "include", "g4.h")) as f:
+        text = f.read()
+    for name in declared_functions():
+        m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*(?:int|void|const char \*)\s*\*?\s*%s\s*\(" % name,
+                      text, re.S)
+        assert m, "%s has no comment block right before it" % name
+        comment = m.group(1)
+        assert "Paper:" in comment, "%s: no 'Paper:' line" % name
+        cite = comment[comment.index("Paper:"):]
+        assert re.search(r"section|Eq\. \(\d\)|Algorithm \d|no passage", cite), (name, cite)
+
+
 def base(**kw):
     d = dict(lx=4, ly=4, nw=64, nwex=8, nq=16, q_begin=0, q_end=128)
     d.update(kw)
@@ -169,22 +184,24 @@ def test_index_maps_bit_exact(w):
 
 def test_packed_mfma_plan_accepted_and_bounded():
     """G4_F_PACKED | G4_F_MFMA: packed operands with the direct term on MFMA;
-    nw = 64, 16-row tiles, PH channels, at most 8 channel-planes per thread
-    group; the packed buffer is sized as for G4_F_PACKED."""
+    nw = 64, 8-row tiles, plane pairs (nwex >= 2), PH channels (one or both);
+    the packed buffer is sized as for G4_F_PACKED."""
     PM = g4.G4_F_PACKED | g4.G4_F_MFMA
     ok = base(mode=1, max_batch=16, prod=1, g_in=1, flags=PM)
-    packed = base(mode=1, max_batch=16, prod=1, g_in=1, flags=g4.G4_F_PACKED, tile=16)
+    packed = base(mode=1, max_batch=16, prod=1, g_in=1, flags=g4.G4_F_PACKED, tile=8)
     assert g4.g4_slice_size(ok) == g4.g4_slice_size(packed)      # same buffers at the same tile
-    assert g4.g4_slice_size(base(mode=1, max_batch=16, prod=1, g_in=1, flags=PM, tile=16))[0] > 0
+    assert g4.g4_slice_size(base(mode=1, max_batch=16, prod=1, g_in=1, flags=PM, tile=8))[0] > 0
     assert g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=PM, nwex=4, q_end=64,
+                                 channels=g4.G4_PH_MAGNETIC | g4.G4_PH_CHARGE))[0] > 0
+    assert g4.g4_slice_size(base(mode=1, max_batch=8, prod=1, g_in=1, flags=PM,
                                  channels=g4.G4_PH_MAGNETIC | g4.G4_PH_CHARGE))[0] > 0
     for kw in (dict(nw=128),                                        # 64 columns per block
                dict(nw=32),
                dict(channels=g4.G4_PP_UPDOWN),                      # PH channels only
                dict(channels=g4.G4_PH_MAGNETIC | g4.G4_PP_UPDOWN),
-               dict(tile=8),                                        # 16-row tiles
-               dict(prod=2),                                        # split direct term runs apart
-               dict(channels=g4.G4_PH_MAGNETIC | g4.G4_PH_CHARGE)):  # 2 channels x 8 planes
+               dict(tile=16),                                       # 8-row tiles
+               dict(nwex=1, q_end=16),                              # plane pairs
+               dict(prod=2)):                                       # split direct term runs apart
         with pytest.raises(g4.G4Error) as e:
             g4.g4_slice_size(base(**{**dict(mode=1, max_batch=8, prod=1, g_in=1, flags=PM), **kw}))
         assert e.value.code == g4.G4_E_UNSUPPORTED, kw

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from gpu_common import config_for, g4mod
-from metrics import rel_fro
+from metrics import check_entries, rel_fro
 from oracle import sampled
 from synth import C1_TINY, C2_PLAIN, C3_BATCHED, C4_RING, C5_SPLIT, signs
 
@@ -56,19 +56,27 @@ def test_plain_slice_full_size():
         free()
     assert st["measurements"] == M and st["launches"] == M
     want = sampled.entries(w, 1, idx, 0, M)
-    assert rel_fro(got, want) <= 1e-12
+    check_entries(got, want, 1e-12)
 
 
-@pytest.mark.parametrize("acc,flags", [(0, 0), (1, 0), (0, 8), (0, 16), (1, 16), (0, 32), (0, 24), (1, 24)],
+FULL_PLANS = [(0, 0, 16, 0), (1, 0, 16, 0), (0, 8, 16, 0), (0, 16, 16, 0), (1, 16, 16, 0), (0, 32, 16, 0),
+              (0, 24, 16, 0), (1, 24, 16, 0),
+              # the benchmark's plan: packed operands, 8-row tiles, passes of 64
+              (0, 16, 64, 8), (1, 16, 64, 8)]
+
+
+@pytest.mark.parametrize("acc,flags,B,tile", FULL_PLANS,
                          ids=["acc-c128", "acc-kahan", "mfma", "packed", "packed-kahan", "deep",
-                              "packed-mfma", "packed-mfma-kahan"])
-def test_batched_full_size(acc, flags):
-    """The same slice, 4096 measurements in passes of 16, complex64 G, FP32 products."""
+                              "packed-mfma", "packed-mfma-kahan", "bench-plan", "bench-plan-kahan"])
+def test_batched_full_size(acc, flags, B, tile):
+    """The same slice, 4096 measurements in passes of B, complex64 G, FP32 products."""
     g4 = g4mod()
     w = C3_BATCHED
-    M, B, chunk = w.measurements, w.batch, 512
-    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=B, flags=flags))
+    M, chunk = w.measurements, 512
+    h = g4.g4_init_slice(config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=B, tile=tile, flags=flags))
     try:
+        st = g4.g4_stats(h)
+        assert st["batch"] == B and (tile == 0 or st["tile"] == tile)
         for b0 in range(0, M, chunk):
             gu, gd = device_g(w, 1, b0, chunk)
             g4.g4_accumulate(h, gu, gd, signs(w, b0, chunk))
@@ -76,11 +84,13 @@ def test_batched_full_size(acc, flags):
             del gu, gd
         idx = sampled.sample_indices(w, 128, seed=2)
         got = readback_sample(h, 1, idx)
+        st = g4.g4_stats(h)
     finally:
         g4.g4_destroy(h)
         free()
+    assert st["launches"] == M // B and st["measurements"] == M
     want = sampled.entries(w, 1, idx, 0, M)
-    assert rel_fro(got, want) <= 1e-6
+    check_entries(got, want, 1e-6)
 
 
 @pytest.mark.parametrize("flags", [0, 16], ids=["valu", "packed"])
@@ -108,7 +118,7 @@ def test_ring_share_slice(flags):
     want = np.zeros(len(idx), dtype=np.complex128)
     for walker in order:
         want += sampled.entries(w, 1, idx, walker * per, per)
-    assert rel_fro(got, want) <= 1e-6
+    check_entries(got, want, 1e-6)
 
 
 @pytest.mark.parametrize("prod,bar", [(1, 1e-6), (3, 1e-6), (2, 2.0 ** -15 + 1e-6)],
@@ -131,10 +141,9 @@ def test_three_channel_quarter_slice(prod, bar):
     finally:
         g4.g4_destroy(h)
         free()
-    errs = {ch: rel_fro(got[ch], sampled.entries(w, ch, idx, 0, M)) for ch in (1, 2, 4)}
-    print("three-channel quarter slice, prod %d: sampled relative errors %s" % (prod, errs))
-    for ch, e in errs.items():
-        assert e <= bar, (ch, e)
+    errs = {ch: check_entries(got[ch], sampled.entries(w, ch, idx, 0, M), bar, what="channel %d" % ch)
+            for ch in (1, 2, 4)}
+    print("three-channel quarter slice, prod %d: sampled errors %s" % (prod, errs))
 
 
 def test_long_run_stability():

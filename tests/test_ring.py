@@ -1,13 +1,15 @@
 """The in-process ring delivery: order (CPU) and double-buffered streaming on the
-GPU, which must give exactly the sequential result and be invariant, to
-rounding, under the rank (rotation of the order)."""
+GPU, which must give exactly the sequential result, be invariant, to
+rounding, under the rank (rotation of the order), and match the FP64 oracle
+applied to the same buffers in the same order."""
 import numpy as np
 import pytest
 
 from gpu_common import config_for, g4mod
-from metrics import rel_fro
+from metrics import check_entries, rel_fro
+from oracle import ref
 from paper_2105_00027_amd.ring import ring_order
-from synth import Workload, signs
+from synth import Workload, g_matrices, signs
 
 
 def test_ring_order_properties():
@@ -68,3 +70,52 @@ def test_streamed_ring_matches_sequential_and_rotation():
     for ch in (1, 2, 4):
         assert np.array_equal(seq[ch], strm[ch])
         assert rel_fro(rot[ch], seq[ch]) <= 1e-15
+    # the oracle on the same buffers, in rank 2's ring order
+    want = oracle_ring(2, S, per)
+    for ch in (1, 2, 4):
+        check_entries(strm[ch], want[ch], 1e-12, what="channel %d" % ch)
+
+
+def oracle_ring(rank, S, per):
+    order = ring_order(rank, S)
+    gu = np.concatenate([g_matrices(W, wk * per, per, 0) for wk in order])
+    gd = np.concatenate([g_matrices(W, wk * per, per, 1) for wk in order])
+    s = np.concatenate([signs(W, wk * per, per) for wk in order])
+    return {ch: ref.accumulate(W, ch, gu, gd, s).reshape(-1) for ch in (1, 2, 4)}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("acc", [0, 1], ids=["acc-c128", "acc-kahan"])
+def test_streamed_ring_fp32_packed_matches_oracle(acc):
+    """The benchmark's product path (complex64 G, FP32 products, packed operands)
+    fed by the double-buffered ring delivery: two passes per walker buffer."""
+    import torch
+    from paper_2105_00027_amd import ring
+    g4 = g4mod()
+    S, per, rank = 4, 3, 1
+    main = torch.cuda.Stream()
+    copy = torch.cuda.Stream()
+    sg = {wk: signs(W, wk * per, per) for wk in range(S)}
+
+    def deliver(walker, bu, bd, stream):
+        for spin, buf in ((0, bu), (1, bd)):
+            g4.g4_synth_fill(buf, 1, W.lx, W.ly, W.nw, W.nwex, W.beta, W.t, W.mu, W.h, W.noise,
+                             W.seed, W.wid, walker * per, per, spin, stream.cuda_stream)
+
+    cfg = config_for(W, mode=1, prod=1, g_in=1, acc=acc, batch=2, flags=g4.G4_F_PACKED,
+                     stream=main.cuda_stream)
+    h = g4.g4_init_slice(cfg)
+    bufs = [tuple(torch.empty((per, W.ng, W.ng), dtype=torch.complex64, device="cuda")
+                  for _ in range(2)) for _ in range(2)]
+    try:
+        ring.stream_ring(h, deliver, sg, rank, S, bufs, main, copy)
+        g4.g4_sync(h)
+        got = {ch: g4.g4_readback(h, ch) for ch in (1, 2, 4)}
+        st = g4.g4_stats(h)
+    finally:
+        torch.cuda.synchronize()
+        g4.g4_destroy(h)
+    assert st["measurements"] == S * per and st["launches"] == 2 * S
+    want = oracle_ring(rank, S, per)
+    for ch in (1, 2, 4):
+        check_entries(got[ch], want[ch], 1e-6, what="channel %d" % ch)
