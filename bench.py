@@ -290,6 +290,58 @@ class Bench:
             torch.cuda.empty_cache()
         return out
 
+    def ring_threads(self, w, k, per, S, rank, pool_bufs, flags, tile, nsample=96):
+        """The multi-threaded ring on one rank: k walker threads per rank, k
+        independent rings; each thread's buffer of `per` measurements is
+        delivered (a device-to-device copy from a resident pool of pool_bufs
+        distinct buffers, the stand-in for the receive) on that thread's own
+        stream into one of its two buffers while the slice accumulates on the
+        main stream.  The timed region covers the whole ring, deliveries
+        included."""
+        g4, torch = self.g4, self.torch
+        from paper_2105_00027_amd import ring
+        from synth import signs
+        pool = [tuple(torch.empty((per, w.ng, w.ng), dtype=torch.complex64, device=self.dev) for _ in range(2))
+                for _ in range(pool_bufs)]
+        for i, (pu, pd) in enumerate(pool):
+            self.fill(w, pu, g4.G4_IN_C64, i * per, per, 0)
+            self.fill(w, pd, g4.G4_IN_C64, i * per, per, 1)
+        src_of = lambda r, t: (r * k + t) % pool_bufs
+        sg = {(r, t): signs(w, src_of(r, t) * per, per) for r in range(S) for t in range(k)}
+        bufs = [[tuple(torch.empty((per, w.ng, w.ng), dtype=torch.complex64, device=self.dev) for _ in range(2))
+                 for _ in range(2)] for _ in range(k)]
+        copies = [torch.cuda.Stream(device=self.dev) for _ in range(k)]
+
+        def deliver(r, t, bu, bd, stream):
+            with torch.cuda.stream(stream):
+                pu, pd = pool[src_of(r, t)]
+                bu.copy_(pu, non_blocking=True)
+                bd.copy_(pd, non_blocking=True)
+
+        h = g4.g4_init_slice(self.cfg(w, mode=g4.G4_MODE_BATCHED, prod=g4.G4_PROD_F32, g_in=g4.G4_IN_C64,
+                                      acc=g4.G4_ACC_C128, max_batch=per, tile=tile, flags=flags))
+        out = {}
+        try:
+            ring.stream_ring_threads(h, deliver, sg, rank, S, bufs, self.stream, copies)   # warm-up
+            g4.g4_sync(h)
+            g4.g4_reset(h)
+            torch.cuda.synchronize()
+            ms = self.timed(lambda i: ring.stream_ring_threads(h, deliver, sg, rank, S, bufs, self.stream, copies), 1)
+            st = g4.g4_stats(h)
+            out["ms"] = ms
+            out["stats"] = st
+            seq = [(r, t) for r in ring.ring_order(rank, S) for t in range(k)]
+            b_seq = [src_of(*x) * per + j for x in seq for j in range(per)]
+            sign_seq = np.concatenate([sg[x] for x in seq])
+            if not self.args.no_check:
+                out["error"] = sampled_error(w, h, g4, 1, b_seq, sign_seq, nsample, 1e-6)
+        finally:
+            g4.g4_destroy(h)
+            del pool, bufs
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        return out
+
     def plain(self, w, M, tile=0, reps=REPS):
         """Plain FP64 leg: M measurements, one pass each, timed `reps` times."""
         g4, torch = self.g4, self.torch
@@ -487,6 +539,19 @@ def main():
         res = bench.batched(ring_w, 16, ring_runs, 8, 2, acc=0, flags=g4.G4_F_PACKED, tile=4,
                             nsample=96, reps=REPS)
         leg["batched"] = leg_line(ring_w, res, 16, 8, 8, 16, 0)
+        # the multi-threaded ring: 2 walker threads per rank, deliveries on their
+        # own streams overlapping the accumulation
+        k, per = 2, 16
+        rt = bench.ring_threads(ring_w, k, per, 8, 3, 4, g4.G4_F_PACKED, 4)
+        n_meas = 8 * k * per
+        leg["streamed_threads"] = {
+            "threads": k, "measurements": n_meas, "ms": rt["ms"],
+            "value": ring_w.entries * n_meas / (rt["ms"] / 1e3), "unit": "entry-updates/s",
+            "delivery": "device-to-device copy of each thread's buffer (16 measurements, 2 x %.0f MB) on "
+                        "that thread's stream into one of its two buffers" % (per * ring_w.ng ** 2 * 8 / 1e6),
+            "timed": "the whole ring, deliveries included"}
+        if "error" in rt:
+            leg["streamed_threads"]["error"] = rt["error"]
         if not args.no_plain:
             leg["plain_fp64"] = plain_line(ring_w, bench.plain(ring_w, 8), 8)
             leg["speedup_vs_plain_fp64"] = leg["batched"]["value"] / leg["plain_fp64"]["value"]
@@ -501,7 +566,8 @@ def main():
                            "accumulators" % sw.entries}
         for name, prod, gate in (("f32", g4.G4_PROD_F32, 1e-6), ("f16x2", g4.G4_PROD_F16X2, 1e-6),
                                  ("bf16x2", g4.G4_PROD_BF16X2, 2.0 ** -15 + 1e-6)):
-            res = bench.batched(sw, 32, [(0, 64)], 2, 1, prod=prod, acc=g4.G4_ACC_C64_KAHAN,
+            # packed operands for every product kind (the split kinds imply them)
+            res = bench.batched(sw, 32, [(0, 64)], 2, 1, prod=prod, acc=g4.G4_ACC_C64_KAHAN, flags=g4.G4_F_PACKED,
                                 err_channels=(1, 2, 4), nsample=64, gate=gate)
             line = leg_line(sw, res, 32, 2, 8, 16, g4.G4_ACC_C64_KAHAN,
                             direct_elsewhere=prod in (g4.G4_PROD_F16X2, g4.G4_PROD_BF16X2))

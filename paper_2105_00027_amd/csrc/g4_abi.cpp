@@ -362,41 +362,6 @@ void build_work(const Plan &P, int nwex, int order, std::vector<int4> &groups,
         spread_over_xcds(sorted, items);
         return;
     }
-    if (order == 4) {
-        // Inside a class, coset cubes.  H is the subgroup of momenta along the
-        // longer lattice axis; for k1 in one coset of H and q in one coset of H,
-        // the tiles read exchange blocks whose rows k1+q lie in a single coset
-        // (|H| of them), |H| G(K2,K1) row blocks and |H|^2 direct vectors, each
-        // shared by |H| tiles.  Consecutive tiles on an XCD run concurrently
-        // (all resident tiles start and end within about one tile's time of
-        // each other), so such a cube, with all its K2 row tiles, is what a
-        // round of resident tiles should hold.  Cubes of one k1 coset follow
-        // each other, so neighbouring cubes share their G(K2,K1) rows.
-        const bool xaxis = d.lx >= d.ly;
-        auto coset = [&](int k) { return xaxis ? k / d.lx : k % d.lx; };   // coordinate off H
-        const int ncos = xaxis ? d.ly : d.lx;
-        std::vector<int> done(d.nc, 0);
-        std::vector<int4> sorted;
-        sorted.reserve((size_t)ng * d.nc * d.nc * ntile);
-        for (int dd = 0; dd < d.nc; ++dd) {
-            if (done[dd]) continue;
-            const int neg = sub(0, dd);
-            done[dd] = done[neg] = 1;
-            const int members[2] = {dd, neg};
-            for (int mi = 0; mi < (neg == dd ? 1 : 2); ++mi)
-                for (int a = 0; a < ncos; ++a)
-                    for (int bq = 0; bq < ncos; ++bq)
-                        for (int c = 0; c < ntile; ++c)
-                            for (int k1 = 0; k1 < d.nc; ++k1) {
-                                if (coset(k1) != a) continue;
-                                for (int g = 0; g < ng; ++g)
-                                    if (coset(groups[(size_t)g].x) == bq)
-                                        sorted.push_back(int4{g, k1, sub(k1, members[mi]), c * P.tile});
-                            }
-        }
-        spread_over_xcds(sorted, items);
-        return;
-    }
     // order 2: inside a class, windows of bk momenta k1 (neighbours along a
     // lattice row) x bg consecutive plane groups x half the K2 tiles, so that
     // the tiles resident together read few G(K2,K1) and exchange blocks
@@ -680,7 +645,6 @@ int enqueue_pass(g4_slice *h, const void *pu, const void *pd, const double *ds, 
     ua.pcb = P.pcb;
     ua.nitems = h->nitems;
     ua.skip_direct = P.split && P.slots ? 1 : 0;
-    ua.phase_r = 0;            // set by the packed launchers
     ua.sign = ds;
     ua.batch = nb;
     ua.acc[0] = h->acc[0];
@@ -865,7 +829,7 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     h->cfg.q_list = nullptr;
     h->P = P;
     h->device = cfg->device;
-    if (const char *o = std::getenv("G4_TILE_ORDER")) h->order = std::min(4, std::max(0, std::atoi(o)));
+    if (const char *o = std::getenv("G4_TILE_ORDER")) h->order = std::min(3, std::max(0, std::atoi(o)));
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) {
         delete h;

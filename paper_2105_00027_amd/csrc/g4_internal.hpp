@@ -79,8 +79,6 @@ struct UpdateArgs {
     int nitems;               // work tiles in the list (one block per tile)
     int skip_direct;          // packed kernel: 1 = the PH direct term is added by
                               // direct_split_kernel; the tile's direct vectors read as zeros
-    int phase_r;              // packed kernel: tiles resident at once per XCD (0: every tile
-                              // takes the pass's measurements in order; see measurement_phase)
     Dims d;
     Tables t;
 };
@@ -177,7 +175,26 @@ hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
 // 2 = packed operands staged straight into LDS (kind 2, even tile).
 hipError_t launch_update(int kind, int channels, int ept, int mgroup, int nitems, int variant,
                          const UpdateArgs &a, hipStream_t s);
-size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant);
+// LDS bytes of one update block (host arithmetic, also used by the validation)
+inline size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant) {
+    if (variant == 2 || variant == 3 || variant == 4) {
+        // staging buffers of 16-byte chunks, rotating by measurement
+        const bool deep = variant == 3;
+        const bool areg = variant == 2 && packed_a_in_regs(d.nw, tile, mgroup, channels, deep);
+        return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels, deep, areg), deep);
+    }
+    // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct
+    // vectors (two copies, by measurement parity, for the MFMA variant)
+    const size_t el = kind == 2 ? sizeof(float2) : sizeof(double2);
+    const int T2 = tile < d.nw ? tile : d.nw;
+    const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
+    size_t pairs = (size_t)T2 * d.nw;
+    if (nph) pairs += (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
+    if (channels & CH_PP) pairs += (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
+    const size_t vecs = (size_t)nph * mgroup * (d.nw + T2) * (variant == 1 ? 2 : 1);
+    return pairs * 2 * el + vecs * el;
+}
+
 // Packed operands with the direct term on MFMA (variant 4): nw = 64, tile 8, plane groups of
 // 4 or 8, PH channels.
 hipError_t launch_update_packed_mfma(int channels, int mgroup, int nitems, size_t lds, const UpdateArgs &a,

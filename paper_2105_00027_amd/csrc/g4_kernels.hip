@@ -358,25 +358,6 @@ hipError_t launch_update_mfma(int channels, int slabs, int mgroup, int nitems, s
 G4_PDECL(1) G4_PDECL(2) G4_PDECL(4) G4_PDECL(8)
 #undef G4_PDECL
 
-size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, const Dims &d, int variant) {
-    if (variant == 2 || variant == 3 || variant == 4) {
-        // staging buffers of 16-byte chunks, rotating by measurement
-        const bool deep = variant == 3;
-        const bool areg = variant == 2 && packed_a_in_regs(d.nw, tile, mgroup, channels, deep);
-        return packed_lds_bytes(packed_geom(d.nw, tile < d.nw ? tile : d.nw, mgroup, channels, deep, areg), deep);
-    }
-    // [exchange block | PP block | G(K2,K1) rows] as spin pairs, then the direct
-    // vectors (two copies, by measurement parity, for the MFMA variant)
-    const size_t el = kind == 2 ? sizeof(float2) : sizeof(double2);
-    const int T2 = tile < d.nw ? tile : d.nw;
-    const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
-    size_t pairs = (size_t)T2 * d.nw;
-    if (nph) pairs += (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
-    if (channels & CH_PP) pairs += (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
-    const size_t vecs = (size_t)nph * mgroup * (d.nw + T2) * (variant == 1 ? 2 : 1);
-    return pairs * 2 * el + vecs * el;
-}
-
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s) {
     const int64_t total = (int64_t)a.batch * a.d.planes * a.d.n;
     if (total == 0) return hipSuccess;

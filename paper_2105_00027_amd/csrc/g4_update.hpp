@@ -100,21 +100,6 @@ __device__ __forceinline__ void acc_st(V *p, V v) {
     nt_st(&p->y, v.y);
 }
 
-// First measurement of a packed tile's loop (it then wraps around the pass).
-// Tiles are dispatched round-robin over the 8 XCDs, and on an XCD each starts
-// when a resident one ends, so in steady state the phase_r tiles resident on
-// an XCD started evenly spread over one tile's lifetime.  Tile i (XCD-local
-// index i/8) starting at measurement i/8 * batch / phase_r puts every resident
-// tile on about the same measurement at any moment: the operands live at
-// once are those of a few measurements, not of the whole pass, and stay in
-// the L2 and the last-level cache.  The sums are the same (each tile still
-// takes every measurement once, in a fixed order: deterministic).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int measurement_phase(const UpdateArgs &a, int item) {
-    if (a.phase_r <= 0 || a.batch <= 1) return 0;
-    return (int)(((int64_t)(item / kXcds) * a.batch / a.phase_r) % a.batch);
-}
-
 // Accumulator read-modify-write of one entry.
 template <typename V>
 __device__ __forceinline__ void acc_update(void *base, int kind, int64_t e, V v) {

@@ -31,8 +31,6 @@
 //      (complex64 pairs).
 #include "g4_update.hpp"
 
-#include <cstdlib>
-
 #if !defined(G4_EPT)
 #error "G4_EPT must be defined"
 #endif
@@ -74,38 +72,41 @@ __device__ __forceinline__ void wait_vm(int n) {
     }
 }
 
-// One block per tile; phase_r (tiles resident per XCD) from the kernel's
-// occupancy, for measurement_phase.
-hipError_t launch_phased(const void *fn, int nitems, int nth, size_t lds, const UpdateArgs &a, hipStream_t s) {
+// One block per tile.
+hipError_t launch_block_per_tile(const void *fn, int nitems, int nth, size_t lds, const UpdateArgs &a,
+                                 hipStream_t s) {
     if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
     UpdateArgs arg = a;
     arg.nitems = nitems;
-    arg.phase_r = 0;
-    if (!std::getenv("G4_NO_PHASE")) {
-        int per_cu = 0, cus = 0, dev = 0;
-        if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) return e;
-        if (hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev); e != hipSuccess)
-            return e;
-        if (hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nth, lds); e != hipSuccess)
-            return e;
-        arg.phase_r = per_cu * cus / kXcds;
-    }
     void *params[] = {&arg};
     return hipLaunchKernel(fn, dim3(nitems), dim3(nth), params, lds, s);
 }
+
+// Geometry of a tile's staging buffer, known at run time (GeoRt) or, for
+// full tiles of a compile-time-nw kernel copy, at compile time (GeoCt), where
+// the divisions of the copy-slot table become multiply-shifts.
+struct GeoRt {
+    int nw, T2, M, zc;
+    PackedGeom g;
+};
+template <int NW, int T2_, int M_, int CH, bool XL, bool AR>
+struct GeoCt {
+    static constexpr int nw = NW, T2 = T2_, M = M_, zc = NW + M_ - 1;
+    static constexpr PackedGeom g = packed_geom(NW, T2_, M_, CH, XL, AR);
+};
 
 // Per-thread copy slots of a tile.  Chunk e = k*NTH + tid of the LDS buffer
 // [Y | Z | X | A | Bv] comes from byte offset off[k] of a measurement's packed
 // block (its G matrix followed by its direct vectors, see pack_gather_kernel);
 // chunks past the tile's end take offset 0 and land in the buffer's padding.
 // G rows are indexed k*nwg + i, packed columns k*pcb + i.
-template <int NTH, int CH, int SLOTS>
-__device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const PackedGeom &pg, int tid, int q,
-                                               int k1, int k2, int c0, int T2, int M, int m_lo, int p0,
-                                               unsigned (&off)[SLOTS]) {
+template <int NTH, int CH, int SLOTS, class GEO>
+__device__ __forceinline__ void packed_offsets(const UpdateArgs &a, const GEO &geo, int tid, int q, int k1,
+                                               int k2, int c0, int m_lo, int p0, unsigned (&off)[SLOTS]) {
     using CI = ChanInfo<CH>;
-    const int nw = a.d.nw, nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
-    const int zc = nw + M - 1;
+    const auto &pg = geo.g;
+    const int nw = geo.nw, T2 = geo.T2, M = geo.M, zc = geo.zc;
+    const int nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
     const int ldp = a.ldp, pcb = a.pcb;
     const int rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
     const int colY = CI::ph ? a.t.kadd[k2 * nc + q] * pcb + c0 + m_lo : 0;
@@ -231,18 +232,20 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         const int rowX = k2 * nwg + c0, colX = k1 * a.pcb;
         constexpr int SLOTS = AR ? kPackedSlotsAReg : kPackedSlots;
         unsigned off[SLOTS];
-        packed_offsets<NTH, CH, SLOTS>(a, pg, tid, q, k1, k2, c0, T2, M, m_lo, p0, off);
+        bool ct = false;
+        if constexpr (NWC > 0) {
+            if (T2 == tile && M == MG) {
+                packed_offsets<NTH, CH, SLOTS>(a, GeoCt<NWC, EPT * (NTH / NWC), MG, CH, XL, AR>{}, tid, q, k1, k2,
+                                               c0, m_lo, p0, off);
+                ct = true;
+            }
+        }
+        if (!ct) packed_offsets<NTH, CH, SLOTS>(a, GeoRt{nw, T2, M, nw + M - 1, pg}, tid, q, k1, k2, c0, m_lo, p0, off);
         const int bufb = S * NTH * 16;   // bytes per buffer
         const unsigned lds_base = (unsigned)(uintptr_t)(lds_t *)smem_raw;
         const unsigned lds0 = lds_base + wave * 64 * 16;
-        // measurement phase: step j of the loop takes measurement mb(j)
-        const int b0 = measurement_phase(a, item);
-        auto mb = [&](int j) __attribute__((always_inline)) {
-            const int b = j + b0;
-            return b >= a.batch ? b - a.batch : b;
-        };
         auto issue = [&](int j) __attribute__((always_inline)) {
-            const char *base = static_cast<const char *>(a.pack) + (int64_t)mb(j) * a.pack_stride;
+            const char *base = static_cast<const char *>(a.pack) + (int64_t)j * a.pack_stride;
             const unsigned buf = lds0 + (j % NB) * bufb;
             static_for<0, SLOTS>([&](auto k) {
                 if (k < S) dma16(base, off[k], buf + k * NTH * 16);
@@ -265,13 +268,15 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         // block into registers, one measurement ahead (the loop waits for every
         // outstanding load before its barrier, so these add no wait)
         float4 xr[EPT], xn[EPT];
+        // a block base common to the wave plus this lane's fixed byte offsets
+        unsigned xoff[EPT];
+        static_for<0, EPT>([&](auto j) {
+            const int r = min(r0 + j * RP, T2 - 1);
+            xoff[j] = (unsigned)(((rowX + r) * ldp + colX + i1) * 16);
+        });
         auto load_x = [&](int jb, float4 *dst) __attribute__((always_inline)) {
-            const float4 *blk = reinterpret_cast<const float4 *>(static_cast<const char *>(a.pack) +
-                                                                 (int64_t)mb(jb) * a.pack_stride);
-            static_for<0, EPT>([&](auto j) {
-                const int r = min(r0 + j * RP, T2 - 1);
-                dst[j] = blk[(int64_t)(rowX + r) * ldp + colX + i1];
-            });
+            const char *blk = static_cast<const char *>(a.pack) + (int64_t)jb * a.pack_stride;
+            static_for<0, EPT>([&](auto j) { dst[j] = *reinterpret_cast<const float4 *>(blk + xoff[j]); });
         };
         static_for<0, EPT>([&](auto j) { xr[j] = xn[j] = float4{0.f, 0.f, 0.f, 0.f}; });
         // AR: this thread's a(Q, K1) for the group's planes (clamped to the
@@ -279,7 +284,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         V ar[AR ? MG : 1], an[AR ? MG : 1];
         auto load_a = [&](int jb, V *dst) __attribute__((always_inline)) {
             const V *pa = reinterpret_cast<const V *>(static_cast<const char *>(a.dir_a) +
-                                                      (int64_t)mb(jb) * a.pack_stride) + k1 * nw + i1;
+                                                      (int64_t)jb * a.pack_stride) + k1 * nw + i1;
             static_for<0, MG>([&](auto m) { dst[m] = pa[(int64_t)(p0 + min((int)m, M - 1)) * n]; });
         };
         for (int b = 0; b < NB - 1 && b < a.batch; ++b) issue(b);
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
                 if (act && b + 1 < a.batch) load_a(b + 1, an);
             }
             if (!act) continue;
-            const float s = sg[mb(b)];
+            const float s = sg[b];
             const float4 *L = reinterpret_cast<const float4 *>(smem_raw + (b % NB) * bufb);
             const float4 *Lx = L + pg.nY + pg.nZ;
             // G(K2,K1) times -s_b for the PH exchange (its minus folded in), +s_b for PP
@@ -450,13 +455,8 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
         packed_offsets_full<NTH, CH, S>(a, pgf, tid, q, k1, k2, c0, TR, M, MG, m_lo, p0, off);
         const int bufb = S * NTH * 16;
         const unsigned lds0 = (unsigned)(uintptr_t)(lds_t *)smem_raw + wave * 64 * 16;
-        const int b0 = measurement_phase(a, item);
-        auto mb = [&](int j) __attribute__((always_inline)) {
-            const int b = j + b0;
-            return b >= a.batch ? b - a.batch : b;
-        };
         auto issue = [&](int j) __attribute__((always_inline)) {
-            const char *base = static_cast<const char *>(a.pack) + (int64_t)mb(j) * a.pack_stride;
+            const char *base = static_cast<const char *>(a.pack) + (int64_t)j * a.pack_stride;
             const unsigned buf = lds0 + (j % NB) * bufb;
             static_for<0, S>([&](auto k) { dma16(base, off[k], buf + k * NTH * 16); });
         };
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
         unsigned xoff[4];
         static_for<0, 4>([&](auto t) { xoff[t] = (unsigned)(((rowX + rb + t) * ldp + colX + i1) * 16); });
         auto load_x = [&](int jb, float4 *dst) __attribute__((always_inline)) {
-            const char *blk = static_cast<const char *>(a.pack) + (int64_t)mb(jb) * a.pack_stride;
+            const char *blk = static_cast<const char *>(a.pack) + (int64_t)jb * a.pack_stride;
             static_for<0, 4>([&](auto t) { dst[t] = *reinterpret_cast<const float4 *>(blk + xoff[t]); });
         };
         if (a.batch > 0) {
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
                 issue(j + 1);
                 load_x(j + 1, nxt);
             }
-            const float s = sg[mb(j)];
+            const float s = sg[j];
             const unsigned char *L = smem_raw + (j % NB) * bufb;
             // G(K2,K1) times -s_b in place (the PH exchange's minus folded in)
             static_for<0, 4>([&](auto t) {
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
                     o.bi[c] = pav[1 - k_c];
                 });
             };
-            auto compute = [&](auto p, const Ops &o) __attribute__((always_inline)) {
+            auto exchange = [&](auto p, const Ops &o) __attribute__((always_inline)) {
                 // exchange: sum over spins of G(K2,K1) G(K1+Q,K2+Q), on the VALU;
                 // straight into the accumulator of one channel, or once for both
                 static_for<0, 4>([&](auto t) {
@@ -536,6 +536,8 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
                         });
                     }
                 });
+            };
+            auto direct = [&](auto p, const Ops &o) __attribute__((always_inline)) {
                 // direct: b(Q,K2) a(Q,K1) of both planes of the pair on the matrix cores
                 static_for<0, CI::nph>([&](auto c) {
                     re[c][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.av[c], bsign * o.br[c], re[c][p], 0, 0, 0);
@@ -548,7 +550,8 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
             static_for<0, NP>([&](auto p) {
                 if constexpr (p + 1 < NP) load(p + 1, o[(p + 1) & 1]);
                 __builtin_amdgcn_sched_barrier(0);
-                compute(p, o[p & 1]);
+                exchange(p, o[p & 1]);
+                direct(p, o[p & 1]);
                 __builtin_amdgcn_sched_barrier(0);
             });
         };
@@ -586,7 +589,7 @@ hipError_t launch_packed_mfma_ch(int channels, int nitems, size_t lds, const Upd
         case 3: fn = reinterpret_cast<const void *>(&update_packed_mfma_kernel<MG, 3>); break;
         default: return hipErrorInvalidValue;
     }
-    return launch_phased(fn, nitems, 256, lds, a, s);
+    return launch_block_per_tile(fn, nitems, 256, lds, a, s);
 }
 #endif
 
@@ -629,7 +632,7 @@ hipError_t launch_packed_ch(int channels, int nitems, size_t lds, const UpdateAr
         default:
             return hipErrorInvalidValue;
     }
-    return launch_phased(fn, nitems, NTH, lds, a, s);
+    return launch_block_per_tile(fn, nitems, NTH, lds, a, s);
 }
 
 template <int NTH, int NB>

@@ -119,3 +119,51 @@ def test_streamed_ring_fp32_packed_matches_oracle(acc):
     want = oracle_ring(rank, S, per)
     for ch in (1, 2, 4):
         check_entries(got[ch], want[ch], 1e-6, what="channel %d" % ch)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_multi_threaded_ring_matches_oracle(k):
+    """k walker threads per rank, k independent rings (each thread index with
+    its own delivery stream and buffer pair): every buffer of every thread of
+    every rank is applied once, in ring order per step and thread order within
+    a step; the result matches the FP64 oracle applied in that order (FP32
+    products, packed operands, compensated accumulator)."""
+    import torch
+    from paper_2105_00027_amd import ring
+    g4 = g4mod()
+    S, per, rank = 3, 2, 2
+    main = torch.cuda.Stream()
+    copies = [torch.cuda.Stream() for _ in range(k)]
+
+    def b0(src, t):                      # first measurement of thread t of rank src
+        return (src * k + t) * per
+
+    sg = {(r, t): signs(W, b0(r, t), per) for r in range(S) for t in range(k)}
+
+    def deliver(src, t, bu, bd, stream):
+        for spin, buf in ((0, bu), (1, bd)):
+            g4.g4_synth_fill(buf, 1, W.lx, W.ly, W.nw, W.nwex, W.beta, W.t, W.mu, W.h, W.noise,
+                             W.seed, W.wid, b0(src, t), per, spin, stream.cuda_stream)
+
+    cfg = config_for(W, mode=1, prod=1, g_in=1, acc=1, batch=per, flags=g4.G4_F_PACKED,
+                     stream=main.cuda_stream)
+    h = g4.g4_init_slice(cfg)
+    bufs = [[tuple(torch.empty((per, W.ng, W.ng), dtype=torch.complex64, device="cuda")
+                   for _ in range(2)) for _ in range(2)] for _ in range(k)]
+    try:
+        ring.stream_ring_threads(h, deliver, sg, rank, S, bufs, main, copies)
+        g4.g4_sync(h)
+        got = {ch: g4.g4_readback(h, ch) for ch in (1, 2, 4)}
+        st = g4.g4_stats(h)
+    finally:
+        torch.cuda.synchronize()
+        g4.g4_destroy(h)
+    assert st["measurements"] == S * k * per
+    seq = [(src, t) for src in ring_order(rank, S) for t in range(k)]
+    gu = np.concatenate([g_matrices(W, b0(*x), per, 0) for x in seq])
+    gd = np.concatenate([g_matrices(W, b0(*x), per, 1) for x in seq])
+    s = np.concatenate([sg[x] for x in seq])
+    for ch in (1, 2, 4):
+        want = ref.accumulate(W, ch, gu, gd, s).reshape(-1)
+        check_entries(got[ch], want, 1e-6, what="channel %d" % ch)
