@@ -64,7 +64,7 @@ def _sanitized_oracle(tmp, source_text, name):
 
 def _run_pins(lib, asan):
     env = dict(os.environ, G4_ORACLE_LIB=lib, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0",
-               OMP_NUM_THREADS="2")
+               OMP_NUM_THREADS="2", PYTHONDONTWRITEBYTECODE="1")
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "--capture=sys",
                            "-k", "not sampled", *PINS], cwd=ROOT, env=env, capture_output=True, text=True,
                           timeout=900)

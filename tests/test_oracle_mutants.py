@@ -75,7 +75,8 @@ def _build_mutant(tmp, name, old, new):
 
 
 def _run_pins(lib):
-    env = dict(os.environ, G4_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    # no bytecode writes: four child test runs share the tests' __pycache__
+    env = dict(os.environ, G4_ORACLE_LIB=lib, OMP_NUM_THREADS="2", PYTHONDONTWRITEBYTECODE="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "--capture=sys",
                         "-k", "not sampled", *PINS], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
