@@ -311,6 +311,33 @@ typedef struct g4_tune_result {
 int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *sign, int32_t batch,
                 double tol, g4_tune_result *out);
 
+/* Allocation-free accumulation, for callers that cannot allocate: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The work of g4_accumulate on a slice described by cfg, into accumulators
+ * the caller owns, with no slice handle, no hipMalloc, no
+ * hipFree and no allocating library call.  The library's workspace (index
+ * tables, work tiles, direct-term vectors, weights) is a static device array
+ * of 64 MiB per GPU (the GPU keeps it until the process ends); a
+ * configuration whose workspace does not fit is rejected with
+ * G4_E_UNSUPPORTED (the message gives the bytes needed: fewer planes or a
+ * smaller max_batch fit).
+ *   cfg: as for g4_init_slice; cfg->stream is the stream used (NULL: the null
+ *     stream), cfg->device the GPU.  Runs the VALU kernels: plain mode, or
+ *     batched with G4_PROD_F64 or G4_PROD_F32 (complex64 G for FP32); no
+ *     G4_F_* flags (G4_E_UNSUPPORTED otherwise).
+ *   acc_mag, acc_chg, acc_pp: DEVICE accumulators, one per channel in
+ *     cfg->channels (NULL for the others), each entries x 16 bytes (G4_ACC_C128,
+ *     G4_ACC_C64_KAHAN) or x 8 bytes (G4_ACC_C64), in the library's device
+ *     layout [plane][k2][k1][i2][i1] (K = k*nw + i), which g4_readback
+ *     translates for a slice; the caller zeroes them before the first call.
+ *   G_up, G_dn, sign, batch: as for g4_accumulate.
+ * Synchronous: returns when the work on the stream is done.  Every call on a
+ * GPU shares its static workspace, which keeps the last call's contents: calls
+ * that overlap on one GPU (from two host threads) race; do not make them.
+ * Errors as for g4_accumulate; validation happens before any HIP call. */
+int g4_accumulate_into(const g4_config *cfg, void *acc_mag, void *acc_chg, void *acc_pp, const void *G_up,
+                       const void *G_dn, const double *sign, int32_t batch);
+
 /* Release everything owned by h (waits for its stream).  NULL is a no-op.
  * Paper: Background section, the solver workflow (G_t is freed at the end of
  * the run). */

@@ -779,6 +779,151 @@ int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, in
 
 }  // namespace
 
+namespace {
+
+// ---- the allocation-free accumulation (g4_accumulate_into) ----------------
+// Everything g4_accumulate keeps in a slice's own allocations (index tables,
+// work tiles, direct vectors, weights) is laid out in a caller-provided
+// device workspace instead; the accumulators are the caller's.  Runs the
+// VALU kernels (plain FP64, or batched with FP64 or FP32 products) with the
+// pass schedule of g4_accumulate.  Synchronous: host tables stay alive until
+// their copies are done.
+int noalloc_accumulate(const g4_config *cfg, void *const acc[3], const void *G_up, const void *G_dn,
+                       const double *sign, int32_t batch, void *ws, uint64_t ws_bytes) {
+    Plan P;
+    int rc = validate(cfg, &P);
+    if (rc) return rc;
+    if (P.variant != G4_VARIANT_VALU || P.split)
+        return fail(G4_E_UNSUPPORTED, "g4_accumulate_into runs the VALU kernels only (no G4_F_MFMA, "
+                                      "G4_F_PACKED, G4_F_PACKED_DEEP or split products)");
+    if (cfg->flags & (G4_F_GRAPH | G4_F_KERNEL_TIMING | G4_F_CHECK_FINITE))
+        return fail(G4_E_UNSUPPORTED, "g4_accumulate_into takes no G4_F_GRAPH, G4_F_KERNEL_TIMING or "
+                                      "G4_F_CHECK_FINITE");
+    if (P.prec == 1 && cfg->g_in == G4_IN_C128)
+        return fail(G4_E_UNSUPPORTED, "g4_accumulate_into: FP32 products need complex64 G");
+    if (batch < 0) return fail(G4_E_ARG, "batch=%d", batch);
+    for (int c = 0; c < 3; ++c) {
+        const bool want = (cfg->channels >> c) & 1u;
+        if (want != (acc[c] != nullptr))
+            return fail(G4_E_ARG, "accumulator %d must be %s", c, want ? "given" : "NULL for an absent channel");
+    }
+    if (batch == 0) return G4_OK;
+    if (!G_up || !G_dn || !sign) return fail(G4_E_ARG, "NULL G or sign pointer");
+    // host tables
+    std::vector<int32_t> kadd, ksub;
+    build_momentum_maps(P.d, kadd, ksub);
+    std::vector<int2> pq;
+    build_planes(P, cfg->nwex, pq);
+    std::vector<int32_t> qpos(P.d.nc, -1);
+    for (size_t i = 0; i < P.qlist.size(); ++i) qpos[(size_t)P.qlist[i]] = (int32_t)i;
+    std::vector<int4> groups, items;
+    build_work(P, cfg->nwex, 2, groups, items);
+    if (items.size() > (size_t)INT32_MAX) return fail(G4_E_UNSUPPORTED, "more than 2^31 work tiles");
+    // workspace layout, 256-byte aligned parts
+    auto up = [](uint64_t b) { return (b + 255) / 256 * 256; };
+    const uint64_t el = P.prec == 0 ? 16 : 8;
+    const int64_t pn = (int64_t)P.d.planes * P.d.n;
+    const uint64_t dir_half = (uint64_t)P.nslots * P.batch * pn * el;
+    uint64_t o = 0;
+    const uint64_t o_kadd = o; o += up(kadd.size() * 4);
+    const uint64_t o_ksub = o; o += up(ksub.size() * 4);
+    const uint64_t o_pq = o; o += up(pq.size() * sizeof(int2));
+    const uint64_t o_qpos = o; o += up(qpos.size() * 4);
+    const uint64_t o_groups = o; o += up(groups.size() * sizeof(int4));
+    const uint64_t o_items = o; o += up(items.size() * sizeof(int4));
+    const uint64_t o_dir = o; o += 2 * up(dir_half);
+    const uint64_t o_sign = o; o += up((uint64_t)P.batch * sizeof(double));
+    if (o > ws_bytes)
+        return fail(G4_E_UNSUPPORTED, "g4_accumulate_into needs %llu bytes of workspace, the static one holds %llu "
+                                      "(fewer planes or a smaller max_batch)",
+                    (unsigned long long)o, (unsigned long long)ws_bytes);
+    char *w = static_cast<char *>(ws);
+    hipStream_t st = static_cast<hipStream_t>(cfg->stream);
+    hipError_t e = hipSetDevice(cfg->device);
+#define G4_NA(call)                                                           \
+    do {                                                                      \
+        e = (call);                                                           \
+        if (e != hipSuccess) return fail(G4_E_HIP, "%s: %s", #call, hipGetErrorString(e)); \
+    } while (0)
+    G4_NA(e);
+    G4_NA(hipMemcpyAsync(w + o_kadd, kadd.data(), kadd.size() * 4, hipMemcpyHostToDevice, st));
+    G4_NA(hipMemcpyAsync(w + o_ksub, ksub.data(), ksub.size() * 4, hipMemcpyHostToDevice, st));
+    G4_NA(hipMemcpyAsync(w + o_pq, pq.data(), pq.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    G4_NA(hipMemcpyAsync(w + o_qpos, qpos.data(), qpos.size() * 4, hipMemcpyHostToDevice, st));
+    G4_NA(hipMemcpyAsync(w + o_groups, groups.data(), groups.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    G4_NA(hipMemcpyAsync(w + o_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    Tables t;
+    t.kadd = reinterpret_cast<const int32_t *>(w + o_kadd);
+    t.ksub = reinterpret_cast<const int32_t *>(w + o_ksub);
+    t.plane_qm = reinterpret_cast<const int2 *>(w + o_pq);
+    t.qpos = reinterpret_cast<const int32_t *>(w + o_qpos);
+    t.groups = reinterpret_cast<const int4 *>(w + o_groups);
+    t.items = reinterpret_cast<const int4 *>(w + o_items);
+    double *ds = reinterpret_cast<double *>(w + o_sign);
+    void *dir_a = w + o_dir, *dir_b = w + o_dir + up(dir_half);
+    const size_t in_el = cfg->g_in == G4_IN_C128 ? 16 : 8;
+    const int64_t per = (int64_t)P.d.ng * P.d.ng;
+    for (int b0 = 0; b0 < batch; b0 += P.batch) {
+        const int nb = std::min(P.batch, batch - b0);
+        const void *pu = static_cast<const char *>(G_up) + (size_t)b0 * per * in_el;
+        const void *pd = static_cast<const char *>(G_dn) + (size_t)b0 * per * in_el;
+        // the previous pass has read the weights (stream order) before they are replaced
+        G4_NA(hipMemcpyAsync(ds, sign + b0, (size_t)nb * sizeof(double), hipMemcpyHostToDevice, st));
+        GatherArgs ga;
+        ga.gu = pu;
+        ga.gd = pd;
+        ga.g_stride = per;
+        ga.dir_a = dir_a;
+        ga.dir_b = dir_b;
+        ga.dir_slot_stride = (int64_t)P.batch * pn;
+        ga.dir_b_stride = pn;
+        ga.sign = ds;
+        ga.batch = nb;
+        ga.slots = P.slots;
+        ga.d = P.d;
+        ga.t = t;
+        if (P.slots) G4_NA(launch_gather(P.prec, ga, st));
+        UpdateArgs ua;
+        ua.gu = pu;
+        ua.gd = pd;
+        ua.g_stride = per;
+        ua.dir_a = dir_a;
+        ua.dir_b = dir_b;
+        ua.dir_slot_stride = ga.dir_slot_stride;
+        ua.dir_b_stride = pn;
+        ua.pack = nullptr;
+        ua.pack_stride = 0;
+        ua.ldp = 0;
+        ua.pcb = 0;
+        ua.nitems = (int)items.size();
+        ua.skip_direct = 0;
+        ua.sign = ds;
+        ua.batch = nb;
+        ua.acc[0] = acc[0];
+        ua.acc[1] = acc[1];
+        ua.acc[2] = acc[2];
+        ua.acc_kind = cfg->acc;
+        ua.tile = P.tile;
+        ua.d = P.d;
+        ua.t = t;
+        G4_NA(launch_update(P.kind, (int)cfg->channels, P.ept, P.mgroup, (int)items.size(), P.variant, ua, st));
+    }
+    G4_NA(hipStreamSynchronize(st));
+#undef G4_NA
+    g_err[0] = 0;
+    return G4_OK;
+}
+
+}  // namespace
+
+namespace g4 {
+int noalloc_accumulate_entry(const g4_config *cfg, void *const acc[3], const void *G_up, const void *G_dn,
+                             const double *sign, int32_t batch, void *ws, uint64_t ws_bytes) {
+    return noalloc_accumulate(cfg, acc, G_up, G_dn, sign, batch, ws, ws_bytes);
+}
+int noalloc_fail(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace g4
+
 extern "C" {
 
 int g4_config_init(g4_config *cfg) {

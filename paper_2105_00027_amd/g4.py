@@ -99,6 +99,7 @@ _sig = {
     "g4_set_plan": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "g4_autotune": ([_vp, _vp, _vp, _dp, ctypes.c_int32, ctypes.c_double,
                      ctypes.POINTER(g4_tune_result)], ctypes.c_int),
+    "g4_accumulate_into": ([_cfgp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.c_int32], ctypes.c_int),
     "g4_destroy": ([_vp], None),
     "g4_last_error": ([], ctypes.c_char_p),
     "g4_synth_fill": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -222,6 +223,40 @@ def g4_accumulate(h: Slice, G_up, G_dn, sign, batch: Optional[int] = None) -> No
     pu = _device_ptr(G_up, need, el)
     pd = _device_ptr(G_dn, need, el)
     _check(_L.g4_accumulate(h.ptr, _vp(pu), _vp(pd), s.ctypes.data_as(_dp), int(batch)))
+
+
+def _acc_ptr(x, nbytes_expected: int) -> int:
+    """Pointer of a caller-owned device accumulator (None for an absent channel)."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous():
+        raise G4Error(G4_E_ARG, "accumulators must be contiguous device tensors")
+    if x.numel() * x.element_size() < nbytes_expected:
+        raise G4Error(G4_E_ARG, "accumulator holds %d bytes, %d needed"
+                      % (x.numel() * x.element_size(), nbytes_expected))
+    return x.data_ptr()
+
+
+def g4_accumulate_into(cfg: Config, acc_mag, acc_chg, acc_pp, G_up, G_dn, sign,
+                       batch: Optional[int] = None) -> None:
+    """Allocation-free accumulation into caller-owned accumulators (device
+    layout [plane][k2][k1][i2][i1]); see include/g4.h."""
+    s = np.ascontiguousarray(np.asarray(sign, dtype=np.float64).reshape(-1))
+    if batch is None:
+        batch = s.shape[0]
+    if batch > s.shape[0]:
+        raise G4Error(G4_E_ARG, "sign has %d entries, batch=%d" % (s.shape[0], batch))
+    el = 16 if cfg.c.g_in == G4_IN_C128 else 8
+    need = batch * cfg.ng * cfg.ng * el
+    pu = _device_ptr(G_up, need, el)
+    pd = _device_ptr(G_dn, need, el)
+    ab = cfg.planes * cfg.n * cfg.n * (8 if cfg.c.acc == G4_ACC_C64 else 16)
+    accs = [_acc_ptr(a, ab) for a in (acc_mag, acc_chg, acc_pp)]
+    _check(_L.g4_accumulate_into(ctypes.byref(cfg.c), *[_vp(a) if a else None for a in accs],
+                                 _vp(pu), _vp(pd), s.ctypes.data_as(_dp), int(batch)))
 
 
 def g4_sync(h: Slice) -> None:
