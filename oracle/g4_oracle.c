@@ -234,6 +234,79 @@ int oracle_entries(const oracle_shape *s, int channel, const double *g_up, const
     return 0;
 }
 
+/*
+ * The step before the accumulation: a walker's single-particle Green's
+ * function G_sigma from its expansion configuration, by the nonuniform
+ * Fourier transform that the paper's walker computes with matrix products
+ * (Background section, the solver workflow).  For n vertices with imaginary
+ * times tau_i and cluster sites r_i = rx + Lx*ry, and the walker's n x n
+ * matrix M (row-major complex), for entries (K1, K2) of the G window:
+ *
+ *   G(K1, K2) = g0(K1) delta_{K1,K2}
+ *               - g0(K1) [ sum_{i,j} e^{+i th_i(K1)} M_ij e^{-i th_j(K2)} ] g0(K2) / (beta Nc)
+ *   th_i(K) = w_n tau_i + k . r_i,   k . r = 2 pi (kx rx / Lx + ky ry / Ly),
+ *   g0(k, n) = 1 / (i w_n + mu + s h - eps_k),  eps_k = -2 t (cos kx + cos ky),
+ *
+ * s = +1 for spin 0 (up), -1 for spin 1 (down); K = k*Nwg + (n + Nw/2) over
+ * the G window n in [-Nw/2, Nw/2+Nwex-2].  Each entry is the double sum
+ * written out (O(n^2) per entry), every exponential evaluated by itself.
+ * idx: count flattened entries K1*Ng + K2; out: count complex values.
+ * Returns 0, or -1 on bad arguments.
+ */
+int oracle_gsigma(int lx, int ly, int nw, int nwex, double beta, double mu, double h, double t, int spin,
+                  int n, const double *tau, const int *site, const double *M, const int64_t *idx, long count,
+                  double *out) {
+    if (lx < 1 || ly < 1 || nw < 2 || (nw & 1) || nwex < 1 || !(beta > 0) || (spin != 0 && spin != 1) ||
+        n < 0 || (n && (!tau || !site || !M)) || (count && (!idx || !out)))
+        return -1;
+    const long nc = (long)lx * ly, nwg = nw + nwex - 1, ng = nc * nwg;
+    for (int i = 0; i < n; ++i)
+        if (site[i] < 0 || site[i] >= nc) return -1;
+    for (long j = 0; j < count; ++j)
+        if (idx[j] < 0 || idx[j] >= ng * ng) return -1;
+    const double pi = 3.14159265358979323846;
+    const double sg = spin == 0 ? 1.0 : -1.0;
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < count; ++j) {
+        const long K1 = idx[j] / ng, K2 = idx[j] % ng;
+        const long k1 = K1 / nwg, k2 = K2 / nwg;
+        const long n1 = K1 % nwg - nw / 2, n2 = K2 % nwg - nw / 2;
+        const double w1 = (2.0 * n1 + 1.0) * pi / beta, w2 = (2.0 * n2 + 1.0) * pi / beta;
+        const long k1x = k1 % lx, k1y = k1 / lx, k2x = k2 % lx, k2y = k2 / lx;
+        /* g0 at both ends */
+        cplx g0a, g0b;
+        {
+            const double ea = -2.0 * t * (cos(2.0 * pi * k1x / lx) + cos(2.0 * pi * k1y / ly));
+            const double eb = -2.0 * t * (cos(2.0 * pi * k2x / lx) + cos(2.0 * pi * k2y / ly));
+            const double ra = mu + sg * h - ea, rb = mu + sg * h - eb;   /* 1/(i w + r) = (r - i w)/(r^2 + w^2) */
+            g0a.re = ra / (ra * ra + w1 * w1);
+            g0a.im = -w1 / (ra * ra + w1 * w1);
+            g0b.re = rb / (rb * rb + w2 * w2);
+            g0b.im = -w2 / (rb * rb + w2 * w2);
+        }
+        cplx sum = {0.0, 0.0};
+        for (int a = 0; a < n; ++a) {
+            const long rax = site[a] % lx, ray = site[a] / lx;
+            const double tha = w1 * tau[a] + 2.0 * pi * ((double)(k1x * rax) / lx + (double)(k1y * ray) / ly);
+            const cplx ea = {cos(tha), sin(tha)};
+            for (int b = 0; b < n; ++b) {
+                const long rbx = site[b] % lx, rby = site[b] / lx;
+                const double thb = w2 * tau[b] + 2.0 * pi * ((double)(k2x * rbx) / lx + (double)(k2y * rby) / ly);
+                const cplx eb = {cos(thb), -sin(thb)};
+                const cplx m = {M[2 * ((long)a * n + b)], M[2 * ((long)a * n + b) + 1]};
+                sum = c_add(sum, c_mul(c_mul(ea, m), eb));
+            }
+        }
+        const double norm = 1.0 / (beta * (double)nc);
+        const cplx corr = c_mul(c_mul(g0a, sum), g0b);
+        cplx g = {-corr.re * norm, -corr.im * norm};
+        if (K1 == K2) g = c_add(g, g0a);
+        out[2 * j] = g.re;
+        out[2 * j + 1] = g.im;
+    }
+    return 0;
+}
+
 /* Threads OpenMP would use (for reporting the CPU-baseline core count). */
 int oracle_max_threads(void) {
 #ifdef _OPENMP

@@ -42,6 +42,11 @@ def lib():
                                      ctypes.c_long, dp]
         L.oracle_entries.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_gsigma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int), dp,
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_long, dp]
+        L.oracle_gsigma.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -104,3 +109,24 @@ def entries(w, channel: int, g_up: np.ndarray, g_dn: np.ndarray, sign: np.ndarra
 
 def max_threads() -> int:
     return lib().oracle_max_threads()
+
+
+def gsigma(w, spin: int, tau, site, M, idx=None) -> np.ndarray:
+    """G_sigma of one expansion configuration (n vertices: imaginary times tau,
+    cluster sites site, n x n matrix M): the full Ng x Ng matrix, or the
+    flattened entries idx (K1*Ng + K2)."""
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    site = np.ascontiguousarray(site, dtype=np.int32)
+    n = tau.shape[0]
+    M = np.ascontiguousarray(M, dtype=np.complex128).reshape(n, n)
+    full = idx is None
+    if full:
+        idx = np.arange(w.ng * w.ng, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(idx.shape[0], dtype=np.complex128)
+    rc = lib().oracle_gsigma(w.lx, w.ly, w.nw, w.nwex, w.beta, w.mu, w.h, w.t, spin, n, _dp(tau),
+                             site.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(M),
+                             idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.shape[0], _dp(out))
+    if rc:
+        raise ValueError("oracle_gsigma rejected the arguments")
+    return out.reshape(w.ng, w.ng) if full else out

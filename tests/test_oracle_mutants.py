@@ -6,7 +6,7 @@ copy with the oracle's own compiler flags into a temporary directory, and
 runs the oracle's pin tests against it (G4_ORACLE_LIB points the oracle's
 loader at the copy) in a child process, which must fail.  The pins are the
 closed forms, the brute-force Wick contraction, the array formulation, the
-invariants and the exact compensated sums; the numpy per-entry oracle's
+invariants, the exact compensated sums and the G_sigma pins; the numpy per-entry oracle's
 comparison with the C oracle is left out, so that only the pins count.
 
 Everything runs on the CPU; the HIP library is not involved.
@@ -24,7 +24,7 @@ from oracle import build as oracle_build
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_wick.py",
         "tests/test_oracle_arrays.py", "tests/test_oracle_invariants.py",
-        "tests/test_oracle_compensated.py"]
+        "tests/test_oracle_compensated.py", "tests/test_oracle_gsigma.py"]
 
 # name -> (text in the oracle source, replacement)
 MUTANTS = {
@@ -59,6 +59,15 @@ MUTANTS = {
         "mom_sub(s, q, k1), m - n1 - 1)", "mom_sub(s, q, k1), m - n2 - 1)"),
     "PP frequency off by one": (
         "mom_sub(s, q, k2), m - n2 - 1)", "mom_sub(s, q, k2), m - n2)"),
+    # G_sigma from an expansion configuration
+    "G_sigma: conjugate phase on the left factor": (
+        "const cplx ea = {cos(tha), sin(tha)};", "const cplx ea = {cos(tha), -sin(tha)};"),
+    "G_sigma: normalisation dropped": (
+        "const double norm = 1.0 / (beta * (double)nc);", "const double norm = 1.0;"),
+    "G_sigma: k.r with the wrong sign": (
+        "const double tha = w1 * tau[a] + 2.0 * pi *", "const double tha = w1 * tau[a] - 2.0 * pi *"),
+    "G_sigma: spin ignored in g0": (
+        "const double sg = spin == 0 ? 1.0 : -1.0;", "const double sg = 1.0;"),
 }
 
 
