@@ -338,6 +338,50 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
 int g4_accumulate_into(const g4_config *cfg, void *acc_mag, void *acc_chg, void *acc_pp, const void *G_up,
                        const void *G_dn, const double *sign, int32_t batch);
 
+/* ---- G_sigma from expansion configurations -----------------------------
+ * For each of `count` measurements b, the walker's single-particle Green's
+ * function of one spin on the G window from its expansion configuration:
+ *   G_b(K1,K2) = g0(K1) d(K1,K2)
+ *              - g0(K1) [sum_ij e^{i th_i(K1)} M_b(i,j) e^{-i th_j(K2)}] g0(K2) / (beta Nc),
+ *   th_i(K) = w_n tau_i + k . r_i,  w_n = (2n+1) pi / beta,
+ *   g0(K) = 1 / (i w_n + mu + s h - eps_k),  eps_k = -2t(cos kx + cos ky),
+ *   s = +1 for spin 0, -1 for spin 1;
+ * K = k*(Nw+Nwex-1) + (n + Nw/2) with k = kx_index + lx*ky_index, as for the
+ * slice's G input, and the time-ordering conventions folded into M.
+ * Computed as E_b M_b E_b^H with E_b(K,i) = e^{i th_i(K)}: phases and g0 in
+ * FP64, the two complex products on MFMA in the precision of dtype.
+ * Paper: Background section, the solver workflow (the walker's nonuniform
+ * Fourier transform of G_sigma, implemented as matrix-matrix products).
+ * Arguments (DEVICE pointers unless noted; all arrays row-major, packed):
+ *   lx, ly        cluster (Nc = lx*ly <= 4096); nw even in [2, 4096]; nwex in
+ *                 [1, 4096]; Ng = Nc*(Nw+Nwex-1) at most 46340;
+ *   beta > 0, mu, h, t   model parameters; spin 0 or 1;
+ *   n >= 0        vertices per configuration (the same for every b);
+ *   count         measurements, 0..65535 (0: nothing is launched);
+ *   tau           count x n doubles in [0, beta);
+ *   site          count x n int32 cluster sites in [0, Nc), x + lx*y (not
+ *                 checked: no memory is indexed by them);
+ *   M             count x n x n complex of dtype (G4_IN_C128 or G4_IN_C64);
+ *   G             count x Ng x Ng complex of dtype, written whole;
+ *   workspace, workspace_bytes   device scratch of at least
+ *                 g4_gsigma_workspace() bytes, owned by the caller, not to be
+ *                 used by anything else until the stream reaches the end of
+ *                 this call; its contents on entry do not matter;
+ *   stream        hipStream_t or NULL (the null stream).
+ * Asynchronous on stream.  G4_E_ARG for a bad shape, NULL pointers (except
+ * tau/site/M when n = 0) or a short workspace; G4_E_UNSUPPORTED beyond the
+ * limits above; G4_E_HIP if a launch fails.  No slice handle is involved. */
+int g4_gsigma(int32_t lx, int32_t ly, int32_t nw, int32_t nwex, double beta, double mu, double h, double t,
+              int32_t spin, int32_t n, int32_t count, const double *tau, const int32_t *site, const void *M,
+              int32_t dtype, void *G, void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Device workspace bytes g4_gsigma needs for these sizes, into *bytes (HOST):
+ * Ng complex128 values of g0, then E and E M (count x Ng x n each, dtype);
+ * 0 for count = 0.  No HIP call.  G4_E_ARG for a bad shape or dtype, or NULL bytes.
+ * Paper: Background section, the solver workflow (the same transform). */
+int g4_gsigma_workspace(int32_t lx, int32_t ly, int32_t nw, int32_t nwex, int32_t n, int32_t count,
+                        int32_t dtype, uint64_t *bytes);
+
 /* Release everything owned by h (waits for its stream).  NULL is a no-op.
  * Paper: Background section, the solver workflow (G_t is freed at the end of
  * the run). */

@@ -921,7 +921,7 @@ int noalloc_accumulate_entry(const g4_config *cfg, void *const acc[3], const voi
                              const double *sign, int32_t batch, void *ws, uint64_t ws_bytes) {
     return noalloc_accumulate(cfg, acc, G_up, G_dn, sign, batch, ws, ws_bytes);
 }
-int noalloc_fail(int code, const char *msg) { return fail(code, "%s", msg); }
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 }  // namespace g4
 
 extern "C" {

@@ -17,7 +17,7 @@
 namespace g4 {
 int noalloc_accumulate_entry(const g4_config *cfg, void *const acc[3], const void *G_up, const void *G_dn,
                              const double *sign, int32_t batch, void *ws, uint64_t ws_bytes);
-int noalloc_fail(int code, const char *msg);
+int set_error(int code, const char *msg);
 }  // namespace g4
 
 namespace {
@@ -35,21 +35,21 @@ extern "C" int g4_accumulate_into(const g4_config *cfg, void *acc_mag, void *acc
                                   const void *G_up, const void *G_dn, const double *sign, int32_t batch) {
     // the configuration is validated before any HIP call
     if (int rc = g4_slice_size(cfg, nullptr, nullptr); rc != G4_OK) return rc;
-    if (cfg->device >= kMaxDevices) return g4::noalloc_fail(G4_E_UNSUPPORTED, "device ordinal above 63");
+    if (cfg->device >= kMaxDevices) return g4::set_error(G4_E_UNSUPPORTED, "device ordinal above 63");
     void *ptr = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_mu);
         ptr = g_ptr[cfg->device];
         if (!ptr) {
             int cur = 0;
-            if (hipGetDevice(&cur) != hipSuccess) return g4::noalloc_fail(G4_E_HIP, "hipGetDevice failed");
+            if (hipGetDevice(&cur) != hipSuccess) return g4::set_error(G4_E_HIP, "hipGetDevice failed");
             if (hipSetDevice(cfg->device) != hipSuccess)
-                return g4::noalloc_fail(G4_E_HIP, "hipSetDevice failed");
+                return g4::set_error(G4_E_HIP, "hipSetDevice failed");
             const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
             (void)hipSetDevice(cur);
             if (e != hipSuccess || !ptr) {
                 (void)hipGetLastError();
-                return g4::noalloc_fail(G4_E_HIP, "hipGetSymbolAddress of the static workspace failed");
+                return g4::set_error(G4_E_HIP, "hipGetSymbolAddress of the static workspace failed");
             }
             g_ptr[cfg->device] = ptr;
         }

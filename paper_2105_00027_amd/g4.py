@@ -100,6 +100,9 @@ _sig = {
     "g4_autotune": ([_vp, _vp, _vp, _dp, ctypes.c_int32, ctypes.c_double,
                      ctypes.POINTER(g4_tune_result)], ctypes.c_int),
     "g4_accumulate_into": ([_cfgp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.c_int32], ctypes.c_int),
+    "g4_gsigma_workspace": ([ctypes.c_int32] * 7 + [ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "g4_gsigma": ([ctypes.c_int32] * 4 + [ctypes.c_double] * 4 + [ctypes.c_int32] * 3
+                  + [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int),
     "g4_destroy": ([_vp], None),
     "g4_last_error": ([], ctypes.c_char_p),
     "g4_synth_fill": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -257,6 +260,52 @@ def g4_accumulate_into(cfg: Config, acc_mag, acc_chg, acc_pp, G_up, G_dn, sign,
     accs = [_acc_ptr(a, ab) for a in (acc_mag, acc_chg, acc_pp)]
     _check(_L.g4_accumulate_into(ctypes.byref(cfg.c), *[_vp(a) if a else None for a in accs],
                                  _vp(pu), _vp(pd), s.ctypes.data_as(_dp), int(batch)))
+
+
+def _dev_buf(x, nbytes: int, what: str, dtype=None) -> int:
+    """Pointer of a contiguous device tensor of at least nbytes bytes (and of
+    the given torch dtype, if one is named), or an integer device pointer."""
+    if isinstance(x, int):
+        return x
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous():
+        raise G4Error(G4_E_ARG, "%s must be a contiguous device tensor" % what)
+    if dtype is not None and x.dtype != dtype:
+        raise G4Error(G4_E_ARG, "%s must be %s, got %s" % (what, dtype, x.dtype))
+    if x.numel() * x.element_size() < nbytes:
+        raise G4Error(G4_E_ARG, "%s holds %d bytes, %d needed" % (what, x.numel() * x.element_size(), nbytes))
+    return x.data_ptr()
+
+
+def g4_gsigma_workspace(lx: int, ly: int, nw: int, nwex: int, n: int, count: int, dtype: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(_L.g4_gsigma_workspace(lx, ly, nw, nwex, n, count, dtype, ctypes.byref(out)))
+    return out.value
+
+
+def g4_gsigma(lx: int, ly: int, nw: int, nwex: int, beta: float, mu: float, h: float, t: float, spin: int,
+              tau, site, M, G, workspace, stream=None) -> None:
+    """G_sigma of count configurations (tau: count x n float64, site: count x n
+    int32, M: count x n x n complex) into G (count x Ng x Ng, M's dtype); see
+    include/g4.h."""
+    import torch
+    if not isinstance(M, torch.Tensor) or M.dim() != 3 or M.shape[1] != M.shape[2]:
+        raise G4Error(G4_E_ARG, "M must be a count x n x n device tensor")
+    count, n = int(M.shape[0]), int(M.shape[1])
+    dtype = {torch.complex128: G4_IN_C128, torch.complex64: G4_IN_C64}.get(M.dtype)
+    if dtype is None:
+        raise G4Error(G4_E_ARG, "M must be complex128 or complex64")
+    el = 16 if dtype == G4_IN_C128 else 8
+    ng = lx * ly * (nw + nwex - 1)
+    pt = _dev_buf(tau, count * n * 8, "tau", torch.float64) if n else 0
+    ps = _dev_buf(site, count * n * 4, "site", torch.int32) if n else 0
+    pm = _dev_buf(M, count * n * n * el, "M")
+    pg = _dev_buf(G, count * ng * ng * el, "G", M.dtype)
+    need = g4_gsigma_workspace(lx, ly, nw, nwex, n, count, dtype)
+    pw = _dev_buf(workspace, need, "workspace")
+    wbytes = workspace.numel() * workspace.element_size() if not isinstance(workspace, int) else need
+    _check(_L.g4_gsigma(lx, ly, nw, nwex, beta, mu, h, t, spin, n, count, _vp(pt), _vp(ps), _vp(pm), dtype,
+                        _vp(pg), _vp(pw), wbytes, _vp(int(stream) if stream else 0)))
 
 
 def g4_sync(h: Slice) -> None:

@@ -190,3 +190,18 @@ def signs(w: Workload, b0: int, count: int) -> np.ndarray:
     x0, x1, _, _ = philox4x32_10(np.uint32(0), b, np.uint32(STREAM_SIGN), np.uint32(0),
                                  np.uint32(w.seed), np.uint32(w.wid))
     return np.where(u53(x0, x1) < w.p_plus, 1.0, -1.0)
+
+
+def expansion_configs(w: Workload, seed: int, count: int, n: int):
+    """Seeded stand-ins for walker expansion configurations: for each of count
+    measurements, n vertex times uniform in [0, beta), n cluster sites uniform
+    over the Nc sites, and an n x n complex matrix with independent normal
+    real and imaginary parts scaled by 1/sqrt(n) (so that M E^H stays O(1)
+    per entry as n grows).  Returns (tau[count, n] float64, site[count, n]
+    int32, M[count, n, n] complex128)."""
+    rng = np.random.default_rng(seed)
+    tau = rng.uniform(0.0, w.beta, size=(count, n))
+    site = rng.integers(0, w.nc, size=(count, n)).astype(np.int32)
+    sc = 1.0 / math.sqrt(max(n, 1))
+    M = (rng.normal(size=(count, n, n)) + 1j * rng.normal(size=(count, n, n))) * sc
+    return tau, site, M
