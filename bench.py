@@ -20,7 +20,10 @@ Further legs in the same JSON line (each with its rate, roofline and error):
   split_precision  a 1/4 slice of the 8x8, Nw=64, Nq=64, Nwex=4 array with PH
                    magnetic, PH charge and PP in one pass, compensated
                    complex64 accumulators, FP32 products and the fp16 / bf16
-                   hi+lo split direct term.
+                   hi+lo split direct term;
+  gsigma           G_sigma of the 4x4 window (Ng = 1136) from seeded expansion
+                   configurations of order n = 512, 64 measurements per call,
+                   complex64 and complex128 (the step before the slice update).
 
 Printed: one JSON line with the entry-update rate (entries x measurements per
 second), the dominant kernel's roofline position (its average launch time from
@@ -49,6 +52,7 @@ HBM_PEAK = 8.0e12                                   # bytes/s, MI355X HBM3E
 ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9                 # FP32 or FP64 FMA, non-packed: 78.6 TFLOP/s
 MFMA_F32_PEAK = 157.3e12                            # dense FP32 MFMA
 MFMA_F16_PEAK = 2.5e15                              # dense fp16 / bf16 MFMA
+MFMA_F64_PEAK = 78.6e12                             # dense FP64 MFMA
 FLOPS_PER_EU = {1: 24, 2: 24, 4: 16}                 # per channel: direct 8 + exchange 16; PP 16
 DIRECT_FLOPS = 8                                     # the PH direct term's share
 VARIANTS = ["valu", "mfma-direct", "packed-lds", "packed-lds-deep", "packed-lds-mfma-direct"]
@@ -342,6 +346,56 @@ class Bench:
             torch.cuda.empty_cache()
         return out
 
+    def gsigma(self, w, n, count, c128, steps=8, warmup=2, nsample=64, check=True):
+        """G_sigma of `count` configurations per call for both spins: time per
+        call (HIP events on the library's stream over `steps` calls after
+        `warmup`), rate, and the sampled error of two measurements against the
+        oracle."""
+        torch, g4 = self.torch, self.g4
+        from synth import expansion_configs
+        dt = torch.complex128 if c128 else torch.complex64
+        tau, site, M = expansion_configs(w, 4242, count, n)
+        tau_d = torch.from_numpy(tau).to(self.dev)
+        site_d = torch.from_numpy(site).to(self.dev)
+        M_d = torch.from_numpy(M).to(device=self.dev, dtype=dt)
+        G = [torch.empty((count, w.ng, w.ng), dtype=dt, device=self.dev) for _ in range(2)]
+        dtype = g4.G4_IN_C128 if c128 else g4.G4_IN_C64
+        ws = torch.empty(g4.g4_gsigma_workspace(w.lx, w.ly, w.nw, w.nwex, n, count, dtype), dtype=torch.uint8,
+                         device=self.dev)
+
+        def call(i):
+            g4.g4_gsigma(w.lx, w.ly, w.nw, w.nwex, w.beta, w.mu, w.h, w.t, i % 2, tau_d, site_d, M_d,
+                         G[i % 2], ws, self.sptr)
+        for i in range(warmup):
+            call(i)
+        torch.cuda.synchronize()
+        ms = [self.timed(call, steps) / steps for _ in range(REPS)]
+        med = statistics.median(ms)
+        flops = 8.0 * count * (w.ng * n * n + w.ng * w.ng * n)
+        peak = MFMA_F64_PEAK if c128 else MFMA_F32_PEAK
+        out = {"dtype": "c128" if c128 else "c64", "ms_per_call": med, "rep_ms": ms,
+               "value": count / (med / 1e3), "unit": "measurements/s",
+               "roofline": {"bound": "mfma", "achieved": flops / (med / 1e3) / 1e12, "peak": peak / 1e12,
+                            "unit": "TFLOP/s", "frac": flops / (med / 1e3) / peak, "traffic": None,
+                            "algorithmic_flops_per_call": flops,
+                            "timed": "whole call (g0, phases and both complex products)"}}
+        if check:
+            from oracle import ref
+            rng = np.random.default_rng(5)
+            errs = []
+            Gh = G[(warmup + steps - 1) % 2].cpu().numpy().astype(np.complex128)
+            spin = (warmup + steps - 1) % 2
+            Mo = M if c128 else M.astype(np.complex64).astype(np.complex128)
+            for b in (0, count - 1):
+                idx = rng.integers(0, w.ng * w.ng, size=nsample)
+                want = ref.gsigma(w, spin, tau[b], site[b], Mo[b], idx)
+                got = Gh[b].reshape(-1)[idx]
+                errs.append(float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+            out["error"] = {"rel_fro_vs_fp64_oracle": max(errs), "sampled_entries": 2 * nsample}
+        del G, ws, M_d
+        torch.cuda.empty_cache()
+        return out
+
     def plain(self, w, M, tile=0, reps=REPS):
         """Plain FP64 leg: M measurements, one pass each, timed `reps` times."""
         g4, torch = self.g4, self.torch
@@ -440,8 +494,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ring", action="store_true", help="skip the ring-share leg")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision leg")
+    ap.add_argument("--no-gsigma", action="store_true", help="skip the G_sigma leg")
+    ap.add_argument("--gsigma-order", type=int, default=512, help="expansion order of the G_sigma leg")
     ap.add_argument("--legs-only", action="store_true",
-                    help="run only the ring-share and split-precision legs (profiling)")
+                    help="run only the ring-share, split-precision and G_sigma legs (profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--pool", type=int, default=1024, help="distinct measurements resident in HBM")
     ap.add_argument("--no-batched", action="store_true")
@@ -574,6 +630,16 @@ def main():
             line["products"] = name
             leg[name] = line
         out["split_precision"] = leg
+
+    # ---- G_sigma from expansion configurations (the step before the update) --
+    if not args.no_gsigma and not ring:
+        gw = C2_PLAIN
+        n, count = args.gsigma_order, 64
+        out["gsigma"] = {"workload": "G_sigma of the 4x4 window (Nc=16, Nw=64, Nwex=8, Ng=%d) from seeded expansion "
+                                     "configurations of order n=%d, %d measurements per call, spins alternating"
+                                     % (gw.ng, n, count),
+                         "c64": bench.gsigma(gw, n, count, False, check=not args.no_check),
+                         "c128": bench.gsigma(gw, n, count, True, check=not args.no_check)}
 
     if not args.no_cpu_baseline and not args.legs_only:
         out["cpu_baseline"] = cpu_baseline(C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC), args.cpu_seconds)
