@@ -17,6 +17,17 @@
  *   PH charge    T = (Gu+Gd)(K1+Q,K1) (Gu+Gd)(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q)
  *   PP up-down   T = sum_s G_s(Q-K2,Q-K1) G_{-s}(K2,K1)
  *
+ * and the spin-resolved particle-hole channels (one spin pair each, the
+ * same Wick rule on the same operator strings):
+ *
+ *   PH longitudinal up-up    s1 = s2 = up:
+ *       T = Gu(K1+Q,K1) Gu(K2,K2+Q) - Gu(K2,K1) Gu(K1+Q,K2+Q)
+ *   PH longitudinal up-down  s1 = up, s2 = down (no exchange contraction):
+ *       T = Gu(K1+Q,K1) Gd(K2,K2+Q)
+ *   PH transverse            c+_{K1+Q,s} c_{K1,-s} c+_{K2,-s} c_{K2+Q,s}, summed over s
+ *       (no direct contraction):
+ *       T = - sum_s G_{-s}(K2,K1) G_s(K1+Q,K2+Q)
+ *
  * The PP term is the paper's Eq. (1) (Background section, "Memory-Bound Issue
  * in DCA++") with K3 read as the transfer Q.  The particle-hole terms are the
  * direct-minus-exchange Wick contractions of c+_{K1+Q,s1} c_{K1,s1}
@@ -60,7 +71,10 @@ typedef struct {
     long q_begin, q_end; /* slice: planes [q_begin, q_end) of nq*nwex */
 } oracle_shape;
 
-enum { ORACLE_PH_MAGNETIC = 1, ORACLE_PH_CHARGE = 2, ORACLE_PP_UPDOWN = 4 };
+enum {
+    ORACLE_PH_MAGNETIC = 1, ORACLE_PH_CHARGE = 2, ORACLE_PP_UPDOWN = 4,
+    ORACLE_PH_LONG_UPUP = 8, ORACLE_PH_LONG_UPDOWN = 16, ORACLE_PH_TRANSVERSE = 32
+};
 
 typedef struct { double re, im; } cplx;
 
@@ -116,17 +130,31 @@ static cplx entry_term(const oracle_shape *s, int channel, const double *gu, con
     int k2 = (int)(K2 / nw), n2 = (int)(K2 % nw) - nw / 2;
     long r_k1 = g_index(s, k1, n1), r_k2 = g_index(s, k2, n2);
     cplx t = {0.0, 0.0};
-    if (channel == ORACLE_PH_MAGNETIC || channel == ORACLE_PH_CHARGE) {
+    if (channel == ORACLE_PH_MAGNETIC || channel == ORACLE_PH_CHARGE || channel == ORACLE_PH_LONG_UPUP ||
+        channel == ORACLE_PH_LONG_UPDOWN || channel == ORACLE_PH_TRANSVERSE) {
         long r_k1q = g_index(s, mom_add(s, k1, q), n1 + m);   /* K1 + Q */
         long r_k2q = g_index(s, mom_add(s, k2, q), n2 + m);   /* K2 + Q */
-        cplx u1 = g_at(gu, ng, r_k1q, r_k1), d1 = g_at(gd, ng, r_k1q, r_k1);
-        cplx u2 = g_at(gu, ng, r_k2, r_k2q), d2 = g_at(gd, ng, r_k2, r_k2q);
-        cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);
-        cplx b = channel == ORACLE_PH_MAGNETIC ? c_sub(u2, d2) : c_add(u2, d2);
-        cplx direct = c_mul(a, b);
-        cplx ex_u = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));
-        cplx ex_d = c_mul(g_at(gd, ng, r_k2, r_k1), g_at(gd, ng, r_k1q, r_k2q));
-        t = c_sub(direct, c_add(ex_u, ex_d));
+        if (channel == ORACLE_PH_MAGNETIC || channel == ORACLE_PH_CHARGE) {
+            cplx u1 = g_at(gu, ng, r_k1q, r_k1), d1 = g_at(gd, ng, r_k1q, r_k1);
+            cplx u2 = g_at(gu, ng, r_k2, r_k2q), d2 = g_at(gd, ng, r_k2, r_k2q);
+            cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);
+            cplx b = channel == ORACLE_PH_MAGNETIC ? c_sub(u2, d2) : c_add(u2, d2);
+            cplx direct = c_mul(a, b);
+            cplx ex_u = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));
+            cplx ex_d = c_mul(g_at(gd, ng, r_k2, r_k1), g_at(gd, ng, r_k1q, r_k2q));
+            t = c_sub(direct, c_add(ex_u, ex_d));
+        } else if (channel == ORACLE_PH_LONG_UPUP) {
+            cplx direct = c_mul(g_at(gu, ng, r_k1q, r_k1), g_at(gu, ng, r_k2, r_k2q));
+            cplx ex = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));
+            t = c_sub(direct, ex);
+        } else if (channel == ORACLE_PH_LONG_UPDOWN) {
+            t = c_mul(g_at(gu, ng, r_k1q, r_k1), g_at(gd, ng, r_k2, r_k2q));
+        } else {
+            cplx ex_du = c_mul(g_at(gd, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));
+            cplx ex_ud = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gd, ng, r_k1q, r_k2q));
+            cplx zero = {0.0, 0.0};
+            t = c_sub(zero, c_add(ex_du, ex_ud));
+        }
     } else if (channel == ORACLE_PP_UPDOWN) {
         long r_qk1 = g_index(s, mom_sub(s, q, k1), m - n1 - 1); /* Q - K1 */
         long r_qk2 = g_index(s, mom_sub(s, q, k2), m - n2 - 1); /* Q - K2 */
@@ -144,7 +172,8 @@ static int check_shape(const oracle_shape *s, int channel) {
         return -1;
     for (int i = 0; i < s->nq; ++i)
         if (s->q_list[i] < 0 || s->q_list[i] >= s->lx * s->ly) return -1;
-    if (channel != ORACLE_PH_MAGNETIC && channel != ORACLE_PH_CHARGE && channel != ORACLE_PP_UPDOWN)
+    if (channel != ORACLE_PH_MAGNETIC && channel != ORACLE_PH_CHARGE && channel != ORACLE_PP_UPDOWN &&
+        channel != ORACLE_PH_LONG_UPUP && channel != ORACLE_PH_LONG_UPDOWN && channel != ORACLE_PH_TRANSVERSE)
         return -1;
     return 0;
 }

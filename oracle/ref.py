@@ -12,6 +12,9 @@ from . import build as _build
 PH_MAGNETIC = 1
 PH_CHARGE = 2
 PP_UPDOWN = 4
+PH_LONG_UPUP = 8
+PH_LONG_UPDOWN = 16
+PH_TRANSVERSE = 32
 
 
 class _Shape(ctypes.Structure):

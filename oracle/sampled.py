@@ -6,8 +6,9 @@ definition
 
     sum_b s_b T_ch(K1, K2, Q)
 
-(PH magnetic/charge: direct minus exchange Wick terms; PP: the paper's Eq. (1)
-with K3 -> Q), the G elements being regenerated one by one from their
+(PH magnetic/charge: direct minus exchange Wick terms; the spin-resolved PH
+channels: longitudinal up-up, longitudinal up-down, transverse; PP: the
+paper's Eq. (1) with K3 -> Q), the G elements being regenerated one by one from their
 Philox counters by the seeded input generator.  Index arithmetic is done on
 cluster coordinates and integer Matsubara labels, as in the C oracle: momenta
 add coordinate-wise modulo the cluster, w_n + nu_m = w_{n+m},
@@ -22,6 +23,9 @@ from synth.hubbard import Workload, g_elements, signs
 PH_MAGNETIC = 1
 PH_CHARGE = 2
 PP_UPDOWN = 4
+PH_LONG_UPUP = 8
+PH_LONG_UPDOWN = 16
+PH_TRANSVERSE = 32
 
 
 def _mom_add(w: Workload, k, q):
@@ -78,6 +82,20 @@ def entries(w: Workload, channel: int, idx, b0: int = 0, count: int = None,
             ex = (g_elements(w, b, 0, r_k2, r_k1) * g_elements(w, b, 0, r_k1q, r_k2q)
                   + g_elements(w, b, 1, r_k2, r_k1) * g_elements(w, b, 1, r_k1q, r_k2q))
             out += sign[j] * (direct - ex)
+    elif channel in (PH_LONG_UPUP, PH_LONG_UPDOWN, PH_TRANSVERSE):
+        r_k1q = _g_index(w, _mom_add(w, k1, q), n1 + m)
+        r_k2q = _g_index(w, _mom_add(w, k2, q), n2 + m)
+        for j in range(count):
+            b = b0 + j
+            if channel == PH_LONG_UPUP:
+                t = (g_elements(w, b, 0, r_k1q, r_k1) * g_elements(w, b, 0, r_k2, r_k2q)
+                     - g_elements(w, b, 0, r_k2, r_k1) * g_elements(w, b, 0, r_k1q, r_k2q))
+            elif channel == PH_LONG_UPDOWN:
+                t = g_elements(w, b, 0, r_k1q, r_k1) * g_elements(w, b, 1, r_k2, r_k2q)
+            else:
+                t = -(g_elements(w, b, 1, r_k2, r_k1) * g_elements(w, b, 0, r_k1q, r_k2q)
+                      + g_elements(w, b, 0, r_k2, r_k1) * g_elements(w, b, 1, r_k1q, r_k2q))
+            out += sign[j] * t
     elif channel == PP_UPDOWN:
         r_qk1 = _g_index(w, _mom_sub(w, q, k1), m - n1 - 1)
         r_qk2 = _g_index(w, _mom_sub(w, q, k2), m - n2 - 1)

@@ -6,6 +6,9 @@ and Wick's theorem reduces every channel to products of g:
   PH magnetic  S [ delta_{Q,0} (g_u - g_d)(K1) (g_u - g_d)(K2) - delta_{K1,K2} sum_s g_s(K1) g_s(K1+Q) ]
   PH charge    S [ delta_{Q,0} (g_u + g_d)(K1) (g_u + g_d)(K2) - delta_{K1,K2} sum_s g_s(K1) g_s(K1+Q) ]
   PP (Eq. 1)   S   delta_{K1,K2} sum_s g_s(Q-K1) g_{-s}(K1)
+  PH up-up     S [ delta_{Q,0} g_u(K1) g_u(K2) - delta_{K1,K2} g_u(K1) g_u(K1+Q) ]
+  PH up-down   S   delta_{Q,0} g_u(K1) g_d(K2)
+  PH transv.  -S   delta_{K1,K2} [ g_u(K1) g_d(K1+Q) + g_d(K1) g_u(K1+Q) ]
 
 with S the sum of the measurement signs.  Here g is evaluated from physical
 momenta and Matsubara frequencies in floating point (k+q as a vector,
@@ -69,6 +72,15 @@ def closed_form(w, channel, h, S):
             if q == 0 and m == 0:
                 out[p] += np.outer(d, d)   # [K2][K1] = d(K2) d(K1)
             out[p][K, K] -= gu * gu_q + gd * gd_q
+        elif channel == ref.PH_LONG_UPUP:
+            if q == 0 and m == 0:
+                out[p] += np.outer(gu, gu)
+            out[p][K, K] -= gu * gu_q
+        elif channel == ref.PH_LONG_UPDOWN:
+            if q == 0 and m == 0:
+                out[p] += np.outer(gd, gu)   # [K2][K1] = g_d(K2) g_u(K1)
+        elif channel == ref.PH_TRANSVERSE:
+            out[p][K, K] -= gu * gd_q + gd * gu_q
         else:
             out[p][K, K] += gu_r * gd + gd_r * gu
     return S * out
@@ -86,7 +98,8 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
-@pytest.mark.parametrize("channel", [ref.PH_MAGNETIC, ref.PH_CHARGE, ref.PP_UPDOWN])
+@pytest.mark.parametrize("channel", [ref.PH_MAGNETIC, ref.PH_CHARGE, ref.PP_UPDOWN, ref.PH_LONG_UPUP,
+                                     ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE])
 @pytest.mark.parametrize("h", [0.0, 0.25])
 def test_noninteracting_closed_form(w, channel, h):
     gu = np.diag(diag_g(w, +1, h))

@@ -24,7 +24,8 @@ from oracle import build as oracle_build
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_wick.py",
         "tests/test_oracle_arrays.py", "tests/test_oracle_invariants.py",
-        "tests/test_oracle_compensated.py", "tests/test_oracle_gsigma.py"]
+        "tests/test_oracle_compensated.py", "tests/test_oracle_gsigma.py",
+        "tests/test_oracle_spin_channels.py"]
 
 # name -> (text in the oracle source, replacement)
 MUTANTS = {
@@ -43,7 +44,8 @@ MUTANTS = {
     "k1-q for k1+q": (
         "g_index(s, mom_add(s, k1, q), n1 + m);", "g_index(s, mom_sub(s, k1, q), n1 + m);"),
     "transposed exchange operand": (
-        "g_at(gu, ng, r_k1q, r_k2q)", "g_at(gu, ng, r_k2q, r_k1q)"),
+        "cplx ex_u = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));",
+        "cplx ex_u = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k2q, r_k1q));"),
     "transposed direct operand": (
         "cplx u1 = g_at(gu, ng, r_k1q, r_k1), d1 = g_at(gd, ng, r_k1q, r_k1);",
         "cplx u1 = g_at(gu, ng, r_k1, r_k1q), d1 = g_at(gd, ng, r_k1, r_k1q);"),
@@ -59,6 +61,17 @@ MUTANTS = {
         "mom_sub(s, q, k1), m - n1 - 1)", "mom_sub(s, q, k1), m - n2 - 1)"),
     "PP frequency off by one": (
         "mom_sub(s, q, k2), m - n2 - 1)", "mom_sub(s, q, k2), m - n2)"),
+    # spin-resolved particle-hole channels
+    "up-up exchange dropped": (
+        "t = c_sub(direct, ex);", "t = direct;"),
+    "up-down spins swapped": (
+        "t = c_mul(g_at(gu, ng, r_k1q, r_k1), g_at(gd, ng, r_k2, r_k2q));",
+        "t = c_mul(g_at(gd, ng, r_k1q, r_k1), g_at(gu, ng, r_k2, r_k2q));"),
+    "transverse with equal spins": (
+        "cplx ex_du = c_mul(g_at(gd, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));",
+        "cplx ex_du = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));"),
+    "transverse sign": (
+        "t = c_sub(zero, c_add(ex_du, ex_ud));", "t = c_add(zero, c_add(ex_du, ex_ud));"),
     # G_sigma from an expansion configuration
     "G_sigma: conjugate phase on the left factor": (
         "const cplx ea = {cos(tha), sin(tha)};", "const cplx ea = {cos(tha), -sin(tha)};"),

@@ -11,6 +11,9 @@ The channels are the operator strings
   PH magnetic  sum_{s1,s2} s1 s2 < c+_{K1+Q,s1} c_{K1,s1} c+_{K2,s2} c_{K2+Q,s2} >
   PH charge    sum_{s1,s2}       < c+_{K1+Q,s1} c_{K1,s1} c+_{K2,s2} c_{K2+Q,s2} >
   PP           sum_s < c+_{K2,-s} c+_{Q-K2,s} c_{Q-K1,s} c_{K1,-s} >   (gives Eq. (1))
+  PH long. up-up     < c+_{K1+Q,u} c_{K1,u} c+_{K2,u} c_{K2+Q,u} >
+  PH long. up-down   < c+_{K1+Q,u} c_{K1,u} c+_{K2,d} c_{K2+Q,d} >
+  PH transverse      sum_s < c+_{K1+Q,s} c_{K1,-s} c+_{K2,-s} c_{K2+Q,s} >
 
 This test enumerates every tuple of G-window indices, keeps the tuples whose
 momenta and Matsubara frequencies are conserved (checked on physical values:
@@ -84,12 +87,25 @@ def transfer_plane(w, dkx, dky, dom):
     return None
 
 
+def ph_strings(channel):
+    """Spins of c+_{K1+Q} c_{K1} c+_{K2} c_{K2+Q} and the weight of each string."""
+    if channel == ref.PH_MAGNETIC:
+        return [((s1, s1, s2, s2), (1 - 2 * s1) * (1 - 2 * s2)) for s1 in (0, 1) for s2 in (0, 1)]
+    if channel == ref.PH_CHARGE:
+        return [((s1, s1, s2, s2), 1.0) for s1 in (0, 1) for s2 in (0, 1)]
+    if channel == ref.PH_LONG_UPUP:
+        return [((0, 0, 0, 0), 1.0)]
+    if channel == ref.PH_LONG_UPDOWN:
+        return [((0, 0, 1, 1), 1.0)]
+    return [((s, 1 - s, 1 - s, s), 1.0) for s in (0, 1)]      # transverse
+
+
 def brute_force(w, channel, Gs, sgn):
     P = [physical(w, r) for r in range(w.ng)]
     out = np.zeros((w.planes, w.n, w.n), dtype=np.complex128)
     hits = np.zeros(out.shape, dtype=int)
     rng = range(w.ng)
-    if channel in (ref.PH_MAGNETIC, ref.PH_CHARGE):
+    if channel in (ref.PH_MAGNETIC, ref.PH_CHARGE, ref.PH_LONG_UPUP, ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE):
         left = {}   # (X1, Y1): transfer X1 - Y1, Y1 = K1
         right = {}  # (X2, Y2): transfer Y2 - X2, X2 = K2
         for x, y in itertools.product(rng, rng):
@@ -106,11 +122,11 @@ def brute_force(w, channel, Gs, sgn):
             for (x1, y1), (x2, y2) in itertools.product(left[p], right.get(p, [])):
                 K1, K2 = g4_index(w, y1), g4_index(w, x2)
                 v = 0j
-                for s1, s2 in itertools.product((0, 1), (0, 1)):
-                    wt = 1.0 if channel == ref.PH_CHARGE else (1 - 2 * s1) * (1 - 2 * s2)
+                for spins, wt in ph_strings(channel):
+                    a1, a2, a3, a4 = spins
                     for b, s in enumerate(sgn):
-                        v += s * wt * wick([(True, x1, s1), (False, y1, s1),
-                                            (True, x2, s2), (False, y2, s2)], Gs[b])
+                        v += s * wt * wick([(True, x1, a1), (False, y1, a2),
+                                            (True, x2, a3), (False, y2, a4)], Gs[b])
                 out[p, K2, K1] += v
                 hits[p, K2, K1] += 1
     else:
@@ -141,7 +157,8 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
-@pytest.mark.parametrize("channel", [ref.PH_MAGNETIC, ref.PH_CHARGE, ref.PP_UPDOWN])
+@pytest.mark.parametrize("channel", [ref.PH_MAGNETIC, ref.PH_CHARGE, ref.PP_UPDOWN, ref.PH_LONG_UPUP,
+                                     ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE])
 def test_brute_force_wick(w, channel):
     rng = np.random.default_rng(11 + channel)
     sgn = np.array([1.0, -1.0])
