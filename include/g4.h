@@ -34,6 +34,18 @@
  *   PH magnetic  G4 += s_b [ (Gu-Gd)(K1+Q,K1) (Gu-Gd)(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q) ]
  *   PH charge    G4 += s_b [ (Gu+Gd)(K1+Q,K1) (Gu+Gd)(K2,K2+Q) - sum_s G_s(K2,K1) G_s(K1+Q,K2+Q) ]
  *   PP up-down   G4 += s_b   sum_s G_s(Q-K2,Q-K1) G_{-s}(K2,K1)          (Eq. (1), K3 -> Q)
+ * and the spin-resolved particle-hole channels, from the same Wick rule on
+ * c+_{K1+Q,s1} c_{K1,s2} c+_{K2,s3} c_{K2+Q,s4} with one spin assignment each:
+ *   PH longitudinal up-up    G4 += s_b [ Gu(K1+Q,K1) Gu(K2,K2+Q) - Gu(K2,K1) Gu(K1+Q,K2+Q) ]
+ *   PH longitudinal up-down  G4 += s_b   Gu(K1+Q,K1) Gd(K2,K2+Q)
+ *   PH transverse            G4 += -s_b  sum_s G_{-s}(K2,K1) G_s(K1+Q,K2+Q)
+ *     (spins (s, -s, -s, s) summed over s)
+ * (magnetic = uu + dd - ud - du and charge = uu + dd + ud + du, with dd, du
+ * the up-up and up-down channels of the spin-swapped pair).
+ * A slice holds channels of one family: a subset of {G4_PH_MAGNETIC,
+ * G4_PH_CHARGE, G4_PP_UPDOWN} or of {G4_PH_LONG_UPUP, G4_PH_LONG_UPDOWN,
+ * G4_PH_TRANSVERSE}; the spin-resolved ones run on the register-staged
+ * (VALU) kernels.
  * The values kept are raw signed sums; g4_stats gives the measurement count
  * and the sum of weights for normalisation.
  *
@@ -68,8 +80,12 @@ enum {
     G4_E_UNSUPPORTED = -5   /* valid request this build does not implement */
 };
 
-/* channels (bitmask) */
-enum { G4_PH_MAGNETIC = 1, G4_PH_CHARGE = 2, G4_PP_UPDOWN = 4 };
+/* channels (bitmask); accumulator slot 0: magnetic or up-up, 1: charge or
+ * up-down, 2: PP or transverse */
+enum {
+    G4_PH_MAGNETIC = 1, G4_PH_CHARGE = 2, G4_PP_UPDOWN = 4,
+    G4_PH_LONG_UPUP = 8, G4_PH_LONG_UPDOWN = 16, G4_PH_TRANSVERSE = 32
+};
 
 /* element type of the G_up / G_dn buffers passed to g4_accumulate */
 enum {
@@ -120,8 +136,8 @@ enum {
                                  as a whole.  The caller's stream must not be capturing already. */
     G4_F_MFMA = 8u,           /* batched FP32: direct term on MFMA (nw = 64 or 128; 16-row tiles).
                                  With G4_F_PACKED: the packed operands of G4_F_PACKED and the
-                                 direct term on MFMA in one kernel (nw = 64, 16-row tiles, PH
-                                 channels only, FP32 products). */
+                                 direct term on MFMA in one kernel (nw = 64, 8-row tiles, PH
+                                 magnetic and charge only, FP32 products). */
     G4_F_PACKED = 16u,        /* batched FP32: each pass first packs G_up and G_dn side by side
                                  (16 bytes per element, each momentum block of Nwg columns padded
                                  to a multiple of 8, with the pass's direct vectors) and the
@@ -153,7 +169,9 @@ typedef struct g4_config {
     const int32_t *q_list;    /* host array of nq distinct momenta in [0,Nc), or NULL for 0..nq-1;
                                  copied by g4_init_slice */
     int64_t q_begin, q_end;   /* slice planes, 0 <= q_begin < q_end <= nq*nwex */
-    uint32_t channels;        /* nonzero bitmask of G4_PH_MAGNETIC | G4_PH_CHARGE | G4_PP_UPDOWN */
+    uint32_t channels;        /* nonzero bitmask of G4_PH_MAGNETIC | G4_PH_CHARGE | G4_PP_UPDOWN,
+                                 or of G4_PH_LONG_UPUP | G4_PH_LONG_UPDOWN | G4_PH_TRANSVERSE
+                                 (not both families; the second on the VALU kernels only) */
     int32_t g_in;             /* G4_IN_* */
     int32_t prod;             /* G4_PROD_* ; G4_MODE_PLAIN requires G4_PROD_F64 */
     int32_t acc;              /* G4_ACC_* */
@@ -325,8 +343,9 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
  *     stream), cfg->device the GPU.  Runs the VALU kernels: plain mode, or
  *     batched with G4_PROD_F64 or G4_PROD_F32 (complex64 G for FP32); no
  *     G4_F_* flags (G4_E_UNSUPPORTED otherwise).
- *   acc_mag, acc_chg, acc_pp: DEVICE accumulators, one per channel in
- *     cfg->channels (NULL for the others), each entries x 16 bytes (G4_ACC_C128,
+ *   acc_mag, acc_chg, acc_pp: DEVICE accumulators of slots 0, 1, 2, one per
+ *     channel in cfg->channels (slot 0: magnetic or up-up, 1: charge or
+ *     up-down, 2: PP or transverse; NULL for absent ones), each entries x 16 bytes (G4_ACC_C128,
  *     G4_ACC_C64_KAHAN) or x 8 bytes (G4_ACC_C64), in the library's device
  *     layout [plane][k2][k1][i2][i1] (K = k*nw + i), which g4_readback
  *     translates for a slice; the caller zeroes them before the first call.

@@ -105,8 +105,9 @@ int validate(const g4_config *c, Plan *p) {
     if (c->q_begin < 0 || c->q_end > nQ || c->q_begin >= c->q_end)
         return fail(G4_E_ARG, "slice [%lld, %lld) not inside [0, %lld)", (long long)c->q_begin,
                     (long long)c->q_end, (long long)nQ);
-    if (c->channels == 0 || (c->channels & ~7u))
-        return fail(G4_E_ARG, "channels bitmask 0x%x invalid", c->channels);
+    const bool spin_set = (c->channels & ~7u) != 0;
+    if (c->channels == 0 || (c->channels & ~63u) || (spin_set && (c->channels & 7u)))
+        return fail(G4_E_ARG, "channels bitmask 0x%x invalid (one family: bits 1|2|4 or 8|16|32)", c->channels);
     if (c->g_in != G4_IN_C128 && c->g_in != G4_IN_C64) return fail(G4_E_ARG, "g_in=%d", c->g_in);
     if (c->prod < G4_PROD_F64 || c->prod > G4_PROD_F16X2) return fail(G4_E_ARG, "prod=%d", c->prod);
     if (c->acc < G4_ACC_C128 || c->acc > G4_ACC_C64) return fail(G4_E_ARG, "acc=%d", c->acc);
@@ -152,7 +153,7 @@ int validate(const g4_config *c, Plan *p) {
     P.kind = c->mode == G4_MODE_PLAIN ? 0 : (P.prec == 0 ? 1 : 2);
     P.batch = c->mode == G4_MODE_PLAIN ? 1 : c->max_batch;
     P.mgroup = choose_mgroup(c->nwex);
-    const int nch = popcount3(c->channels);
+    const int nch = popcount3((uint32_t)acc_slots((int)c->channels));
     const int rp = 256 / c->nw;
     const uint32_t vf = c->flags & (G4_F_MFMA | G4_F_PACKED | G4_F_PACKED_DEEP);
     if (popcount3(vf >> 3) > 1 && vf != (G4_F_MFMA | G4_F_PACKED))
@@ -162,6 +163,9 @@ int validate(const g4_config *c, Plan *p) {
               : (c->flags & G4_F_MFMA) ? G4_VARIANT_MFMA
               : (c->flags & G4_F_PACKED) ? G4_VARIANT_PACKED
               : (c->flags & G4_F_PACKED_DEEP) ? G4_VARIANT_PACKED_DEEP : G4_VARIANT_VALU;
+    if (spin_set && (P.variant != G4_VARIANT_VALU || P.split))
+        return fail(G4_E_UNSUPPORTED, "spin-resolved channels run on the VALU kernels only (no G4_F_MFMA, "
+                                      "G4_F_PACKED, G4_F_PACKED_DEEP or split products)");
     // split-precision plans run the packed kernels (their direct vectors can be
     // read as zeros there, with no test in the arithmetic loop)
     if (P.split && P.variant == G4_VARIANT_VALU) P.variant = G4_VARIANT_PACKED;
@@ -209,8 +213,8 @@ int validate(const g4_config *c, Plan *p) {
     if (P.variant != 1) P.tile = P.ept * rp_v;
     if (update_lds_bytes(P.kind, (int)c->channels, P.tile, P.mgroup, d, P.variant) > 160 * 1024)
         return fail(G4_E_UNSUPPORTED, "LDS tile above 160 KiB");
-    P.slots = c->channels & 3u;
-    P.nslots = popcount3(P.slots);
+    P.slots = direct_recipes((int)c->channels);
+    P.nslots = __builtin_popcount((unsigned)P.slots);
     // packed operands: one block per measurement, [G rows of ldp 16-byte
     // elements | direct vectors a | b]; every copy offset inside it is 32-bit.
     // Momentum blocks of columns start on 128-byte boundaries; one zero
@@ -251,7 +255,7 @@ int validate(const g4_config *c, Plan *p) {
         return fail(G4_E_UNSUPPORTED, "%llu work tiles at one K2 row per tile: above 2^31",
                     (unsigned long long)nitems_max);
     P.table_bytes = 2ull * nc * nc * 4 + (uint64_t)d.planes * 16 + nitems_max * 16 + (uint64_t)d.planes * 8;
-    P.total_bytes = P.acc_bytes * popcount3(c->channels) + P.dir_bytes + P.stage_bytes + P.sign_bytes +
+    P.total_bytes = P.acc_bytes * nch + P.dir_bytes + P.stage_bytes + P.sign_bytes +
                     P.scratch_bytes + P.table_bytes + P.pack_bytes;
     return G4_OK;
 }
@@ -458,7 +462,12 @@ int usable(g4_slice *h) {
 }
 
 int channel_slot(uint32_t channel) {
-    return channel == G4_PH_MAGNETIC ? 0 : channel == G4_PH_CHARGE ? 1 : channel == G4_PP_UPDOWN ? 2 : -1;
+    switch (channel) {
+        case G4_PH_MAGNETIC: case G4_PH_LONG_UPUP: return 0;
+        case G4_PH_CHARGE: case G4_PH_LONG_UPDOWN: return 1;
+        case G4_PP_UPDOWN: case G4_PH_TRANSVERSE: return 2;
+        default: return -1;
+    }
 }
 
 void drop_graphs(g4_slice *h) {
@@ -803,7 +812,7 @@ int noalloc_accumulate(const g4_config *cfg, void *const acc[3], const void *G_u
         return fail(G4_E_UNSUPPORTED, "g4_accumulate_into: FP32 products need complex64 G");
     if (batch < 0) return fail(G4_E_ARG, "batch=%d", batch);
     for (int c = 0; c < 3; ++c) {
-        const bool want = (cfg->channels >> c) & 1u;
+        const bool want = (acc_slots((int)cfg->channels) >> c) & 1;
         if (want != (acc[c] != nullptr))
             return fail(G4_E_ARG, "accumulator %d must be %s", c, want ? "given" : "NULL for an absent channel");
     }
@@ -1010,7 +1019,7 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     }
     const uint64_t ab = P.acc_bytes;
     for (int c = 0; c < 3; ++c)
-        if (cfg->channels & (1u << c)) G4_INIT(hipMalloc(&h->acc[c], ab));
+        if (acc_slots((int)cfg->channels) & (1 << c)) G4_INIT(hipMalloc(&h->acc[c], ab));
     const int nc = P.d.nc;
     G4_INIT(hipMalloc(&h->kadd, (size_t)nc * nc * 4));
     G4_INIT(hipMalloc(&h->ksub, (size_t)nc * nc * 4));
@@ -1300,7 +1309,7 @@ int make_sample(g4_slice *h, const void *gu, const void *gd, const double *sign,
     G4_HIP(h, hipMemcpy(ts.idx_dev, ts.idx.data(), ns * sizeof(uint64_t), hipMemcpyHostToDevice));
     G4_HIP(h, hipMemcpy(ts.sign_dev, sign, (size_t)nb * sizeof(double), hipMemcpyHostToDevice));
     for (int c = 0; c < 3; ++c) {
-        if (!(h->cfg.channels & (1u << c))) continue;
+        if (!(acc_slots((int)h->cfg.channels) & (1 << c))) continue;
         RefArgs ra;
         ra.gu = gu;
         ra.gd = gd;
@@ -1308,7 +1317,7 @@ int make_sample(g4_slice *h, const void *gu, const void *gd, const double *sign,
         ra.g_stride = (int64_t)h->P.d.ng * h->P.d.ng;
         ra.sign = ts.sign_dev;
         ra.batch = nb;
-        ra.channel = 1 << c;
+        ra.channel = (int)h->cfg.channels & (9 << c);   // the slice's channel in slot c
         ra.idx = ts.idx_dev;
         ra.count = (int64_t)ns;
         ra.out = ts.vals_dev;

@@ -55,7 +55,19 @@ inline hipError_t ensure_lds_limit(const void *fn, size_t lds) {
     if (e == hipSuccess) done[{fn, dev}] = lds;
     return e;
 }
-enum { CH_MAG = 1, CH_CHG = 2, CH_PP = 4 };
+enum { CH_MAG = 1, CH_CHG = 2, CH_PP = 4, CH_UU = 8, CH_UD = 16, CH_TR = 32 };
+// Accumulator slot of each channel bit (0 magnetic / up-up, 1 charge /
+// up-down, 2 PP / transverse) and the slots a channel set occupies.
+__host__ __device__ constexpr int acc_slot_of(int ch) {
+    return (ch & (CH_MAG | CH_UU)) ? 0 : (ch & (CH_CHG | CH_UD)) ? 1 : 2;
+}
+__host__ __device__ constexpr int acc_slots(int channels) { return (channels | (channels >> 3)) & 7; }
+// Direct-vector recipes (GatherArgs::slots bits), in slot order:
+// bit 0 magnetic a = s(Gu-Gd), b = Gu-Gd; bit 1 charge (sums); bit 2 up-up
+// a = s Gu, b = Gu; bit 3 up-down a = s Gu, b = Gd.
+__host__ __device__ constexpr int direct_recipes(int channels) {
+    return (channels & (CH_MAG | CH_CHG)) | ((channels & CH_UU) ? 4 : 0) | ((channels & CH_UD) ? 8 : 0);
+}
 
 // Arguments of the slice-update kernel.  G elements are complex of the
 // product precision (double2 for FP64, float2 for FP32).
@@ -162,7 +174,8 @@ struct GatherArgs {
     int64_t dir_b_stride;
     const double *sign;
     int batch;
-    int slots;          // bit 0: magnetic (G_up - G_dn), bit 1: charge (G_up + G_dn)
+    int slots;          // direct_recipes(): bit 0 magnetic (G_up - G_dn), bit 1 charge
+                        // (G_up + G_dn), bit 2 up-up (G_up, G_up), bit 3 up-down (G_up, G_dn)
     Dims d;
     Tables t;
 };
@@ -187,9 +200,10 @@ inline size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, con
     // vectors (two copies, by measurement parity, for the MFMA variant)
     const size_t el = kind == 2 ? sizeof(float2) : sizeof(double2);
     const int T2 = tile < d.nw ? tile : d.nw;
-    const int nph = ((channels & CH_MAG) ? 1 : 0) + ((channels & CH_CHG) ? 1 : 0);
+    const int nph = __builtin_popcount(direct_recipes(channels));
+    const bool ex = (channels & (CH_MAG | CH_CHG | CH_UU | CH_TR)) != 0;
     size_t pairs = (size_t)T2 * d.nw;
-    if (nph) pairs += (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
+    if (ex) pairs += (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
     if (channels & CH_PP) pairs += (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
     const size_t vecs = (size_t)nph * mgroup * (d.nw + T2) * (variant == 1 ? 2 : 1);
     return pairs * 2 * el + vecs * el;
@@ -233,7 +247,7 @@ hipError_t launch_merge(int dkind, void *dst, int skind, const void *src, uint64
 // FP64 evaluation, straight from the G matrices, of sum_b s_b T_ch at listed
 // slice entries (documented [plane][K2][K1] order): the reference of the
 // autotuner's accuracy gate.  G elements complex128 (g_in 0) or complex64
-// (g_in 1, widened); `channel` one of CH_MAG, CH_CHG, CH_PP.
+// (g_in 1, widened); `channel` one CH_* bit.
 struct RefArgs {
     const void *gu, *gd;
     int g_in;

@@ -55,6 +55,16 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
         if (a.slots & 2) {
             da[o] = V{s * (au.x + ad.x), s * (au.y + ad.y)};
             db[o] = V{bu.x + bd.x, bu.y + bd.y};
+            o += a.dir_slot_stride;
+        }
+        if (a.slots & 4) {          // longitudinal up-up
+            da[o] = V{s * au.x, s * au.y};
+            db[o] = bu;
+            o += a.dir_slot_stride;
+        }
+        if (a.slots & 8) {          // longitudinal up-down
+            da[o] = V{s * au.x, s * au.y};
+            db[o] = bd;
         }
     }
 }
@@ -294,14 +304,25 @@ __global__ void ref_entries_kernel(RefArgs a) {
                 // K+Q: momentum k+q, local frequency i + m
                 const int64_t p1 = (int64_t)a.t.kadd[k1 * nc + q] * nwg + i1 + m;
                 const int64_t p2 = (int64_t)a.t.kadd[k2 * nc + q] * nwg + i2 + m;
-                const double sg = a.channel == CH_MAG ? -1.0 : 1.0;
                 const double2 u1 = ref_g(a.gu, a.g_in, base + p1 * ng + r1), d1 = ref_g(a.gd, a.g_in, base + p1 * ng + r1);
                 const double2 u2 = ref_g(a.gu, a.g_in, base + r2 * ng + p2), d2 = ref_g(a.gd, a.g_in, base + r2 * ng + p2);
-                const double2 dir = zmul(double2{u1.x + sg * d1.x, u1.y + sg * d1.y},
-                                         double2{u2.x + sg * d2.x, u2.y + sg * d2.y});
-                const double2 eu = zmul(ref_g(a.gu, a.g_in, base + r2 * ng + r1), ref_g(a.gu, a.g_in, base + p1 * ng + p2));
-                const double2 ed = zmul(ref_g(a.gd, a.g_in, base + r2 * ng + r1), ref_g(a.gd, a.g_in, base + p1 * ng + p2));
-                t = double2{dir.x - eu.x - ed.x, dir.y - eu.y - ed.y};
+                const double2 xu = ref_g(a.gu, a.g_in, base + r2 * ng + r1), xd = ref_g(a.gd, a.g_in, base + r2 * ng + r1);
+                const double2 yu = ref_g(a.gu, a.g_in, base + p1 * ng + p2), yd = ref_g(a.gd, a.g_in, base + p1 * ng + p2);
+                if (a.channel == CH_MAG || a.channel == CH_CHG) {
+                    const double sg = a.channel == CH_MAG ? -1.0 : 1.0;
+                    const double2 dir = zmul(double2{u1.x + sg * d1.x, u1.y + sg * d1.y},
+                                             double2{u2.x + sg * d2.x, u2.y + sg * d2.y});
+                    const double2 eu = zmul(xu, yu), ed = zmul(xd, yd);
+                    t = double2{dir.x - eu.x - ed.x, dir.y - eu.y - ed.y};
+                } else if (a.channel == CH_UU) {
+                    const double2 dir = zmul(u1, u2), eu = zmul(xu, yu);
+                    t = double2{dir.x - eu.x, dir.y - eu.y};
+                } else if (a.channel == CH_UD) {
+                    t = zmul(u1, d2);
+                } else {
+                    const double2 e1 = zmul(xd, yu), e2 = zmul(xu, yd);
+                    t = double2{-(e1.x + e2.x), -(e1.y + e2.y)};
+                }
             }
             const double s = a.sign[b];
             acc.x += s * t.x;

@@ -146,16 +146,27 @@ constexpr int NT = 256;   // threads per block
 constexpr int SX = 32;    // staging lanes along a G row
 constexpr int SY = NT / SX;
 
+// Channel set CH: magnetic / charge / PP, or the spin-resolved PH channels
+// (longitudinal up-up, up-down, transverse; VALU kernel only).  Register
+// accumulators are numbered in bit order; direct-vector slots likewise over
+// the channels with a direct term.
 template <int CH>
 struct ChanInfo {
     static constexpr bool mag = (CH & CH_MAG) != 0;
     static constexpr bool chg = (CH & CH_CHG) != 0;
     static constexpr bool pp = (CH & CH_PP) != 0;
-    static constexpr bool ph = mag || chg;
-    static constexpr int count = (mag ? 1 : 0) + (chg ? 1 : 0) + (pp ? 1 : 0);
-    static constexpr int nph = (mag ? 1 : 0) + (chg ? 1 : 0);
+    static constexpr bool uu = (CH & CH_UU) != 0;
+    static constexpr bool ud = (CH & CH_UD) != 0;
+    static constexpr bool tr = (CH & CH_TR) != 0;
+    static constexpr bool ph = mag || chg || uu || ud || tr;
+    static constexpr bool ex = mag || chg || uu || tr;      // needs the exchange block
+    static constexpr int count = (mag ? 1 : 0) + (chg ? 1 : 0) + (pp ? 1 : 0) + (uu ? 1 : 0) + (ud ? 1 : 0) +
+                                 (tr ? 1 : 0);
+    static constexpr int nph = (mag ? 1 : 0) + (chg ? 1 : 0) + (uu ? 1 : 0) + (ud ? 1 : 0);
     static constexpr int slot_chg = mag ? 1 : 0;
-    static constexpr int slot_pp = nph;
+    static constexpr int slot_pp = (mag ? 1 : 0) + (chg ? 1 : 0);
+    static constexpr int slot_ud = uu ? 1 : 0;
+    static constexpr int slot_tr = (uu ? 1 : 0) + (ud ? 1 : 0);
 };
 
 // Kind: 0 plain FP64 (one measurement, c128 accumulator, prefetched);
@@ -212,7 +223,7 @@ struct Tile {
         T2 = min(tile, nw - c0);
         yr = nw + M - 1; yc = T2 + M - 1;
         zr = T2 + M - 1; zc = nw + M - 1;
-        nY = CI::ph ? yr * yc : 0;
+        nY = CI::ex ? yr * yc : 0;
         nZ = CI::pp ? zr * zc : 0;
         nX = T2 * nw;
         nG = nY + nZ + nX;
@@ -221,8 +232,8 @@ struct Tile {
         nV = nA + nB;
         Gp = reinterpret_cast<V *>(smem);
         Vt = Gp + 2 * nG;
-        rowY = CI::ph ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
-        colY = CI::ph ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
+        rowY = CI::ex ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
+        colY = CI::ex ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
         rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
         colZ = CI::pp ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
         rowX = k2 * nwg + c0;
@@ -377,6 +388,9 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
                         if (CI::mag) acc[0][j][m] = acc_ld(static_cast<const V *>(a.acc[0]) + e);
                         if (CI::chg) acc[CI::slot_chg][j][m] = acc_ld(static_cast<const V *>(a.acc[1]) + e);
                         if (CI::pp) acc[CI::slot_pp][j][m] = acc_ld(static_cast<const V *>(a.acc[2]) + e);
+                        if (CI::uu) acc[0][j][m] = acc_ld(static_cast<const V *>(a.acc[0]) + e);
+                        if (CI::ud) acc[CI::slot_ud][j][m] = acc_ld(static_cast<const V *>(a.acc[1]) + e);
+                        if (CI::tr) acc[CI::slot_tr][j][m] = acc_ld(static_cast<const V *>(a.acc[2]) + e);
                     }
                 });
             });
@@ -408,7 +422,23 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
         });
         auto body = [&](auto j, auto m) __attribute__((always_inline)) {
             const int i2l = r0 + j * RP;
-            if (CI::ph) {
+            if (CI::uu || CI::ud || CI::tr) {
+                // spin-resolved channels; xu, xd carry -s_b (the exchange sign)
+                V yu{0, 0}, yd{0, 0};
+                if (CI::ex) t.y_at(i2l, i1, m, yu, yd);
+                if (CI::uu) {
+                    cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
+                    cmac(acc[0][j][m], xu[j], yu);
+                }
+                if (CI::ud) {
+                    const int sm = CI::slot_ud * M + m;
+                    cmac(acc[CI::slot_ud][j][m], ld(At + sm * nw + i1), ld(Bt + sm * T2 + i2l));
+                }
+                if (CI::tr) {
+                    cmac(acc[CI::slot_tr][j][m], xd[j], yu);
+                    cmac(acc[CI::slot_tr][j][m], xu[j], yd);
+                }
+            } else if (CI::ph) {
                 V yu, yd;
                 t.y_at(i2l, i1, m, yu, yd);
                 if (CI::mag) {
@@ -457,10 +487,16 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
                 if (CI::mag) acc_st(static_cast<V *>(a.acc[0]) + e, acc[0][j][m]);
                 if (CI::chg) acc_st(static_cast<V *>(a.acc[1]) + e, acc[CI::slot_chg][j][m]);
                 if (CI::pp) acc_st(static_cast<V *>(a.acc[2]) + e, acc[CI::slot_pp][j][m]);
+                if (CI::uu) acc_st(static_cast<V *>(a.acc[0]) + e, acc[0][j][m]);
+                if (CI::ud) acc_st(static_cast<V *>(a.acc[1]) + e, acc[CI::slot_ud][j][m]);
+                if (CI::tr) acc_st(static_cast<V *>(a.acc[2]) + e, acc[CI::slot_tr][j][m]);
             } else {
                 if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
                 if (CI::chg) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_chg][j][m]);
                 if (CI::pp) acc_update(a.acc[2], a.acc_kind, e, acc[CI::slot_pp][j][m]);
+                if (CI::uu) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
+                if (CI::ud) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_ud][j][m]);
+                if (CI::tr) acc_update(a.acc[2], a.acc_kind, e, acc[CI::slot_tr][j][m]);
             }
         });
     });
@@ -598,6 +634,7 @@ hipError_t launch_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, 
         fn = reinterpret_cast<const void *>(&update_kernel<KIND, EPT, MG, CHV>);     \
         break;
         G4_CASE(1) G4_CASE(2) G4_CASE(3) G4_CASE(4) G4_CASE(5) G4_CASE(6) G4_CASE(7)
+        G4_CASE(8) G4_CASE(16) G4_CASE(24) G4_CASE(32) G4_CASE(40) G4_CASE(48) G4_CASE(56)
 #undef G4_CASE
         default:
             return hipErrorInvalidValue;
