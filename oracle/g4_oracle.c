@@ -28,6 +28,14 @@
  *       (no direct contraction):
  *       T = - sum_s G_{-s}(K2,K1) G_s(K1+Q,K2+Q)
  *
+ * and the singlet and triplet (S_z = 0) projections of the PP up-down pair,
+ * with the pair operators (c+_{K,up} c+_{Q-K,dn} -/+ c+_{K,dn} c+_{Q-K,up})/sqrt(2):
+ *
+ *   PP singlet  T = 1/2 sum_s [ G_s(Q-K2,Q-K1) G_{-s}(K2,K1) + G_s(Q-K2,K1) G_{-s}(K2,Q-K1) ]
+ *   PP triplet  T = 1/2 sum_s [ G_s(Q-K2,Q-K1) G_{-s}(K2,K1) - G_s(Q-K2,K1) G_{-s}(K2,Q-K1) ]
+ *
+ * (singlet + triplet = PP up-down, Eq. (1)).
+ *
  * The PP term is the paper's Eq. (1) (Background section, "Memory-Bound Issue
  * in DCA++") with K3 read as the transfer Q.  The particle-hole terms are the
  * direct-minus-exchange Wick contractions of c+_{K1+Q,s1} c_{K1,s1}
@@ -73,7 +81,8 @@ typedef struct {
 
 enum {
     ORACLE_PH_MAGNETIC = 1, ORACLE_PH_CHARGE = 2, ORACLE_PP_UPDOWN = 4,
-    ORACLE_PH_LONG_UPUP = 8, ORACLE_PH_LONG_UPDOWN = 16, ORACLE_PH_TRANSVERSE = 32
+    ORACLE_PH_LONG_UPUP = 8, ORACLE_PH_LONG_UPDOWN = 16, ORACLE_PH_TRANSVERSE = 32,
+    ORACLE_PP_SINGLET = 64, ORACLE_PP_TRIPLET = 128
 };
 
 typedef struct { double re, im; } cplx;
@@ -155,12 +164,19 @@ static cplx entry_term(const oracle_shape *s, int channel, const double *gu, con
             cplx zero = {0.0, 0.0};
             t = c_sub(zero, c_add(ex_du, ex_ud));
         }
-    } else if (channel == ORACLE_PP_UPDOWN) {
+    } else if (channel == ORACLE_PP_UPDOWN || channel == ORACLE_PP_SINGLET || channel == ORACLE_PP_TRIPLET) {
         long r_qk1 = g_index(s, mom_sub(s, q, k1), m - n1 - 1); /* Q - K1 */
         long r_qk2 = g_index(s, mom_sub(s, q, k2), m - n2 - 1); /* Q - K2 */
         cplx up = c_mul(g_at(gu, ng, r_qk2, r_qk1), g_at(gd, ng, r_k2, r_k1));
         cplx dn = c_mul(g_at(gd, ng, r_qk2, r_qk1), g_at(gu, ng, r_k2, r_k1));
         t = c_add(up, dn);
+        if (channel != ORACLE_PP_UPDOWN) {
+            cplx crossed = c_add(c_mul(g_at(gu, ng, r_qk2, r_k1), g_at(gd, ng, r_k2, r_qk1)),
+                                 c_mul(g_at(gd, ng, r_qk2, r_k1), g_at(gu, ng, r_k2, r_qk1)));
+            cplx sum = channel == ORACLE_PP_SINGLET ? c_add(t, crossed) : c_sub(t, crossed);
+            t.re = 0.5 * sum.re;
+            t.im = 0.5 * sum.im;
+        }
     }
     return t;
 }
@@ -173,7 +189,8 @@ static int check_shape(const oracle_shape *s, int channel) {
     for (int i = 0; i < s->nq; ++i)
         if (s->q_list[i] < 0 || s->q_list[i] >= s->lx * s->ly) return -1;
     if (channel != ORACLE_PH_MAGNETIC && channel != ORACLE_PH_CHARGE && channel != ORACLE_PP_UPDOWN &&
-        channel != ORACLE_PH_LONG_UPUP && channel != ORACLE_PH_LONG_UPDOWN && channel != ORACLE_PH_TRANSVERSE)
+        channel != ORACLE_PH_LONG_UPUP && channel != ORACLE_PH_LONG_UPDOWN && channel != ORACLE_PH_TRANSVERSE &&
+        channel != ORACLE_PP_SINGLET && channel != ORACLE_PP_TRIPLET)
         return -1;
     return 0;
 }

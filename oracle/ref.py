@@ -15,6 +15,8 @@ PP_UPDOWN = 4
 PH_LONG_UPUP = 8
 PH_LONG_UPDOWN = 16
 PH_TRANSVERSE = 32
+PP_SINGLET = 64
+PP_TRIPLET = 128
 
 
 class _Shape(ctypes.Structure):

@@ -8,7 +8,7 @@ definition
 
 (PH magnetic/charge: direct minus exchange Wick terms; the spin-resolved PH
 channels: longitudinal up-up, longitudinal up-down, transverse; PP: the
-paper's Eq. (1) with K3 -> Q), the G elements being regenerated one by one from their
+paper's Eq. (1) with K3 -> Q, and its singlet and triplet projections), the G elements being regenerated one by one from their
 Philox counters by the seeded input generator.  Index arithmetic is done on
 cluster coordinates and integer Matsubara labels, as in the C oracle: momenta
 add coordinate-wise modulo the cluster, w_n + nu_m = w_{n+m},
@@ -26,6 +26,8 @@ PP_UPDOWN = 4
 PH_LONG_UPUP = 8
 PH_LONG_UPDOWN = 16
 PH_TRANSVERSE = 32
+PP_SINGLET = 64
+PP_TRIPLET = 128
 
 
 def _mom_add(w: Workload, k, q):
@@ -104,6 +106,17 @@ def entries(w: Workload, channel: int, idx, b0: int = 0, count: int = None,
             t = (g_elements(w, b, 0, r_qk2, r_qk1) * g_elements(w, b, 1, r_k2, r_k1)
                  + g_elements(w, b, 1, r_qk2, r_qk1) * g_elements(w, b, 0, r_k2, r_k1))
             out += sign[j] * t
+    elif channel in (PP_SINGLET, PP_TRIPLET):
+        r_qk1 = _g_index(w, _mom_sub(w, q, k1), m - n1 - 1)
+        r_qk2 = _g_index(w, _mom_sub(w, q, k2), m - n2 - 1)
+        pm = 1.0 if channel == PP_SINGLET else -1.0
+        for j in range(count):
+            b = b0 + j
+            same = (g_elements(w, b, 0, r_qk2, r_qk1) * g_elements(w, b, 1, r_k2, r_k1)
+                    + g_elements(w, b, 1, r_qk2, r_qk1) * g_elements(w, b, 0, r_k2, r_k1))
+            crossed = (g_elements(w, b, 0, r_qk2, r_k1) * g_elements(w, b, 1, r_k2, r_qk1)
+                       + g_elements(w, b, 1, r_qk2, r_k1) * g_elements(w, b, 0, r_k2, r_qk1))
+            out += sign[j] * 0.5 * (same + pm * crossed)
     else:
         raise ValueError("unknown channel")
     return out

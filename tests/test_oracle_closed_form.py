@@ -9,6 +9,9 @@ and Wick's theorem reduces every channel to products of g:
   PH up-up     S [ delta_{Q,0} g_u(K1) g_u(K2) - delta_{K1,K2} g_u(K1) g_u(K1+Q) ]
   PH up-down   S   delta_{Q,0} g_u(K1) g_d(K2)
   PH transv.  -S   delta_{K1,K2} [ g_u(K1) g_d(K1+Q) + g_d(K1) g_u(K1+Q) ]
+  PP singlet / triplet  S/2 [ delta_{K1,K2} sum_s g_s(Q-K1) g_{-s}(K1)
+                              +/- delta_{K2,Q-K1} sum_s g_s(K1) g_{-s}(Q-K1) ]
+    (the second term where Q-K1 lies in the G4 frequency range)
 
 with S the sum of the measurement signs.  Here g is evaluated from physical
 momenta and Matsubara frequencies in floating point (k+q as a vector,
@@ -81,6 +84,15 @@ def closed_form(w, channel, h, S):
                 out[p] += np.outer(gd, gu)   # [K2][K1] = g_d(K2) g_u(K1)
         elif channel == ref.PH_TRANSVERSE:
             out[p][K, K] -= gu * gd_q + gd * gu_q
+        elif channel in (ref.PP_SINGLET, ref.PP_TRIPLET):
+            pm = 1.0 if channel == ref.PP_SINGLET else -1.0
+            out[p][K, K] += 0.5 * (gu_r * gd + gd_r * gu)
+            # K2 = Q - K1: momentum q - k1 (lattice coordinates), label m - n1 - 1
+            k2 = ((q % w.lx - k % w.lx) % w.lx) + w.lx * ((q // w.lx - k // w.lx) % w.ly)
+            n2 = m - n - 1
+            ok = (n2 >= -(w.nw // 2)) & (n2 < w.nw // 2)
+            K2 = k2 * w.nw + n2 + w.nw // 2
+            out[p][K2[ok], K[ok]] += pm * 0.5 * (gu * gd_r + gd * gu_r)[ok]
         else:
             out[p][K, K] += gu_r * gd + gd_r * gu
     return S * out
@@ -99,7 +111,7 @@ SHAPES = [
 
 @pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
 @pytest.mark.parametrize("channel", [ref.PH_MAGNETIC, ref.PH_CHARGE, ref.PP_UPDOWN, ref.PH_LONG_UPUP,
-                                     ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE])
+                                     ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE, ref.PP_SINGLET, ref.PP_TRIPLET])
 @pytest.mark.parametrize("h", [0.0, 0.25])
 def test_noninteracting_closed_form(w, channel, h):
     gu = np.diag(diag_g(w, +1, h))

@@ -72,6 +72,18 @@ MUTANTS = {
         "cplx ex_du = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));"),
     "transverse sign": (
         "t = c_sub(zero, c_add(ex_du, ex_ud));", "t = c_add(zero, c_add(ex_du, ex_ud));"),
+    # PP singlet / triplet
+    "PP crossed term with Q-K1 for K1": (
+        "c_mul(g_at(gu, ng, r_qk2, r_k1), g_at(gd, ng, r_k2, r_qk1))",
+        "c_mul(g_at(gu, ng, r_qk2, r_qk1), g_at(gd, ng, r_k2, r_qk1))"),
+    "PP crossed term with equal spins": (
+        "c_mul(g_at(gd, ng, r_qk2, r_k1), g_at(gu, ng, r_k2, r_qk1))",
+        "c_mul(g_at(gu, ng, r_qk2, r_k1), g_at(gu, ng, r_k2, r_qk1))"),
+    "PP singlet and triplet swapped": (
+        "cplx sum = channel == ORACLE_PP_SINGLET ? c_add(t, crossed) : c_sub(t, crossed);",
+        "cplx sum = channel == ORACLE_PP_SINGLET ? c_sub(t, crossed) : c_add(t, crossed);"),
+    "PP projection without the 1/2": (
+        "t.re = 0.5 * sum.re;", "t.re = sum.re;"),
     # G_sigma from an expansion configuration
     "G_sigma: conjugate phase on the left factor": (
         "const cplx ea = {cos(tha), sin(tha)};", "const cplx ea = {cos(tha), -sin(tha)};"),

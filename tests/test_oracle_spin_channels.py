@@ -1,4 +1,5 @@
-"""Pins of the oracle's spin-resolved particle-hole channels.
+"""Pins of the oracle's channel variants: the spin-resolved particle-hole
+channels and the singlet / triplet projections of the particle-particle one.
 
 Longitudinal up-up, longitudinal up-down and transverse are separate code in
 the oracle.  Besides the brute-force Wick contraction and the noninteracting
@@ -13,6 +14,8 @@ magnetic and charge channels, whose code they share nothing with:
 - no down spin (Gd = 0): up-down and transverse vanish exactly, up-up is
   the magnetic channel of the same input;
 - transverse is symmetric under the spin swap, bit for bit;
+- PP singlet + PP triplet = PP up-down (Eq. (1)), and the two differ (the
+  crossed term is not zero);
 - the per-entry numpy oracle (regenerated inputs) agrees with the C one.
 """
 import numpy as np
@@ -24,7 +27,7 @@ from synth import Workload, g_matrices, signs
 
 W = Workload("spin", lx=3, ly=2, nw=4, nwex=3, nq=6, q_begin=2, q_end=16, beta=6.0, seed=31, wid=31,
              measurements=3)
-SPIN = [ref.PH_LONG_UPUP, ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE]
+SPIN = [ref.PH_LONG_UPUP, ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE, ref.PP_SINGLET, ref.PP_TRIPLET]
 
 
 def inputs(w, count):
@@ -65,6 +68,15 @@ def test_transverse_spin_swap_is_exact():
     a = ref.accumulate(W, ref.PH_TRANSVERSE, gu, gd, s)
     b = ref.accumulate(W, ref.PH_TRANSVERSE, gd, gu, s)
     assert np.array_equal(a, b)
+
+
+def test_singlet_and_triplet_sum_to_eq1():
+    gu, gd, s = inputs(W, 3)
+    st = ref.accumulate(W, ref.PP_SINGLET, gu, gd, s)
+    tt = ref.accumulate(W, ref.PP_TRIPLET, gu, gd, s)
+    pp = ref.accumulate(W, ref.PP_UPDOWN, gu, gd, s)
+    assert rel_fro(st + tt, pp) < 1e-15
+    assert rel_fro(st, tt) > 0.1
 
 
 @pytest.mark.parametrize("channel", SPIN)

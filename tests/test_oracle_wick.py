@@ -14,6 +14,8 @@ The channels are the operator strings
   PH long. up-up     < c+_{K1+Q,u} c_{K1,u} c+_{K2,u} c_{K2+Q,u} >
   PH long. up-down   < c+_{K1+Q,u} c_{K1,u} c+_{K2,d} c_{K2+Q,d} >
   PH transverse      sum_s < c+_{K1+Q,s} c_{K1,-s} c+_{K2,-s} c_{K2+Q,s} >
+  PP singlet / triplet  < P+(K2) P(K1) > with the pair operator
+                     P+(K) = (c+_{K,u} c+_{Q-K,d} -/+ c+_{K,d} c+_{Q-K,u}) / sqrt(2)
 
 This test enumerates every tuple of G-window indices, keeps the tuples whose
 momenta and Matsubara frequencies are conserved (checked on physical values:
@@ -100,6 +102,19 @@ def ph_strings(channel):
     return [((s, 1 - s, 1 - s, s), 1.0) for s in (0, 1)]      # transverse
 
 
+def pp_strings(channel):
+    """Spins of c+_{K2} c+_{Q-K2} c_{Q-K1} c_{K1} and the weight of each string."""
+    if channel == ref.PP_UPDOWN:
+        return [((1 - s, s, s, 1 - s), 1.0) for s in (0, 1)]
+    # P+(K2) = sum_a ca c+_{K2,sa} c+_{Q-K2,-sa};  P(K1) = sum_b cb c_{Q-K1,-sb} c_{K1,sb}
+    sgn = -1.0 if channel == ref.PP_SINGLET else 1.0
+    terms = []
+    for sa, ca in ((0, 1.0), (1, sgn)):
+        for sb, cb in ((0, 1.0), (1, sgn)):
+            terms.append(((sa, 1 - sa, 1 - sb, sb), 0.5 * ca * cb))
+    return terms
+
+
 def brute_force(w, channel, Gs, sgn):
     P = [physical(w, r) for r in range(w.ng)]
     out = np.zeros((w.planes, w.n, w.n), dtype=np.complex128)
@@ -140,10 +155,10 @@ def brute_force(w, channel, Gs, sgn):
             for (A, B), (D, C) in itertools.product(pairs[p], pairs[p]):
                 K2, K1 = g4_index(w, A), g4_index(w, D)
                 v = 0j
-                for s in (0, 1):
+                for (a1, a2, a3, a4), wt in pp_strings(channel):
                     for b, sg in enumerate(sgn):
-                        v += sg * wick([(True, A, 1 - s), (True, B, s), (False, C, s),
-                                        (False, D, 1 - s)], Gs[b])
+                        v += sg * wt * wick([(True, A, a1), (True, B, a2), (False, C, a3),
+                                             (False, D, a4)], Gs[b])
                 out[p, K2, K1] += v
                 hits[p, K2, K1] += 1
     return out, hits
@@ -158,7 +173,7 @@ SHAPES = [
 
 @pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
 @pytest.mark.parametrize("channel", [ref.PH_MAGNETIC, ref.PH_CHARGE, ref.PP_UPDOWN, ref.PH_LONG_UPUP,
-                                     ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE])
+                                     ref.PH_LONG_UPDOWN, ref.PH_TRANSVERSE, ref.PP_SINGLET, ref.PP_TRIPLET])
 def test_brute_force_wick(w, channel):
     rng = np.random.default_rng(11 + channel)
     sgn = np.array([1.0, -1.0])
