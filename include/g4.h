@@ -41,11 +41,16 @@
  *   PH transverse            G4 += -s_b  sum_s G_{-s}(K2,K1) G_s(K1+Q,K2+Q)
  *     (spins (s, -s, -s, s) summed over s)
  * (magnetic = uu + dd - ud - du and charge = uu + dd + ud + du, with dd, du
- * the up-up and up-down channels of the spin-swapped pair).
+ * the up-up and up-down channels of the spin-swapped pair), and the singlet
+ * and triplet (S_z = 0) projections of the PP pair, with pair operators
+ * (c+_{K,up} c+_{Q-K,dn} -/+ c+_{K,dn} c+_{Q-K,up})/sqrt(2):
+ *   PP singlet   G4 += s_b/2 sum_s [ G_s(Q-K2,Q-K1) G_{-s}(K2,K1) + G_s(Q-K2,K1) G_{-s}(K2,Q-K1) ]
+ *   PP triplet   G4 += s_b/2 sum_s [ G_s(Q-K2,Q-K1) G_{-s}(K2,K1) - G_s(Q-K2,K1) G_{-s}(K2,Q-K1) ]
+ *   (singlet + triplet = PP up-down).
  * A slice holds channels of one family: a subset of {G4_PH_MAGNETIC,
- * G4_PH_CHARGE, G4_PP_UPDOWN} or of {G4_PH_LONG_UPUP, G4_PH_LONG_UPDOWN,
- * G4_PH_TRANSVERSE}; the spin-resolved ones run on the register-staged
- * (VALU) kernels.
+ * G4_PH_CHARGE, G4_PP_UPDOWN}, of {G4_PH_LONG_UPUP, G4_PH_LONG_UPDOWN,
+ * G4_PH_TRANSVERSE}, or of {G4_PP_SINGLET, G4_PP_TRIPLET}; the last two
+ * families run on the register-staged (VALU) kernels.
  * The values kept are raw signed sums; g4_stats gives the measurement count
  * and the sum of weights for normalisation.
  *
@@ -80,11 +85,12 @@ enum {
     G4_E_UNSUPPORTED = -5   /* valid request this build does not implement */
 };
 
-/* channels (bitmask); accumulator slot 0: magnetic or up-up, 1: charge or
- * up-down, 2: PP or transverse */
+/* channels (bitmask); accumulator slot 0: magnetic, up-up or PP singlet,
+ * 1: charge, up-down or PP triplet, 2: PP or transverse */
 enum {
     G4_PH_MAGNETIC = 1, G4_PH_CHARGE = 2, G4_PP_UPDOWN = 4,
-    G4_PH_LONG_UPUP = 8, G4_PH_LONG_UPDOWN = 16, G4_PH_TRANSVERSE = 32
+    G4_PH_LONG_UPUP = 8, G4_PH_LONG_UPDOWN = 16, G4_PH_TRANSVERSE = 32,
+    G4_PP_SINGLET = 64, G4_PP_TRIPLET = 128
 };
 
 /* element type of the G_up / G_dn buffers passed to g4_accumulate */
@@ -170,8 +176,9 @@ typedef struct g4_config {
                                  copied by g4_init_slice */
     int64_t q_begin, q_end;   /* slice planes, 0 <= q_begin < q_end <= nq*nwex */
     uint32_t channels;        /* nonzero bitmask of G4_PH_MAGNETIC | G4_PH_CHARGE | G4_PP_UPDOWN,
-                                 or of G4_PH_LONG_UPUP | G4_PH_LONG_UPDOWN | G4_PH_TRANSVERSE
-                                 (not both families; the second on the VALU kernels only) */
+                                 of G4_PH_LONG_UPUP | G4_PH_LONG_UPDOWN | G4_PH_TRANSVERSE, or
+                                 of G4_PP_SINGLET | G4_PP_TRIPLET (one family; the last two on
+                                 the VALU kernels only) */
     int32_t g_in;             /* G4_IN_* */
     int32_t prod;             /* G4_PROD_* ; G4_MODE_PLAIN requires G4_PROD_F64 */
     int32_t acc;              /* G4_ACC_* */
@@ -344,8 +351,9 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
  *     batched with G4_PROD_F64 or G4_PROD_F32 (complex64 G for FP32); no
  *     G4_F_* flags (G4_E_UNSUPPORTED otherwise).
  *   acc_mag, acc_chg, acc_pp: DEVICE accumulators of slots 0, 1, 2, one per
- *     channel in cfg->channels (slot 0: magnetic or up-up, 1: charge or
- *     up-down, 2: PP or transverse; NULL for absent ones), each entries x 16 bytes (G4_ACC_C128,
+ *     channel in cfg->channels (slot 0: magnetic, up-up or PP singlet; 1:
+ *     charge, up-down or PP triplet; 2: PP or transverse; NULL for absent
+ *     ones), each entries x 16 bytes (G4_ACC_C128,
  *     G4_ACC_C64_KAHAN) or x 8 bytes (G4_ACC_C64), in the library's device
  *     layout [plane][k2][k1][i2][i1] (K = k*nw + i), which g4_readback
  *     translates for a slice; the caller zeroes them before the first call.

@@ -105,9 +105,12 @@ int validate(const g4_config *c, Plan *p) {
     if (c->q_begin < 0 || c->q_end > nQ || c->q_begin >= c->q_end)
         return fail(G4_E_ARG, "slice [%lld, %lld) not inside [0, %lld)", (long long)c->q_begin,
                     (long long)c->q_end, (long long)nQ);
+    // channel families: {1, 2, 4}, {8, 16, 32} (spin-resolved PH), {64, 128} (PP singlet / triplet)
     const bool spin_set = (c->channels & ~7u) != 0;
-    if (c->channels == 0 || (c->channels & ~63u) || (spin_set && (c->channels & 7u)))
-        return fail(G4_E_ARG, "channels bitmask 0x%x invalid (one family: bits 1|2|4 or 8|16|32)", c->channels);
+    const int families = ((c->channels & 7u) ? 1 : 0) + ((c->channels & 56u) ? 1 : 0) + ((c->channels & 192u) ? 1 : 0);
+    if (c->channels == 0 || (c->channels & ~255u) || families != 1)
+        return fail(G4_E_ARG, "channels bitmask 0x%x invalid (one family: bits of 1|2|4, 8|16|32 or 64|128)",
+                    c->channels);
     if (c->g_in != G4_IN_C128 && c->g_in != G4_IN_C64) return fail(G4_E_ARG, "g_in=%d", c->g_in);
     if (c->prod < G4_PROD_F64 || c->prod > G4_PROD_F16X2) return fail(G4_E_ARG, "prod=%d", c->prod);
     if (c->acc < G4_ACC_C128 || c->acc > G4_ACC_C64) return fail(G4_E_ARG, "acc=%d", c->acc);
@@ -164,8 +167,8 @@ int validate(const g4_config *c, Plan *p) {
               : (c->flags & G4_F_PACKED) ? G4_VARIANT_PACKED
               : (c->flags & G4_F_PACKED_DEEP) ? G4_VARIANT_PACKED_DEEP : G4_VARIANT_VALU;
     if (spin_set && (P.variant != G4_VARIANT_VALU || P.split))
-        return fail(G4_E_UNSUPPORTED, "spin-resolved channels run on the VALU kernels only (no G4_F_MFMA, "
-                                      "G4_F_PACKED, G4_F_PACKED_DEEP or split products)");
+        return fail(G4_E_UNSUPPORTED, "spin-resolved and PP singlet / triplet channels run on the VALU kernels "
+                                      "only (no G4_F_MFMA, G4_F_PACKED, G4_F_PACKED_DEEP or split products)");
     // split-precision plans run the packed kernels (their direct vectors can be
     // read as zeros there, with no test in the arithmetic loop)
     if (P.split && P.variant == G4_VARIANT_VALU) P.variant = G4_VARIANT_PACKED;
@@ -463,8 +466,8 @@ int usable(g4_slice *h) {
 
 int channel_slot(uint32_t channel) {
     switch (channel) {
-        case G4_PH_MAGNETIC: case G4_PH_LONG_UPUP: return 0;
-        case G4_PH_CHARGE: case G4_PH_LONG_UPDOWN: return 1;
+        case G4_PH_MAGNETIC: case G4_PH_LONG_UPUP: case G4_PP_SINGLET: return 0;
+        case G4_PH_CHARGE: case G4_PH_LONG_UPDOWN: case G4_PP_TRIPLET: return 1;
         case G4_PP_UPDOWN: case G4_PH_TRANSVERSE: return 2;
         default: return -1;
     }
@@ -1317,7 +1320,7 @@ int make_sample(g4_slice *h, const void *gu, const void *gd, const double *sign,
         ra.g_stride = (int64_t)h->P.d.ng * h->P.d.ng;
         ra.sign = ts.sign_dev;
         ra.batch = nb;
-        ra.channel = (int)h->cfg.channels & (9 << c);   // the slice's channel in slot c
+        ra.channel = (int)h->cfg.channels & (73 << c);   // the slice's channel in slot c
         ra.idx = ts.idx_dev;
         ra.count = (int64_t)ns;
         ra.out = ts.vals_dev;

@@ -55,13 +55,16 @@ inline hipError_t ensure_lds_limit(const void *fn, size_t lds) {
     if (e == hipSuccess) done[{fn, dev}] = lds;
     return e;
 }
-enum { CH_MAG = 1, CH_CHG = 2, CH_PP = 4, CH_UU = 8, CH_UD = 16, CH_TR = 32 };
-// Accumulator slot of each channel bit (0 magnetic / up-up, 1 charge /
-// up-down, 2 PP / transverse) and the slots a channel set occupies.
+enum { CH_MAG = 1, CH_CHG = 2, CH_PP = 4, CH_UU = 8, CH_UD = 16, CH_TR = 32, CH_PS = 64, CH_PT = 128 };
+// Accumulator slot of each channel bit (0 magnetic / up-up / PP singlet,
+// 1 charge / up-down / PP triplet, 2 PP / transverse) and the slots a channel
+// set occupies.
 __host__ __device__ constexpr int acc_slot_of(int ch) {
-    return (ch & (CH_MAG | CH_UU)) ? 0 : (ch & (CH_CHG | CH_UD)) ? 1 : 2;
+    return (ch & (CH_MAG | CH_UU | CH_PS)) ? 0 : (ch & (CH_CHG | CH_UD | CH_PT)) ? 1 : 2;
 }
-__host__ __device__ constexpr int acc_slots(int channels) { return (channels | (channels >> 3)) & 7; }
+__host__ __device__ constexpr int acc_slots(int channels) {
+    return (channels | (channels >> 3) | (channels >> 6)) & 7;
+}
 // Direct-vector recipes (GatherArgs::slots bits), in slot order:
 // bit 0 magnetic a = s(Gu-Gd), b = Gu-Gd; bit 1 charge (sums); bit 2 up-up
 // a = s Gu, b = Gu; bit 3 up-down a = s Gu, b = Gd.
@@ -202,9 +205,12 @@ inline size_t update_lds_bytes(int kind, int channels, int tile, int mgroup, con
     const int T2 = tile < d.nw ? tile : d.nw;
     const int nph = __builtin_popcount(direct_recipes(channels));
     const bool ex = (channels & (CH_MAG | CH_CHG | CH_UU | CH_TR)) != 0;
+    const bool pair = (channels & (CH_PS | CH_PT)) != 0;
     size_t pairs = (size_t)T2 * d.nw;
     if (ex) pairs += (size_t)(d.nw + mgroup - 1) * (T2 + mgroup - 1);
-    if (channels & CH_PP) pairs += (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
+    if ((channels & CH_PP) || pair) pairs += (size_t)(T2 + mgroup - 1) * (d.nw + mgroup - 1);
+    // singlet / triplet: G(Q-K2, K1) and G(K2, Q-K1) blocks
+    if (pair) pairs += (size_t)(T2 + mgroup - 1) * d.nw + (size_t)T2 * (d.nw + mgroup - 1);
     const size_t vecs = (size_t)nph * mgroup * (d.nw + T2) * (variant == 1 ? 2 : 1);
     return pairs * 2 * el + vecs * el;
 }

@@ -293,13 +293,20 @@ __global__ void ref_entries_kernel(RefArgs a) {
         for (int b = 0; b < a.batch; ++b) {
             const int64_t base = (int64_t)b * a.g_stride;
             double2 t;
-            if (a.channel == CH_PP) {
+            if (a.channel == CH_PP || a.channel == CH_PS || a.channel == CH_PT) {
                 // Q-K: momentum q-k, local frequency m + nw - 1 - i
                 const int64_t s1 = (int64_t)a.t.ksub[q * nc + k1] * nwg + (m + nw - 1 - i1);
                 const int64_t s2 = (int64_t)a.t.ksub[q * nc + k2] * nwg + (m + nw - 1 - i2);
                 const double2 up = zmul(ref_g(a.gu, a.g_in, base + s2 * ng + s1), ref_g(a.gd, a.g_in, base + r2 * ng + r1));
                 const double2 dn = zmul(ref_g(a.gd, a.g_in, base + s2 * ng + s1), ref_g(a.gu, a.g_in, base + r2 * ng + r1));
                 t = double2{up.x + dn.x, up.y + dn.y};
+                if (a.channel != CH_PP) {
+                    // crossed: sum_s G_s(Q-K2, K1) G_-s(K2, Q-K1); singlet (t + c)/2, triplet (t - c)/2
+                    const double2 c1 = zmul(ref_g(a.gu, a.g_in, base + s2 * ng + r1), ref_g(a.gd, a.g_in, base + r2 * ng + s1));
+                    const double2 c2 = zmul(ref_g(a.gd, a.g_in, base + s2 * ng + r1), ref_g(a.gu, a.g_in, base + r2 * ng + s1));
+                    const double pm = a.channel == CH_PS ? 1.0 : -1.0;
+                    t = double2{0.5 * (t.x + pm * (c1.x + c2.x)), 0.5 * (t.y + pm * (c1.y + c2.y))};
+                }
             } else {
                 // K+Q: momentum k+q, local frequency i + m
                 const int64_t p1 = (int64_t)a.t.kadd[k1 * nc + q] * nwg + i1 + m;

@@ -146,8 +146,9 @@ constexpr int NT = 256;   // threads per block
 constexpr int SX = 32;    // staging lanes along a G row
 constexpr int SY = NT / SX;
 
-// Channel set CH: magnetic / charge / PP, or the spin-resolved PH channels
-// (longitudinal up-up, up-down, transverse; VALU kernel only).  Register
+// Channel set CH: magnetic / charge / PP, the spin-resolved PH channels
+// (longitudinal up-up, up-down, transverse), or the PP singlet / triplet
+// projections (the last two families on the VALU kernel only).  Register
 // accumulators are numbered in bit order; direct-vector slots likewise over
 // the channels with a direct term.
 template <int CH>
@@ -158,15 +159,19 @@ struct ChanInfo {
     static constexpr bool uu = (CH & CH_UU) != 0;
     static constexpr bool ud = (CH & CH_UD) != 0;
     static constexpr bool tr = (CH & CH_TR) != 0;
+    static constexpr bool ps = (CH & CH_PS) != 0;
+    static constexpr bool pt = (CH & CH_PT) != 0;
+    static constexpr bool pair = ps || pt;                  // needs the crossed PP blocks
     static constexpr bool ph = mag || chg || uu || ud || tr;
     static constexpr bool ex = mag || chg || uu || tr;      // needs the exchange block
     static constexpr int count = (mag ? 1 : 0) + (chg ? 1 : 0) + (pp ? 1 : 0) + (uu ? 1 : 0) + (ud ? 1 : 0) +
-                                 (tr ? 1 : 0);
+                                 (tr ? 1 : 0) + (ps ? 1 : 0) + (pt ? 1 : 0);
     static constexpr int nph = (mag ? 1 : 0) + (chg ? 1 : 0) + (uu ? 1 : 0) + (ud ? 1 : 0);
     static constexpr int slot_chg = mag ? 1 : 0;
     static constexpr int slot_pp = (mag ? 1 : 0) + (chg ? 1 : 0);
     static constexpr int slot_ud = uu ? 1 : 0;
     static constexpr int slot_tr = (uu ? 1 : 0) + (ud ? 1 : 0);
+    static constexpr int slot_pt = ps ? 1 : 0;
 };
 
 // Kind: 0 plain FP64 (one measurement, c128 accumulator, prefetched);
@@ -189,6 +194,8 @@ constexpr int NSV = 4;
 //      K1 read consecutive words);
 //   Z  PP block, rows q-k2, columns q-k1, row-major (descending runs);
 //   X  G(K2, K1) rows of the tile, row-major;
+//   W  (PP singlet / triplet) G(Q-K2, K1): the PP block's rows, the K1 columns;
+//   U  (PP singlet / triplet) G(K2, Q-K1): the tile's rows, the PP block's columns;
 //   A  a(Q, K1) per PH channel and plane; Bv b(Q, K2) per channel, plane, row.
 // FP32 spin pairs (16 bytes) sit side by side and are read with one 16-byte
 // access; FP64 values are kept in two planes so that consecutive lanes stay
@@ -197,7 +204,7 @@ template <typename V, typename CI, int NSG, int NVB>
 struct Tile {
     int nw, nwg, nc, n, planes, ng;
     int q, m_lo, M, p0, k1, k2, c0, T2;
-    int yr, yc, zr, zc, nY, nZ, nX, nG, nA, nB, nV;
+    int yr, yc, zr, zc, nY, nZ, nX, nW, nU, nG, nA, nB, nV;
     int rowY, colY, rowZ, colZ, rowX, colX;
     V *Gp, *Vt;
     const V *dA, *dB;
@@ -224,9 +231,11 @@ struct Tile {
         yr = nw + M - 1; yc = T2 + M - 1;
         zr = T2 + M - 1; zc = nw + M - 1;
         nY = CI::ex ? yr * yc : 0;
-        nZ = CI::pp ? zr * zc : 0;
+        nZ = (CI::pp || CI::pair) ? zr * zc : 0;
         nX = T2 * nw;
-        nG = nY + nZ + nX;
+        nW = CI::pair ? zr * nw : 0;
+        nU = CI::pair ? T2 * zc : 0;
+        nG = nY + nZ + nX + nW + nU;
         nA = CI::nph * M * nw;
         nB = CI::nph * M * T2;
         nV = nA + nB;
@@ -234,8 +243,8 @@ struct Tile {
         Vt = Gp + 2 * nG;
         rowY = CI::ex ? a.t.kadd[k1 * nc + q] * nwg + m_lo : 0;
         colY = CI::ex ? a.t.kadd[k2 * nc + q] * nwg + c0 + m_lo : 0;
-        rowZ = CI::pp ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
-        colZ = CI::pp ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
+        rowZ = (CI::pp || CI::pair) ? a.t.ksub[q * nc + k2] * nwg + m_lo + nw - c0 - T2 : 0;
+        colZ = (CI::pp || CI::pair) ? a.t.ksub[q * nc + k1] * nwg + m_lo : 0;
         rowX = k2 * nwg + c0;
         colX = k1 * nwg;
         dA = static_cast<const V *>(a.dir_a);
@@ -264,11 +273,21 @@ struct Tile {
             const int r = f / zc, c = f - r * zc;
             goff = (rowZ + r) * ng + colZ + c;
             loff = nY + f;
-        } else {
+        } else if (e < nY + nZ + nX) {
             const int f = e - nY - nZ;
             const int r = f / nw, c = f - r * nw;
             goff = (rowX + r) * ng + colX + c;
             loff = nY + nZ + f;
+        } else if (e < nY + nZ + nX + nW) {
+            const int f = e - nY - nZ - nX;          // W: rows of Q-K2, columns K1
+            const int r = f / nw, c = f - r * nw;
+            goff = (rowZ + r) * ng + colX + c;
+            loff = nY + nZ + nX + f;
+        } else {
+            const int f = e - nY - nZ - nX - nW;     // U: rows K2, columns of Q-K1
+            const int r = f / zc, c = f - r * zc;
+            goff = (rowX + r) * ng + colZ + c;
+            loff = nY + nZ + nX + nW + f;
         }
     }
     // element e of the staged direct vectors -> (offset at b = 0, LDS offset)
@@ -340,6 +359,16 @@ struct Tile {
         u = ld(Gp + pu(i));
         d = ld(Gp + pd(i));
     }
+    __device__ __forceinline__ void w_at(int i2l, int i1, int m, V &u, V &d) const {
+        const int i = nY + nZ + nX + (m + T2 - 1 - i2l) * nw + i1;
+        u = ld(Gp + pu(i));
+        d = ld(Gp + pd(i));
+    }
+    __device__ __forceinline__ void u_at(int i2l, int i1, int m, V &u, V &d) const {
+        const int i = nY + nZ + nX + nW + i2l * zc + m + nw - 1 - i1;
+        u = ld(Gp + pu(i));
+        d = ld(Gp + pd(i));
+    }
     // physical accumulator index (tile-contiguous layout, see update_kernel)
     __device__ __forceinline__ int64_t entry(int m, int i2l, int i1) const {
         return (((int64_t)(p0 + m) * nc + k2) * nc + k1) * nw * nw + (int64_t)(c0 + i2l) * nw + i1;
@@ -391,6 +420,8 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
                         if (CI::uu) acc[0][j][m] = acc_ld(static_cast<const V *>(a.acc[0]) + e);
                         if (CI::ud) acc[CI::slot_ud][j][m] = acc_ld(static_cast<const V *>(a.acc[1]) + e);
                         if (CI::tr) acc[CI::slot_tr][j][m] = acc_ld(static_cast<const V *>(a.acc[2]) + e);
+                        if (CI::ps) acc[0][j][m] = acc_ld(static_cast<const V *>(a.acc[0]) + e);
+                        if (CI::pt) acc[CI::slot_pt][j][m] = acc_ld(static_cast<const V *>(a.acc[1]) + e);
                     }
                 });
             });
@@ -422,7 +453,28 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
         });
         auto body = [&](auto j, auto m) __attribute__((always_inline)) {
             const int i2l = r0 + j * RP;
-            if (CI::uu || CI::ud || CI::tr) {
+            if (CI::pair) {
+                // PP singlet / triplet: 1/2 [ s sum_s' G_s'(Q-K2,Q-K1) G_-s'(K2,K1)
+                //                           +/- s sum_s' G_s'(Q-K2,K1) G_-s'(K2,Q-K1) ]
+                // (xu, xd carry +s_b here)
+                V zu, zd, wu, wd, uu_, ud_;
+                t.z_at(i2l, i1, m, zu, zd);
+                t.w_at(i2l, i1, m, wu, wd);
+                t.u_at(i2l, i1, m, uu_, ud_);
+                V same = cmul(zu, xd[j]);
+                cmac(same, zd, xu[j]);
+                V cr = cmul(wu, ud_);
+                cmac(cr, wd, uu_);
+                const R h = (R)0.5, hs = (R)0.5 * s;
+                if (CI::ps) {
+                    acc[0][j][m].x += h * same.x + hs * cr.x;
+                    acc[0][j][m].y += h * same.y + hs * cr.y;
+                }
+                if (CI::pt) {
+                    acc[CI::slot_pt][j][m].x += h * same.x - hs * cr.x;
+                    acc[CI::slot_pt][j][m].y += h * same.y - hs * cr.y;
+                }
+            } else if (CI::uu || CI::ud || CI::tr) {
                 // spin-resolved channels; xu, xd carry -s_b (the exchange sign)
                 V yu{0, 0}, yd{0, 0};
                 if (CI::ex) t.y_at(i2l, i1, m, yu, yd);
@@ -490,6 +542,8 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
                 if (CI::uu) acc_st(static_cast<V *>(a.acc[0]) + e, acc[0][j][m]);
                 if (CI::ud) acc_st(static_cast<V *>(a.acc[1]) + e, acc[CI::slot_ud][j][m]);
                 if (CI::tr) acc_st(static_cast<V *>(a.acc[2]) + e, acc[CI::slot_tr][j][m]);
+                if (CI::ps) acc_st(static_cast<V *>(a.acc[0]) + e, acc[0][j][m]);
+                if (CI::pt) acc_st(static_cast<V *>(a.acc[1]) + e, acc[CI::slot_pt][j][m]);
             } else {
                 if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
                 if (CI::chg) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_chg][j][m]);
@@ -497,6 +551,8 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
                 if (CI::uu) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
                 if (CI::ud) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_ud][j][m]);
                 if (CI::tr) acc_update(a.acc[2], a.acc_kind, e, acc[CI::slot_tr][j][m]);
+                if (CI::ps) acc_update(a.acc[0], a.acc_kind, e, acc[0][j][m]);
+                if (CI::pt) acc_update(a.acc[1], a.acc_kind, e, acc[CI::slot_pt][j][m]);
             }
         });
     });
@@ -635,6 +691,7 @@ hipError_t launch_ch(int channels, int nitems, size_t lds, const UpdateArgs &a, 
         break;
         G4_CASE(1) G4_CASE(2) G4_CASE(3) G4_CASE(4) G4_CASE(5) G4_CASE(6) G4_CASE(7)
         G4_CASE(8) G4_CASE(16) G4_CASE(24) G4_CASE(32) G4_CASE(40) G4_CASE(48) G4_CASE(56)
+        G4_CASE(64) G4_CASE(128) G4_CASE(192)
 #undef G4_CASE
         default:
             return hipErrorInvalidValue;

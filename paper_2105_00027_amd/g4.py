@@ -25,6 +25,7 @@ G4_ABI_VERSION = 1
 G4_OK, G4_E_ARG, G4_E_OOM, G4_E_HIP, G4_E_STATE, G4_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 G4_PH_MAGNETIC, G4_PH_CHARGE, G4_PP_UPDOWN = 1, 2, 4
 G4_PH_LONG_UPUP, G4_PH_LONG_UPDOWN, G4_PH_TRANSVERSE = 8, 16, 32
+G4_PP_SINGLET, G4_PP_TRIPLET = 64, 128
 G4_IN_C128, G4_IN_C64 = 0, 1
 G4_PROD_F64, G4_PROD_F32, G4_PROD_BF16X2, G4_PROD_F16X2 = 0, 1, 2, 3
 G4_ACC_C128, G4_ACC_C64_KAHAN, G4_ACC_C64 = 0, 1, 2

@@ -19,7 +19,8 @@ from . import g4
 
 CHANNELS = {g4.G4_PH_MAGNETIC: "ph_magnetic", g4.G4_PH_CHARGE: "ph_charge", g4.G4_PP_UPDOWN: "pp_updown",
             g4.G4_PH_LONG_UPUP: "ph_long_upup", g4.G4_PH_LONG_UPDOWN: "ph_long_updown",
-            g4.G4_PH_TRANSVERSE: "ph_transverse"}
+            g4.G4_PH_TRANSVERSE: "ph_transverse", g4.G4_PP_SINGLET: "pp_singlet",
+            g4.G4_PP_TRIPLET: "pp_triplet"}
 
 
 def _meta(h: g4.Slice) -> dict:

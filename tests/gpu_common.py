@@ -42,7 +42,7 @@ def run_slice(cfg, gu_dev, gd_dev, sgn, chunks=None):
             g4.g4_accumulate(h, gu_dev[a:b], gd_dev[a:b], sgn[a:b])
         g4.g4_sync(h)
         out = {}
-        for ch in (1, 2, 4, 8, 16, 32):
+        for ch in (1, 2, 4, 8, 16, 32, 64, 128):
             if cfg.c.channels & ch:
                 out[ch] = g4.g4_readback(h, ch).reshape(cfg.planes, cfg.n, cfg.n)
         st = g4.g4_stats(h)

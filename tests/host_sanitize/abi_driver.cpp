@@ -51,7 +51,8 @@ int main() {
         {"nq", [](g4_config &x) { x.nq = 17; }, G4_E_ARG},
         {"empty slice", [](g4_config &x) { x.q_begin = x.q_end = 5; }, G4_E_ARG},
         {"slice end", [](g4_config &x) { x.q_end = 129; }, G4_E_ARG},
-        {"channels", [](g4_config &x) { x.channels = 64; }, G4_E_ARG},
+        {"channels", [](g4_config &x) { x.channels = 256; }, G4_E_ARG},
+        {"PP and singlet families", [](g4_config &x) { x.channels = G4_PP_UPDOWN | G4_PP_SINGLET; }, G4_E_ARG},
         {"mixed channel families", [](g4_config &x) { x.channels = G4_PH_MAGNETIC | G4_PH_LONG_UPUP; }, G4_E_ARG},
         {"spin channels on packed", [](g4_config &x) { x.mode = G4_MODE_BATCHED; x.max_batch = 8; x.prod = G4_PROD_F32;
                                                        x.g_in = G4_IN_C64; x.channels = G4_PH_TRANSVERSE;

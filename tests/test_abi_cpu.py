@@ -56,7 +56,8 @@ BAD = [
     dict(abi_version=7), dict(lx=0), dict(nw=63), dict(nw=0), dict(nwex=0), dict(nq=17),
     dict(q_list=[0, 1, 1] + list(range(3, 16))), dict(q_list=[0] * 15 + [16]),
     dict(q_begin=5, q_end=5), dict(q_end=129), dict(q_begin=-1), dict(channels=0),
-    dict(channels=64), dict(channels=9), dict(channels=7 | 56), dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9), dict(flags=64),
+    dict(channels=256), dict(channels=9), dict(channels=7 | 56), dict(channels=4 | 64), dict(channels=32 | 128),
+    dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9), dict(flags=64),
     dict(device=-1), dict(mode=1, max_batch=0), dict(mode=1, max_batch=257),
     dict(mode=0, prod=1), dict(mode=0, acc=1), dict(mode=1, max_batch=8, prod=0, g_in=1),
     dict(tile=-1),
@@ -121,21 +122,30 @@ def test_packed_rejections():
         assert e.value.code == g4.G4_E_UNSUPPORTED, kw
 
 
-def test_spin_resolved_channels_on_valu_plans_only():
+def test_channel_families_on_valu_plans_only():
     """The spin-resolved family sizes like the standard one (one accumulator
-    per channel, direct vectors for up-up and up-down only) and runs on the
-    VALU kernels: packed, MFMA and split plans are G4_E_UNSUPPORTED."""
+    per channel, direct vectors for up-up and up-down only), the PP singlet /
+    triplet family like PP up-down; both run on the VALU kernels: packed,
+    MFMA and split plans are G4_E_UNSUPPORTED."""
     for ch in (8, 16, 32, 24, 40, 48, 56):
         for kw in (dict(mode=0), dict(mode=1, max_batch=8, prod=0), dict(mode=1, max_batch=8, prod=1, g_in=1)):
             e, b = g4.g4_slice_size(base(channels=ch, **kw))
             std = {8: 1, 16: 2, 32: 4, 24: 3, 40: 5, 48: 6, 56: 7}[ch]
             e0, b0 = g4.g4_slice_size(base(channels=std, **kw))
             assert e == e0 and b == b0, (ch, kw)       # same accumulators, same direct-vector slots
-    for kw in (dict(flags=g4.G4_F_PACKED), dict(flags=g4.G4_F_MFMA), dict(flags=g4.G4_F_PACKED_DEEP),
-               dict(flags=g4.G4_F_PACKED | g4.G4_F_MFMA), dict(prod=2), dict(prod=3)):
-        with pytest.raises(g4.G4Error) as e:
-            g4.g4_slice_size(base(channels=8, mode=1, max_batch=8, **dict(dict(prod=1, g_in=1), **kw)))
-        assert e.value.code == g4.G4_E_UNSUPPORTED, kw
+    for ch in (8, 64):
+        for kw in (dict(flags=g4.G4_F_PACKED), dict(flags=g4.G4_F_MFMA), dict(flags=g4.G4_F_PACKED_DEEP),
+                   dict(flags=g4.G4_F_PACKED | g4.G4_F_MFMA), dict(prod=2), dict(prod=3)):
+            with pytest.raises(g4.G4Error) as e:
+                g4.g4_slice_size(base(channels=ch, mode=1, max_batch=8, **dict(dict(prod=1, g_in=1), **kw)))
+            assert e.value.code == g4.G4_E_UNSUPPORTED, (ch, kw)
+    # PP singlet / triplet: one accumulator each, no direct vectors (as PP up-down)
+    for kw in (dict(mode=0), dict(mode=1, max_batch=8, prod=1, g_in=1)):
+        e4, b4 = g4.g4_slice_size(base(channels=4, **kw))
+        for ch in (64, 128):
+            assert g4.g4_slice_size(base(channels=ch, **kw)) == (e4, b4)
+        e, b = g4.g4_slice_size(base(channels=192, **kw))
+        assert b - b4 == e4 * 16
 
 
 def test_unsupported_is_distinguished():
