@@ -353,6 +353,91 @@ int oracle_gsigma(int lx, int ly, int nw, int nwex, double beta, double mu, doub
     return 0;
 }
 
+/*
+ * Multi-orbital G4: every single-particle index carries an orbital label,
+ * (K, b) with b in [0, nb); G_sigma is (Ng nb) x (Ng nb), row/column index
+ * (k*Nwg + n + Nw/2)*nb + b.  A G4 entry carries four labels: (K1, b1, b2),
+ * (K2, b3, b4).  By the same Wick rule as the single-band channels, on the
+ * strings c+_{K1+Q,b1,s1} c_{K1,b2,s1} c+_{K2,b3,s2} c_{K2+Q,b4,s2} (PH) and
+ * c+_{K2,b3,-s} c+_{Q-K2,b4,s} c_{Q-K1,b2,s} c_{K1,b1,-s} (PP):
+ *
+ *   PH magnetic/charge  T = (Gu -/+ Gd)(K1+Q b1, K1 b2) (Gu -/+ Gd)(K2 b3, K2+Q b4)
+ *                           - sum_s G_s(K2 b3, K1 b2) G_s(K1+Q b1, K2+Q b4)
+ *   PP up-down          T = sum_s G_s(Q-K2 b4, Q-K1 b2) G_{-s}(K2 b3, K1 b1)
+ *
+ * nb = 1 is the single-band definition above.  Slice entry
+ * ((p*N + K2)*nb*nb + b3*nb + b4) * (N*nb*nb) + (K1*nb + b1)*nb + b2, p the
+ * plane within the slice; the slice holds planes*(N nb^2)^2 entries.
+ */
+static cplx mo_g(const double *g, long ngb, long r, int br, long c, int bc, int nb) {
+    return g_at(g, ngb, r * nb + br, c * nb + bc);
+}
+
+static cplx mo_term(const oracle_shape *s, int nb, int channel, const double *gu, const double *gd, long ngb,
+                    long iQ, long K2, int b3, int b4, long K1, int b1, int b2) {
+    int nw = s->nw;
+    int iq = (int)(iQ / s->nwex), m = (int)(iQ % s->nwex);
+    int q = s->q_list[iq];
+    int k1 = (int)(K1 / nw), n1 = (int)(K1 % nw) - nw / 2;
+    int k2 = (int)(K2 / nw), n2 = (int)(K2 % nw) - nw / 2;
+    long r_k1 = g_index(s, k1, n1), r_k2 = g_index(s, k2, n2);
+    cplx t = {0.0, 0.0};
+    if (channel == ORACLE_PH_MAGNETIC || channel == ORACLE_PH_CHARGE) {
+        long r_k1q = g_index(s, mom_add(s, k1, q), n1 + m);
+        long r_k2q = g_index(s, mom_add(s, k2, q), n2 + m);
+        cplx u1 = mo_g(gu, ngb, r_k1q, b1, r_k1, b2, nb), d1 = mo_g(gd, ngb, r_k1q, b1, r_k1, b2, nb);
+        cplx u2 = mo_g(gu, ngb, r_k2, b3, r_k2q, b4, nb), d2 = mo_g(gd, ngb, r_k2, b3, r_k2q, b4, nb);
+        cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);
+        cplx b = channel == ORACLE_PH_MAGNETIC ? c_sub(u2, d2) : c_add(u2, d2);
+        cplx ex_u = c_mul(mo_g(gu, ngb, r_k2, b3, r_k1, b2, nb), mo_g(gu, ngb, r_k1q, b1, r_k2q, b4, nb));
+        cplx ex_d = c_mul(mo_g(gd, ngb, r_k2, b3, r_k1, b2, nb), mo_g(gd, ngb, r_k1q, b1, r_k2q, b4, nb));
+        t = c_sub(c_mul(a, b), c_add(ex_u, ex_d));
+    } else if (channel == ORACLE_PP_UPDOWN) {
+        long r_qk1 = g_index(s, mom_sub(s, q, k1), m - n1 - 1);
+        long r_qk2 = g_index(s, mom_sub(s, q, k2), m - n2 - 1);
+        cplx up = c_mul(mo_g(gu, ngb, r_qk2, b4, r_qk1, b2, nb), mo_g(gd, ngb, r_k2, b3, r_k1, b1, nb));
+        cplx dn = c_mul(mo_g(gd, ngb, r_qk2, b4, r_qk1, b2, nb), mo_g(gu, ngb, r_k2, b3, r_k1, b1, nb));
+        t = c_add(up, dn);
+    }
+    return t;
+}
+
+/*
+ * Accumulate `batch` measurements of the multi-orbital slice into g4
+ * (complex interleaved, planes*(N nb^2)^2 values).  Channels: magnetic,
+ * charge, PP up-down.  Returns 0, or -1 on a bad shape or argument.
+ */
+int oracle_accumulate_mo(const oracle_shape *s, int nb, int channel, const double *g_up, const double *g_dn,
+                         const double *sign, int batch, double *g4) {
+    if (check_shape(s, channel) || nb < 1 || batch < 0 || !g_up || !g_dn || !sign || !g4) return -1;
+    if (channel != ORACLE_PH_MAGNETIC && channel != ORACLE_PH_CHARGE && channel != ORACLE_PP_UPDOWN) return -1;
+    long nc = (long)s->lx * s->ly;
+    long ngb = nc * (s->nw + s->nwex - 1) * nb;
+    long n = nc * s->nw;
+    long side = n * nb * nb;
+    long planes = s->q_end - s->q_begin;
+    for (int b = 0; b < batch; ++b) {
+        const double *gu = g_up + 2 * (size_t)b * ngb * ngb;
+        const double *gd = g_dn + 2 * (size_t)b * ngb * ngb;
+#pragma omp parallel for schedule(dynamic, 4)
+        for (long row = 0; row < planes * side; ++row) {
+            long iQ = s->q_begin + row / side;
+            long r = row % side;
+            long K2 = r / (nb * nb);
+            int b3 = (int)((r / nb) % nb), b4 = (int)(r % nb);
+            for (long col = 0; col < side; ++col) {
+                long K1 = col / (nb * nb);
+                int b1 = (int)((col / nb) % nb), b2 = (int)(col % nb);
+                cplx t = mo_term(s, nb, channel, gu, gd, ngb, iQ, K2, b3, b4, K1, b1, b2);
+                double *acc = g4 + 2 * (row * side + col);
+                acc[0] += sign[b] * t.re;
+                acc[1] += sign[b] * t.im;
+            }
+        }
+    }
+    return 0;
+}
+
 /* Threads OpenMP would use (for reporting the CPU-baseline core count). */
 int oracle_max_threads(void) {
 #ifdef _OPENMP

@@ -52,6 +52,9 @@ def lib():
                                     ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int), dp,
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_long, dp]
         L.oracle_gsigma.restype = ctypes.c_int
+        L.oracle_accumulate_mo.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, ctypes.c_int, dp, dp, dp,
+                                           ctypes.c_int, dp]
+        L.oracle_accumulate_mo.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -91,6 +94,26 @@ def accumulate(w, channel: int, g_up: np.ndarray, g_dn: np.ndarray, sign: np.nda
                                  _dp(g4), _dp(comp) if comp is not None else None, nthreads)
     if rc:
         raise ValueError("oracle_accumulate rejected the shape or arguments")
+    return g4
+
+
+def accumulate_mo(w, nb: int, channel: int, g_up: np.ndarray, g_dn: np.ndarray, sign: np.ndarray,
+                  g4: Optional[np.ndarray] = None) -> np.ndarray:
+    """Multi-orbital slice (complex128 [planes, N nb^2, N nb^2]; rows (K2, b3, b4),
+    columns (K1, b1, b2)) += sum_b s_b T_channel; G: batch x (Ng nb)^2."""
+    sign = np.ascontiguousarray(sign, dtype=np.float64)
+    batch = sign.shape[0]
+    ngb = w.ng * nb
+    g_up = _c128(g_up, (batch, ngb, ngb))
+    g_dn = _c128(g_dn, (batch, ngb, ngb))
+    side = w.n * nb * nb
+    if g4 is None:
+        g4 = np.zeros((w.planes, side, side), dtype=np.complex128)
+    assert g4.dtype == np.complex128 and g4.flags.c_contiguous and g4.shape == (w.planes, side, side)
+    s, q = _shape(w)
+    rc = lib().oracle_accumulate_mo(ctypes.byref(s), nb, channel, _dp(g_up), _dp(g_dn), _dp(sign), batch, _dp(g4))
+    if rc:
+        raise ValueError("oracle_accumulate_mo rejected the shape or arguments")
     return g4
 
 

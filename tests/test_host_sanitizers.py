@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g", "-O1"]
 PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_wick.py", "tests/test_oracle_arrays.py",
         "tests/test_oracle_invariants.py", "tests/test_oracle_compensated.py", "tests/test_oracle_gsigma.py",
-        "tests/test_oracle_spin_channels.py"]
+        "tests/test_oracle_spin_channels.py", "tests/test_oracle_multiorbital.py"]
 
 
 def _libasan():

@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_wick.py",
         "tests/test_oracle_arrays.py", "tests/test_oracle_invariants.py",
         "tests/test_oracle_compensated.py", "tests/test_oracle_gsigma.py",
-        "tests/test_oracle_spin_channels.py"]
+        "tests/test_oracle_spin_channels.py", "tests/test_oracle_multiorbital.py"]
 
 # name -> (text in the oracle source, replacement)
 MUTANTS = {
@@ -42,7 +42,7 @@ MUTANTS = {
     "exchange sign": (
         "t = c_sub(direct, c_add(ex_u, ex_d));", "t = c_add(direct, c_add(ex_u, ex_d));"),
     "k1-q for k1+q": (
-        "g_index(s, mom_add(s, k1, q), n1 + m);", "g_index(s, mom_sub(s, k1, q), n1 + m);"),
+        "g_index(s, mom_add(s, k1, q), n1 + m);   /* K1 + Q */", "g_index(s, mom_sub(s, k1, q), n1 + m);"),
     "transposed exchange operand": (
         "cplx ex_u = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k1q, r_k2q));",
         "cplx ex_u = c_mul(g_at(gu, ng, r_k2, r_k1), g_at(gu, ng, r_k2q, r_k1q));"),
@@ -50,17 +50,17 @@ MUTANTS = {
         "cplx u1 = g_at(gu, ng, r_k1q, r_k1), d1 = g_at(gd, ng, r_k1q, r_k1);",
         "cplx u1 = g_at(gu, ng, r_k1, r_k1q), d1 = g_at(gd, ng, r_k1, r_k1q);"),
     "charge and magnetic spin weights swapped": (
-        "cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);",
-        "cplx a = channel == ORACLE_PH_MAGNETIC ? c_add(u1, d1) : c_sub(u1, d1);"),
+        "            cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);",
+        "            cplx a = channel == ORACLE_PH_MAGNETIC ? c_add(u1, d1) : c_sub(u1, d1);"),
     # particle-particle term, Eq. (1)
     "transposed PP operand": (
         "cplx up = c_mul(g_at(gu, ng, r_qk2, r_qk1)", "cplx up = c_mul(g_at(gu, ng, r_qk1, r_qk2)"),
     "PP same spin for the opposite spin": (
         "g_at(gd, ng, r_k2, r_k1));\n        cplx dn", "g_at(gu, ng, r_k2, r_k1));\n        cplx dn"),
     "PP frequency n2 for n1 in Q-K1": (
-        "mom_sub(s, q, k1), m - n1 - 1)", "mom_sub(s, q, k1), m - n2 - 1)"),
+        "mom_sub(s, q, k1), m - n1 - 1); /* Q - K1 */", "mom_sub(s, q, k1), m - n2 - 1);"),
     "PP frequency off by one": (
-        "mom_sub(s, q, k2), m - n2 - 1)", "mom_sub(s, q, k2), m - n2)"),
+        "mom_sub(s, q, k2), m - n2 - 1); /* Q - K2 */", "mom_sub(s, q, k2), m - n2);"),
     # spin-resolved particle-hole channels
     "up-up exchange dropped": (
         "t = c_sub(direct, ex);", "t = direct;"),
@@ -84,6 +84,20 @@ MUTANTS = {
         "cplx sum = channel == ORACLE_PP_SINGLET ? c_sub(t, crossed) : c_add(t, crossed);"),
     "PP projection without the 1/2": (
         "t.re = 0.5 * sum.re;", "t.re = sum.re;"),
+    # multi-orbital labels
+    "MO exchange with b1 and b4 swapped": (
+        "mo_g(gu, ngb, r_k1q, b1, r_k2q, b4, nb));", "mo_g(gu, ngb, r_k1q, b4, r_k2q, b1, nb));"),
+    "MO direct with b3 and b4 swapped": (
+        "cplx u2 = mo_g(gu, ngb, r_k2, b3, r_k2q, b4, nb)", "cplx u2 = mo_g(gu, ngb, r_k2, b4, r_k2q, b3, nb)"),
+    "MO PP with b1 and b2 swapped": (
+        "cplx up = c_mul(mo_g(gu, ngb, r_qk2, b4, r_qk1, b2, nb), mo_g(gd, ngb, r_k2, b3, r_k1, b1, nb));",
+        "cplx up = c_mul(mo_g(gu, ngb, r_qk2, b4, r_qk1, b1, nb), mo_g(gd, ngb, r_k2, b3, r_k1, b2, nb));"),
+    "MO magnetic and charge spin weights swapped": (
+        "\n        cplx a = channel == ORACLE_PH_MAGNETIC ? c_sub(u1, d1) : c_add(u1, d1);",
+        "\n        cplx a = channel == ORACLE_PH_MAGNETIC ? c_add(u1, d1) : c_sub(u1, d1);"),
+    "MO G index with the orbital slowest": (
+        "return g_at(g, ngb, r * nb + br, c * nb + bc);",
+        "return g_at(g, ngb, br * (ngb / nb) + r, bc * (ngb / nb) + c);"),
     # G_sigma from an expansion configuration
     "G_sigma: conjugate phase on the left factor": (
         "const cplx ea = {cos(tha), sin(tha)};", "const cplx ea = {cos(tha), -sin(tha)};"),
