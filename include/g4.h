@@ -409,6 +409,40 @@ int g4_gsigma(int32_t lx, int32_t ly, int32_t nw, int32_t nwex, double beta, dou
 int g4_gsigma_workspace(int32_t lx, int32_t ly, int32_t nw, int32_t nwex, int32_t n, int32_t count,
                         int32_t dtype, uint64_t *bytes);
 
+/* ---- multi-orbital G4 ---------------------------------------------------
+ * Accumulate `batch` measurements of the multi-orbital G4 into caller-owned
+ * accumulators: every single-particle index carries an orbital label b in
+ * [0, nb), so an entry is (Q; K1, b1, b2; K2, b3, b4) and the array holds
+ * planes x (N nb^2)^2 entries per channel.  Per measurement:
+ *   PH magnetic/charge  s_b [ (Gu-/+Gd)(K1+Q b1, K1 b2) (Gu-/+Gd)(K2 b3, K2+Q b4)
+ *                             - sum_s G_s(K2 b3, K1 b2) G_s(K1+Q b1, K2+Q b4) ]
+ *   PP up-down          s_b sum_s G_s(Q-K2 b4, Q-K1 b2) G_{-s}(K2 b3, K1 b1)
+ * (nb = 1: the single-band channels above).
+ * Paper: Background section, "Memory-Bound Issue in DCA++" (Eq. (1), and the
+ * multi-orbital case whose G_t grows with the fourth power of the orbital
+ * count, which motivates distributing G_t).
+ * Arguments: lx, ly, nw, nwex, nq, q_list (HOST, nq distinct momenta, or NULL
+ *   for 0..nq-1), q_begin, q_end as in g4_config; nb in [1, 64];
+ *   channels: bitmask of G4_PH_MAGNETIC | G4_PH_CHARGE | G4_PP_UPDOWN;
+ *   prod: G4_PROD_F64 (G complex128, FP64 products) or G4_PROD_F32 (G
+ *   complex64, FP32 products and sums over each launch's measurements);
+ *   G_up, G_dn: DEVICE, batch matrices of (Ng nb) x (Ng nb), row-major, row
+ *   and column index (k*Nwg + n + nw/2)*nb + b, borrowed until the stream
+ *   reaches the end of this call's work;
+ *   sign: HOST, batch weights (copied before return);
+ *   acc_mag, acc_chg, acc_pp: DEVICE complex128 accumulators, one per channel
+ *   in `channels` (NULL for the others), each (q_end-q_begin) x (N nb^2)^2
+ *   entries, entry ((p*N + K2)*nb^2 + b3*nb + b4)*(N nb^2) + (K1*nb + b1)*nb
+ *   + b2; owned by the caller, who zeroes them;
+ *   stream: hipStream_t or NULL.
+ * Asynchronous on stream; allocates nothing.  G4_E_ARG for bad shapes,
+ * channels, pointers or accumulators not matching `channels`; G4_E_UNSUPPORTED
+ * when (Ng nb)^2 >= 2^40 or N nb^2 > 2^30; G4_E_HIP if a launch fails. */
+int g4_accumulate_mo(int32_t lx, int32_t ly, int32_t nw, int32_t nwex, int32_t nb, int32_t nq,
+                     const int32_t *q_list, int64_t q_begin, int64_t q_end, uint32_t channels, int32_t prod,
+                     const void *G_up, const void *G_dn, const double *sign, int32_t batch, void *acc_mag,
+                     void *acc_chg, void *acc_pp, void *stream);
+
 /* Release everything owned by h (waits for its stream).  NULL is a no-op.
  * Paper: Background section, the solver workflow (G_t is freed at the end of
  * the run). */

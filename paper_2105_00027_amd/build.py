@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libg4.so")
 SOURCES = [("g4_abi.cpp", "g4_abi", []), ("g4_kernels.hip", "g4_kernels", []),
            ("g4_synth.hip", "g4_synth", []), ("g4_update_mfma.hip", "g4_update_mfma", []),
            ("g4_direct.hip", "g4_direct", []), ("g4_noalloc.hip", "g4_noalloc", []),
-           ("g4_gsigma.hip", "g4_gsigma", [])] + [
+           ("g4_gsigma.hip", "g4_gsigma", []), ("g4_multiorbital.hip", "g4_multiorbital", [])] + [
     ("g4_update_inst.hip", "g4_update_k%d_e%d" % (k, e), ["-DG4_KIND=%d" % k, "-DG4_EPT=%d" % e])
     for k in (0, 1, 2) for e in (1, 2, 4, 8)] + [
     ("g4_update_packed.hip", "g4_update_packed_e%d" % e, ["-DG4_EPT=%d" % e]) for e in (1, 2, 4, 8)]

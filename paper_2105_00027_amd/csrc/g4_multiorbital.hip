@@ -1,0 +1,195 @@
+// Multi-orbital G4 accumulation for gfx950: every single-particle index
+// carries an orbital label, so a G4 entry is (Q; K1, b1, b2; K2, b3, b4) and
+// the array grows as nb^4 (the paper's motivating case for distributing G_t:
+// Background section, "Memory-Bound Issue in DCA++").
+//
+// Per measurement b with weight s_b:
+//   PH magnetic/charge  s_b [ (Gu -/+ Gd)(K1+Q b1, K1 b2) (Gu -/+ Gd)(K2 b3, K2+Q b4)
+//                             - sum_s G_s(K2 b3, K1 b2) G_s(K1+Q b1, K2+Q b4) ]
+//   PP up-down          s_b sum_s G_s(Q-K2 b4, Q-K1 b2) G_{-s}(K2 b3, K1 b1)
+// G_sigma is (Ng nb) x (Ng nb), index (k*Nwg + n + Nw/2)*nb + b.  The slice is
+// stored as documented: entry ((p*N + K2)*nb^2 + b3*nb + b4)*(N nb^2) +
+// (K1*nb + b1)*nb + b2, complex128.
+//
+// One thread per entry, lanes along (K1, b1, b2); a launch covers up to 64
+// measurements of one channel over up to 256 planes and keeps the sum over the
+// measurements in registers, then reads, adds and writes each entry once.  The
+// G elements come straight from global memory: the row-side operands
+// (K2 b3, K2+Q b4) are the same for a whole block, the column-side ones are
+// reused from L2 across the rows of a plane.  Momenta are added on the lattice
+// coordinates in the kernel (no tables).
+#include "../../include/g4.h"
+#include "g4_internal.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+namespace g4 {
+namespace {
+
+constexpr int kMoPlanes = 256;   // planes per launch
+constexpr int kMoBatch = 64;     // measurements per launch
+
+struct MoArgs {
+    const void *gu, *gd;
+    int64_t g_stride;            // elements between matrices
+    double2 *acc;                // slice of this launch's first plane
+    int64_t total;               // entries of this launch
+    int64_t side;                // N nb^2
+    int lx, ly, nw, nwg, nb, ngb, channel, batch, planes;
+    int2 qm[kMoPlanes];          // (q, m) per plane of the launch
+    double sign[kMoBatch];
+};
+
+template <typename R> struct MoCx;
+template <> struct MoCx<double> { using V = double2; };
+template <> struct MoCx<float> { using V = float2; };
+
+template <typename V>
+__device__ __forceinline__ V mo_ld(const V *g, int64_t i) { return g[i]; }
+
+template <typename R>
+__global__ __launch_bounds__(256) void mo_kernel(MoArgs a) {
+    using V = typename MoCx<R>::V;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= a.total) return;
+    const int nb = a.nb, nw = a.nw, nwg = a.nwg, lx = a.lx, ly = a.ly;
+    const int64_t side = a.side, ngb = a.ngb;
+    const int64_t col = e % side, rr = e / side;
+    const int p = (int)(rr / side);
+    const int64_t row = rr % side;
+    const int K1 = (int)(col / (nb * nb)), b1 = (int)((col / nb) % nb), b2 = (int)(col % nb);
+    const int K2 = (int)(row / (nb * nb)), b3 = (int)((row / nb) % nb), b4 = (int)(row % nb);
+    const int q = a.qm[p].x, m = a.qm[p].y;
+    const int k1 = K1 / nw, i1 = K1 % nw, k2 = K2 / nw, i2 = K2 % nw;
+    const int qx = q % lx, qy = q / lx;
+    auto kadd = [&](int k) { return (k % lx + qx) % lx + lx * ((k / lx + qy) % ly); };
+    auto ksub = [&](int k) { return (qx - k % lx + lx) % lx + lx * ((qy - k / lx + ly) % ly); };
+    // G row/column of (window index, orbital)
+    auto gi = [&](int w, int b) { return (int64_t)w * nb + b; };
+    const V *gu = static_cast<const V *>(a.gu);
+    const V *gd = static_cast<const V *>(a.gd);
+    R sr = 0, si = 0;
+    if (a.channel == CH_PP) {
+        const int w_qk1 = ksub(k1) * nwg + (m + nw - 1 - i1), w_qk2 = ksub(k2) * nwg + (m + nw - 1 - i2);
+        const int64_t iz = gi(w_qk2, b4) * ngb + gi(w_qk1, b2);          // G(Q-K2 b4, Q-K1 b2)
+        const int64_t ix = gi(k2 * nwg + i2, b3) * ngb + gi(k1 * nwg + i1, b1);   // G(K2 b3, K1 b1)
+        for (int b = 0; b < a.batch; ++b) {
+            const int64_t o = (int64_t)b * a.g_stride;
+            const V zu = mo_ld(gu, o + iz), zd = mo_ld(gd, o + iz), xu = mo_ld(gu, o + ix), xd = mo_ld(gd, o + ix);
+            const R s = (R)a.sign[b];
+            const R tr = zu.x * xd.x - zu.y * xd.y + zd.x * xu.x - zd.y * xu.y;
+            const R ti = zu.x * xd.y + zu.y * xd.x + zd.x * xu.y + zd.y * xu.x;
+            sr += s * tr;
+            si += s * ti;
+        }
+    } else {
+        const R sg = a.channel == CH_MAG ? (R)-1 : (R)1;
+        const int w_k1 = k1 * nwg + i1, w_k2 = k2 * nwg + i2;
+        const int w_k1q = kadd(k1) * nwg + i1 + m, w_k2q = kadd(k2) * nwg + i2 + m;
+        const int64_t i_a = gi(w_k1q, b1) * ngb + gi(w_k1, b2);    // G(K1+Q b1, K1 b2)
+        const int64_t i_b = gi(w_k2, b3) * ngb + gi(w_k2q, b4);    // G(K2 b3, K2+Q b4)
+        const int64_t i_x = gi(w_k2, b3) * ngb + gi(w_k1, b2);     // G(K2 b3, K1 b2)
+        const int64_t i_y = gi(w_k1q, b1) * ngb + gi(w_k2q, b4);   // G(K1+Q b1, K2+Q b4)
+        for (int b = 0; b < a.batch; ++b) {
+            const int64_t o = (int64_t)b * a.g_stride;
+            const V au = mo_ld(gu, o + i_a), ad = mo_ld(gd, o + i_a);
+            const V bu = mo_ld(gu, o + i_b), bd = mo_ld(gd, o + i_b);
+            const V xu = mo_ld(gu, o + i_x), xd = mo_ld(gd, o + i_x);
+            const V yu = mo_ld(gu, o + i_y), yd = mo_ld(gd, o + i_y);
+            const R ar = au.x + sg * ad.x, ai = au.y + sg * ad.y;
+            const R br = bu.x + sg * bd.x, bi = bu.y + sg * bd.y;
+            const R tr = ar * br - ai * bi - (xu.x * yu.x - xu.y * yu.y) - (xd.x * yd.x - xd.y * yd.y);
+            const R ti = ar * bi + ai * br - (xu.x * yu.y + xu.y * yu.x) - (xd.x * yd.y + xd.y * yd.x);
+            const R s = (R)a.sign[b];
+            sr += s * tr;
+            si += s * ti;
+        }
+    }
+    double2 *pa = a.acc + e;
+    double2 v = *pa;
+    v.x += (double)sr;
+    v.y += (double)si;
+    *pa = v;
+}
+
+}  // namespace
+
+int set_error(int code, const char *msg);
+
+}  // namespace g4
+
+extern "C" int g4_accumulate_mo(int32_t lx, int32_t ly, int32_t nw, int32_t nwex, int32_t nb, int32_t nq,
+                                const int32_t *q_list, int64_t q_begin, int64_t q_end, uint32_t channels,
+                                int32_t prod, const void *G_up, const void *G_dn, const double *sign,
+                                int32_t batch, void *acc_mag, void *acc_chg, void *acc_pp, void *stream) {
+    using namespace g4;
+    if (lx < 1 || ly < 1 || (int64_t)lx * ly > 4096 || nw < 2 || (nw & 1) || nw > 4096 || nwex < 1 ||
+        nwex > 4096 || nb < 1 || nb > 64)
+        return set_error(G4_E_ARG, "multi-orbital: bad cluster, frequency or orbital count");
+    const int nc = lx * ly;
+    if (nq < 1 || nq > nc) return set_error(G4_E_ARG, "multi-orbital: nq outside [1, Nc]");
+    std::vector<int> ql(nq), seen(nc, 0);
+    for (int i = 0; i < nq; ++i) {
+        ql[i] = q_list ? q_list[i] : i;
+        if (ql[i] < 0 || ql[i] >= nc || seen[ql[i]]) return set_error(G4_E_ARG, "multi-orbital: bad q_list");
+        seen[ql[i]] = 1;
+    }
+    if (q_begin < 0 || q_end > (int64_t)nq * nwex || q_begin >= q_end)
+        return set_error(G4_E_ARG, "multi-orbital: slice planes outside [0, nq*nwex)");
+    if (channels == 0 || (channels & ~7u)) return set_error(G4_E_ARG, "multi-orbital: channels of 1|2|4 only");
+    if (prod != G4_PROD_F64 && prod != G4_PROD_F32)
+        return set_error(G4_E_ARG, "multi-orbital: prod must be G4_PROD_F64 or G4_PROD_F32");
+    if (batch < 0) return set_error(G4_E_ARG, "multi-orbital: batch < 0");
+    void *acc[3] = {acc_mag, acc_chg, acc_pp};
+    for (int c = 0; c < 3; ++c)
+        if (((channels >> c) & 1u) != (acc[c] != nullptr))
+            return set_error(G4_E_ARG, "multi-orbital: one accumulator per channel, NULL for the others");
+    const int64_t nwg = nw + nwex - 1;
+    const int64_t ngb = (int64_t)nc * nwg * nb;
+    const int64_t side = (int64_t)nc * nw * nb * nb;
+    if (ngb * ngb >= ((int64_t)1 << 40) || side > ((int64_t)1 << 30))
+        return set_error(G4_E_UNSUPPORTED, "multi-orbital: matrices too large");
+    if (batch == 0) return G4_OK;
+    if (!G_up || !G_dn || !sign) return set_error(G4_E_ARG, "multi-orbital: NULL G or sign");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t planes = q_end - q_begin;
+    for (int c = 0; c < 3; ++c) {
+        if (!acc[c]) continue;
+        for (int64_t p0 = 0; p0 < planes; p0 += kMoPlanes) {
+            const int np = (int)std::min<int64_t>(kMoPlanes, planes - p0);
+            for (int b0 = 0; b0 < batch; b0 += kMoBatch) {
+                MoArgs a{};
+                a.g_stride = ngb * ngb;
+                const size_t el = prod == G4_PROD_F64 ? 16 : 8;
+                a.gu = static_cast<const char *>(G_up) + (size_t)b0 * a.g_stride * el;
+                a.gd = static_cast<const char *>(G_dn) + (size_t)b0 * a.g_stride * el;
+                a.acc = static_cast<double2 *>(acc[c]) + p0 * side * side;
+                a.total = (int64_t)np * side * side;
+                a.side = side;
+                a.lx = lx; a.ly = ly; a.nw = nw; a.nwg = (int)nwg; a.nb = nb; a.ngb = (int)ngb;
+                a.channel = 1 << c;
+                a.batch = std::min(kMoBatch, batch - b0);
+                a.planes = np;
+                for (int i = 0; i < np; ++i) {
+                    const int64_t iQ = q_begin + p0 + i;
+                    a.qm[i] = int2{ql[(size_t)(iQ / nwex)], (int)(iQ % nwex)};
+                }
+                for (int j = 0; j < a.batch; ++j) a.sign[j] = sign[b0 + j];
+                const int64_t blocks = (a.total + 255) / 256;
+                if (blocks >= ((int64_t)1 << 31)) return set_error(G4_E_UNSUPPORTED, "multi-orbital: grid too large");
+                if (prod == G4_PROD_F64)
+                    hipLaunchKernelGGL(mo_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+                else
+                    hipLaunchKernelGGL(mo_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+                if (hipError_t e = hipGetLastError(); e != hipSuccess) {
+                    char msg[160];
+                    std::snprintf(msg, sizeof(msg), "multi-orbital launch: %s", hipGetErrorString(e));
+                    return set_error(G4_E_HIP, msg);
+                }
+            }
+        }
+    }
+    return G4_OK;
+}

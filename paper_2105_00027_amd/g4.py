@@ -105,6 +105,9 @@ _sig = {
     "g4_gsigma_workspace": ([ctypes.c_int32] * 7 + [ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "g4_gsigma": ([ctypes.c_int32] * 4 + [ctypes.c_double] * 4 + [ctypes.c_int32] * 3
                   + [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int),
+    "g4_accumulate_mo": ([ctypes.c_int32] * 6 + [ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.c_int64,
+                          ctypes.c_uint32, ctypes.c_int32, _vp, _vp, _dp, ctypes.c_int32, _vp, _vp, _vp, _vp],
+                         ctypes.c_int),
     "g4_destroy": ([_vp], None),
     "g4_last_error": ([], ctypes.c_char_p),
     "g4_synth_fill": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -308,6 +311,31 @@ def g4_gsigma(lx: int, ly: int, nw: int, nwex: int, beta: float, mu: float, h: f
     wbytes = workspace.numel() * workspace.element_size() if not isinstance(workspace, int) else need
     _check(_L.g4_gsigma(lx, ly, nw, nwex, beta, mu, h, t, spin, n, count, _vp(pt), _vp(ps), _vp(pm), dtype,
                         _vp(pg), _vp(pw), wbytes, _vp(int(stream) if stream else 0)))
+
+
+def g4_accumulate_mo(lx: int, ly: int, nw: int, nwex: int, nb: int, nq: int, q_list, q_begin: int, q_end: int,
+                     channels: int, prod: int, G_up, G_dn, sign, acc_mag=None, acc_chg=None, acc_pp=None,
+                     stream=None) -> None:
+    """Multi-orbital accumulation into caller-owned complex128 accumulators
+    (planes x (N nb^2)^2 each); see include/g4.h."""
+    s = np.ascontiguousarray(np.asarray(sign, dtype=np.float64).reshape(-1))
+    batch = s.shape[0]
+    ngb = lx * ly * (nw + nwex - 1) * nb
+    el = 16 if prod == G4_PROD_F64 else 8
+    pu = _device_ptr(G_up, batch * ngb * ngb * el, el)
+    pd = _device_ptr(G_dn, batch * ngb * ngb * el, el)
+    side = lx * ly * nw * nb * nb
+    ab = (q_end - q_begin) * side * side * 16
+    accs = [_acc_ptr(a, ab) for a in (acc_mag, acc_chg, acc_pp)]
+    ql = None
+    if q_list is not None:
+        qa = np.ascontiguousarray(np.asarray(q_list, dtype=np.int32))
+        if qa.shape[0] != nq:
+            raise G4Error(G4_E_ARG, "q_list has %d entries, nq=%d" % (qa.shape[0], nq))
+        ql = qa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _check(_L.g4_accumulate_mo(lx, ly, nw, nwex, nb, nq, ql, q_begin, q_end, channels, prod, _vp(pu), _vp(pd),
+                               s.ctypes.data_as(_dp), batch, *[_vp(a) if a else None for a in accs],
+                               _vp(int(stream) if stream else 0)))
 
 
 def g4_sync(h: Slice) -> None:
