@@ -23,7 +23,10 @@ Further legs in the same JSON line (each with its rate, roofline and error):
                    hi+lo split direct term;
   gsigma           G_sigma of the 4x4 window (Ng = 1136) from seeded expansion
                    configurations of order n = 512, 64 measurements per call,
-                   complex64 and complex128 (the step before the slice update).
+                   complex64 and complex128 (the step before the slice update);
+  multi_orbital    the whole multi-orbital G4 of a 2x2 cluster with 4 orbitals
+                   (Nw = 32, Nwex = 4, all 16 transfer planes: 67M entries per
+                   channel), PH magnetic, 64 measurements per launch, FP32.
 
 Printed: one JSON line with the entry-update rate (entries x measurements per
 second), the dominant kernel's roofline position (its average launch time from
@@ -396,6 +399,54 @@ class Bench:
         torch.cuda.empty_cache()
         return out
 
+    def multi_orbital(self, w, nb, B, steps=4, warmup=1, nsample=64, check=True):
+        """Multi-orbital accumulation, PH magnetic, FP32 products, B measurements
+        per call into a caller-owned complex128 accumulator."""
+        torch, g4 = self.torch, self.g4
+        ngb = w.ng * nb
+        rng = np.random.default_rng(17)
+        gu_h = ((rng.normal(size=(B, ngb, ngb)) + 1j * rng.normal(size=(B, ngb, ngb))) * 0.1).astype(np.complex64)
+        gd_h = ((rng.normal(size=(B, ngb, ngb)) + 1j * rng.normal(size=(B, ngb, ngb))) * 0.1).astype(np.complex64)
+        s = np.where(rng.random(B) < 0.95, 1.0, -1.0)
+        gu = torch.from_numpy(gu_h).to(self.dev)
+        gd = torch.from_numpy(gd_h).to(self.dev)
+        side = w.n * nb * nb
+        acc = torch.zeros((w.planes, side, side), dtype=torch.complex128, device=self.dev)
+
+        def call(i):
+            g4.g4_accumulate_mo(w.lx, w.ly, w.nw, w.nwex, nb, w.nq, None, w.q0, w.q1, g4.G4_PH_MAGNETIC,
+                                g4.G4_PROD_F32, gu, gd, s, acc, None, None, self.sptr)
+        for i in range(warmup):
+            call(i)
+        torch.cuda.synchronize()
+        acc.zero_()
+        ms = [self.timed(call, steps) / steps for _ in range(REPS)]
+        med = statistics.median(ms)
+        E = w.planes * side * side
+        launch_s = med / 1e3
+        flops = 24.0 * E * B
+        byts = 32.0 * E + 2.0 * B * ngb * ngb * 8
+        out = {"value": E * B / launch_s, "unit": "entry-updates/s", "ms_per_call": med, "rep_ms": ms,
+               "entries": E, "measurements_per_call": B,
+               "roofline": {"bound": "alu", "achieved": flops / launch_s / 1e12, "peak": ALU_PEAK / 1e12,
+                            "unit": "TFLOP/s", "frac": flops / launch_s / ALU_PEAK, "traffic": None,
+                            "algorithmic_flops_per_launch": flops,
+                            "hbm_algorithmic_bytes_per_launch": byts,
+                            "hbm_frac": byts / launch_s / HBM_PEAK}}
+        if check:
+            from oracle import ref
+            torch.cuda.synchronize()
+            idx = rng.integers(0, E, size=nsample)
+            got = acc.reshape(-1)[torch.from_numpy(idx).to(self.dev)].cpu().numpy()
+            # the accumulator holds REPS * steps calls of the same B measurements
+            want = ref.entries_mo(w, nb, 1, gu_h.astype(np.complex128), gd_h.astype(np.complex128), s,
+                                  idx) * (REPS * steps)
+            out["error"] = {"rel_fro_vs_fp64_oracle": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+                            "sampled_entries": nsample}
+        del gu, gd, acc
+        torch.cuda.empty_cache()
+        return out
+
     def plain(self, w, M, tile=0, reps=REPS):
         """Plain FP64 leg: M measurements, one pass each, timed `reps` times."""
         g4, torch = self.g4, self.torch
@@ -495,6 +546,7 @@ def main():
     ap.add_argument("--no-ring", action="store_true", help="skip the ring-share leg")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision leg")
     ap.add_argument("--no-gsigma", action="store_true", help="skip the G_sigma leg")
+    ap.add_argument("--no-mo", action="store_true", help="skip the multi-orbital leg")
     ap.add_argument("--gsigma-order", type=int, default=512, help="expansion order of the G_sigma leg")
     ap.add_argument("--legs-only", action="store_true",
                     help="run only the ring-share, split-precision and G_sigma legs (profiling)")
@@ -512,7 +564,7 @@ def main():
 
     bench = Bench(args)
     g4, torch = bench.g4, bench.torch
-    from synth import C2_PLAIN, C4_RING, C5_SPLIT
+    from synth import C2_PLAIN, C4_RING, C5_SPLIT, Workload
 
     out = {"metric": METRIC, "unit": "entry-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
@@ -640,6 +692,15 @@ def main():
                                      % (gw.ng, n, count),
                          "c64": bench.gsigma(gw, n, count, False, check=not args.no_check),
                          "c128": bench.gsigma(gw, n, count, True, check=not args.no_check)}
+
+    # ---- multi-orbital G4 ------------------------------------------------------
+    if not args.no_mo and not ring:
+        mw = Workload("mo", lx=2, ly=2, nw=32, nwex=4, nq=4, beta=10.0)
+        leg = {"workload": "multi-orbital G4 of a 2x2 cluster, 4 orbitals, Nw=32, Nwex=4, all 16 transfer planes "
+                           "(%d entries), PH magnetic, 64 measurements per call, complex64 G, FP32 products, "
+                           "complex128 accumulator" % (mw.planes * (mw.n * 16) ** 2)}
+        leg.update(bench.multi_orbital(mw, 4, 64, check=not args.no_check))
+        out["multi_orbital"] = leg
 
     if not args.no_cpu_baseline and not args.legs_only:
         out["cpu_baseline"] = cpu_baseline(C2_PLAIN.with_(channels=g4.G4_PH_MAGNETIC), args.cpu_seconds)

@@ -438,6 +438,41 @@ int oracle_accumulate_mo(const oracle_shape *s, int nb, int channel, const doubl
     return 0;
 }
 
+/*
+ * Sum over the batch, in measurement order, of s_b * T_ch of the
+ * multi-orbital slice at `count` entries given by their flattened index
+ * (layout of oracle_accumulate_mo).  out: count complex values.
+ */
+int oracle_entries_mo(const oracle_shape *s, int nb, int channel, const double *g_up, const double *g_dn,
+                      const double *sign, int batch, const int64_t *idx, long count, double *out) {
+    if (check_shape(s, channel) || nb < 1 || batch < 0 || !g_up || !g_dn || !sign || (count && (!idx || !out)))
+        return -1;
+    if (channel != ORACLE_PH_MAGNETIC && channel != ORACLE_PH_CHARGE && channel != ORACLE_PP_UPDOWN) return -1;
+    long nc = (long)s->lx * s->ly;
+    long ngb = nc * (s->nw + s->nwex - 1) * nb;
+    long side = nc * s->nw * nb * nb;
+    long total = (s->q_end - s->q_begin) * side * side;
+    for (long j = 0; j < count; ++j)
+        if (idx[j] < 0 || idx[j] >= total) return -1;
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < count; ++j) {
+        long e = idx[j];
+        long col = e % side, row = (e / side) % side, iQ = s->q_begin + e / (side * side);
+        long K1 = col / (nb * nb), K2 = row / (nb * nb);
+        int b1 = (int)((col / nb) % nb), b2 = (int)(col % nb), b3 = (int)((row / nb) % nb), b4 = (int)(row % nb);
+        double re = 0.0, im = 0.0;
+        for (int b = 0; b < batch; ++b) {
+            cplx t = mo_term(s, nb, channel, g_up + 2 * (size_t)b * ngb * ngb, g_dn + 2 * (size_t)b * ngb * ngb,
+                             ngb, iQ, K2, b3, b4, K1, b1, b2);
+            re += sign[b] * t.re;
+            im += sign[b] * t.im;
+        }
+        out[2 * j] = re;
+        out[2 * j + 1] = im;
+    }
+    return 0;
+}
+
 /* Threads OpenMP would use (for reporting the CPU-baseline core count). */
 int oracle_max_threads(void) {
 #ifdef _OPENMP

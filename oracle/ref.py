@@ -55,6 +55,9 @@ def lib():
         L.oracle_accumulate_mo.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, ctypes.c_int, dp, dp, dp,
                                            ctypes.c_int, dp]
         L.oracle_accumulate_mo.restype = ctypes.c_int
+        L.oracle_entries_mo.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_long, dp]
+        L.oracle_entries_mo.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -115,6 +118,24 @@ def accumulate_mo(w, nb: int, channel: int, g_up: np.ndarray, g_dn: np.ndarray, 
     if rc:
         raise ValueError("oracle_accumulate_mo rejected the shape or arguments")
     return g4
+
+
+def entries_mo(w, nb: int, channel: int, g_up: np.ndarray, g_dn: np.ndarray, sign: np.ndarray,
+               idx: np.ndarray) -> np.ndarray:
+    """sum_b s_b T_channel of the multi-orbital slice at flattened entries idx."""
+    sign = np.ascontiguousarray(sign, dtype=np.float64)
+    batch = sign.shape[0]
+    ngb = w.ng * nb
+    g_up = _c128(g_up, (batch, ngb, ngb))
+    g_dn = _c128(g_dn, (batch, ngb, ngb))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(idx.shape[0], dtype=np.complex128)
+    s, q = _shape(w)
+    rc = lib().oracle_entries_mo(ctypes.byref(s), nb, channel, _dp(g_up), _dp(g_dn), _dp(sign), batch,
+                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.shape[0], _dp(out))
+    if rc:
+        raise ValueError("oracle_entries_mo rejected the shape or arguments")
+    return out
 
 
 def entries(w, channel: int, g_up: np.ndarray, g_dn: np.ndarray, sign: np.ndarray,

@@ -11,13 +11,19 @@
 // stored as documented: entry ((p*N + K2)*nb^2 + b3*nb + b4)*(N nb^2) +
 // (K1*nb + b1)*nb + b2, complex128.
 //
-// One thread per entry, lanes along (K1, b1, b2); a launch covers up to 64
-// measurements of one channel over up to 256 planes and keeps the sum over the
-// measurements in registers, then reads, adds and writes each entry once.  The
-// G elements come straight from global memory: the row-side operands
-// (K2 b3, K2+Q b4) are the same for a whole block, the column-side ones are
-// reused from L2 across the rows of a plane.  Momenta are added on the lattice
-// coordinates in the kernel (no tables).
+// A launch covers up to 64 measurements of one channel over up to 256 planes
+// and keeps the sums over the measurements in registers, then reads, adds and
+// writes each entry once.  For nb <= 4 (mo_rows_kernel) a thread owns one
+// column (K1, b1, b2) of one (plane, K2) and all nb^2 rows (b3, b4): per
+// measurement it loads the column's a = G(K1+Q b1, K1 b2) once, the nb
+// exchange operands of each side (G(K2 b3, K1 b2) and G(K1+Q b1, K2+Q b4):
+// one per b3, one per b4), and the nb^2 values b = G(K2 b3, K2+Q b4) that are
+// the same for every lane of the block, so about one vector load per entry
+// and measurement instead of eight; lanes run along the column, so each of
+// the nb^2 output rows is written as one contiguous run.  Larger nb takes the
+// one-thread-per-entry kernel (mo_kernel).  G elements come straight from
+// global memory (L2-resident across a plane's rows).  Momenta are added on
+// the lattice coordinates in the kernel (no tables).
 #include "../../include/g4.h"
 #include "g4_internal.hpp"
 
@@ -114,6 +120,126 @@ __global__ __launch_bounds__(256) void mo_kernel(MoArgs a) {
     *pa = v;
 }
 
+// Thread (plane p, K2, column (K1, b1, b2)) for all (b3, b4); NB = nb.
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void mo_rows_kernel(MoArgs a) {
+    using V = typename MoCx<R>::V;
+    const int64_t side = a.side;                       // N NB^2
+    const int64_t n = side / (NB * NB);
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t cols_per_row = side;
+    if (t >= (int64_t)a.planes * n * cols_per_row) return;
+    const int64_t col = t % cols_per_row, pk = t / cols_per_row;
+    const int K2 = (int)(pk % n), p = (int)(pk / n);
+    const int nw = a.nw, nwg = a.nwg, lx = a.lx, ly = a.ly;
+    const int64_t ngb = a.ngb;
+    const int K1 = (int)(col / (NB * NB)), b1 = (int)((col / NB) % NB), b2 = (int)(col % NB);
+    const int q = a.qm[p].x, m = a.qm[p].y;
+    const int k1 = K1 / nw, i1 = K1 % nw, k2 = K2 / nw, i2 = K2 % nw;
+    const int qx = q % lx, qy = q / lx;
+    auto kadd = [&](int k) { return (k % lx + qx) % lx + lx * ((k / lx + qy) % ly); };
+    auto ksub = [&](int k) { return (qx - k % lx + lx) % lx + lx * ((qy - k / lx + ly) % ly); };
+    auto gi = [&](int w, int b) { return (int64_t)w * NB + b; };
+    const V *gu = static_cast<const V *>(a.gu);
+    const V *gd = static_cast<const V *>(a.gd);
+    R sr[NB][NB], si[NB][NB];
+    for (int i = 0; i < NB; ++i)
+        for (int j = 0; j < NB; ++j) sr[i][j] = si[i][j] = 0;
+    if (a.channel == CH_PP) {
+        const int w_qk1 = ksub(k1) * nwg + (m + nw - 1 - i1), w_qk2 = ksub(k2) * nwg + (m + nw - 1 - i2);
+        const int w_k1 = k1 * nwg + i1, w_k2 = k2 * nwg + i2;
+        for (int b = 0; b < a.batch; ++b) {
+            const int64_t o = (int64_t)b * a.g_stride;
+            const R s = (R)a.sign[b];
+            V zu[NB], zd[NB], xu[NB], xd[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {   // G(Q-K2 b4, Q-K1 b2), b4 = j
+                const int64_t i = o + gi(w_qk2, j) * ngb + gi(w_qk1, b2);
+                zu[j] = gu[i];
+                zd[j] = gd[i];
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {   // G(K2 b3, K1 b1), b3 = j
+                const int64_t i = o + gi(w_k2, j) * ngb + gi(w_k1, b1);
+                xu[j] = gu[i];
+                xd[j] = gd[i];
+            }
+#pragma unroll
+            for (int b3 = 0; b3 < NB; ++b3)
+#pragma unroll
+                for (int b4 = 0; b4 < NB; ++b4) {
+                    const R tr = zu[b4].x * xd[b3].x - zu[b4].y * xd[b3].y + zd[b4].x * xu[b3].x - zd[b4].y * xu[b3].y;
+                    const R ti = zu[b4].x * xd[b3].y + zu[b4].y * xd[b3].x + zd[b4].x * xu[b3].y + zd[b4].y * xu[b3].x;
+                    sr[b3][b4] += s * tr;
+                    si[b3][b4] += s * ti;
+                }
+        }
+    } else {
+        const R sg = a.channel == CH_MAG ? (R)-1 : (R)1;
+        const int w_k1 = k1 * nwg + i1, w_k2 = k2 * nwg + i2;
+        const int w_k1q = kadd(k1) * nwg + i1 + m, w_k2q = kadd(k2) * nwg + i2 + m;
+        for (int b = 0; b < a.batch; ++b) {
+            const int64_t o = (int64_t)b * a.g_stride;
+            const R s = (R)a.sign[b];
+            const int64_t ia = o + gi(w_k1q, b1) * ngb + gi(w_k1, b2);          // G(K1+Q b1, K1 b2)
+            const V au = gu[ia], ad = gd[ia];
+            const R ar = au.x + sg * ad.x, ai = au.y + sg * ad.y;
+            V xu[NB], xd[NB], yu[NB], yd[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int64_t ix = o + gi(w_k2, j) * ngb + gi(w_k1, b2);       // G(K2 b3, K1 b2), b3 = j
+                const int64_t iy = o + gi(w_k1q, b1) * ngb + gi(w_k2q, j);     // G(K1+Q b1, K2+Q b4), b4 = j
+                xu[j] = gu[ix];
+                xd[j] = gd[ix];
+                yu[j] = gu[iy];
+                yd[j] = gd[iy];
+            }
+#pragma unroll
+            for (int b3 = 0; b3 < NB; ++b3)
+#pragma unroll
+                for (int b4 = 0; b4 < NB; ++b4) {
+                    const int64_t ib = o + gi(w_k2, b3) * ngb + gi(w_k2q, b4);   // G(K2 b3, K2+Q b4): block-uniform
+                    const V bu = gu[ib], bd = gd[ib];
+                    const R br = bu.x + sg * bd.x, bi = bu.y + sg * bd.y;
+                    const R tr = ar * br - ai * bi - (xu[b3].x * yu[b4].x - xu[b3].y * yu[b4].y) -
+                                 (xd[b3].x * yd[b4].x - xd[b3].y * yd[b4].y);
+                    const R ti = ar * bi + ai * br - (xu[b3].x * yu[b4].y + xu[b3].y * yu[b4].x) -
+                                 (xd[b3].x * yd[b4].y + xd[b3].y * yd[b4].x);
+                    sr[b3][b4] += s * tr;
+                    si[b3][b4] += s * ti;
+                }
+        }
+    }
+    // entry ((p*N + K2)*NB^2 + b3*NB + b4)*side + col
+#pragma unroll
+    for (int b3 = 0; b3 < NB; ++b3)
+#pragma unroll
+        for (int b4 = 0; b4 < NB; ++b4) {
+            double2 *pa = a.acc + (((int64_t)p * n + K2) * (NB * NB) + b3 * NB + b4) * side + col;
+            double2 v = *pa;
+            v.x += (double)sr[b3][b4];
+            v.y += (double)si[b3][b4];
+            *pa = v;
+        }
+}
+
+template <typename R>
+hipError_t launch_mo(const MoArgs &a, hipStream_t st) {
+    const int64_t n = a.side / ((int64_t)a.nb * a.nb);
+    const int64_t threads = a.nb <= 4 ? (int64_t)a.planes * n * a.side : a.total;
+    const int64_t blocks = (threads + 255) / 256;
+    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
+    const dim3 g((unsigned)blocks), b(256);
+    switch (a.nb) {
+        case 1: hipLaunchKernelGGL((mo_rows_kernel<R, 1>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((mo_rows_kernel<R, 2>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((mo_rows_kernel<R, 3>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((mo_rows_kernel<R, 4>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL(mo_kernel<R>, g, b, 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int set_error(int code, const char *msg);
@@ -177,13 +303,10 @@ extern "C" int g4_accumulate_mo(int32_t lx, int32_t ly, int32_t nw, int32_t nwex
                     a.qm[i] = int2{ql[(size_t)(iQ / nwex)], (int)(iQ % nwex)};
                 }
                 for (int j = 0; j < a.batch; ++j) a.sign[j] = sign[b0 + j];
-                const int64_t blocks = (a.total + 255) / 256;
-                if (blocks >= ((int64_t)1 << 31)) return set_error(G4_E_UNSUPPORTED, "multi-orbital: grid too large");
-                if (prod == G4_PROD_F64)
-                    hipLaunchKernelGGL(mo_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, a);
-                else
-                    hipLaunchKernelGGL(mo_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, a);
-                if (hipError_t e = hipGetLastError(); e != hipSuccess) {
+                if ((a.total + 255) / 256 >= ((int64_t)1 << 31))
+                    return set_error(G4_E_UNSUPPORTED, "multi-orbital: grid too large");
+                const hipError_t e = prod == G4_PROD_F64 ? launch_mo<double>(a, st) : launch_mo<float>(a, st);
+                if (e != hipSuccess) {
                     char msg[160];
                     std::snprintf(msg, sizeof(msg), "multi-orbital launch: %s", hipGetErrorString(e));
                     return set_error(G4_E_HIP, msg);

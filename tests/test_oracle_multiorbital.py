@@ -5,6 +5,8 @@
   G-window indices and orbital labels conserving momentum and frequency,
   contracted by the generic routine of the single-band Wick test, for the
   operator strings the oracle's header names;
+- the per-entry form equals the whole-slice form at sampled entries, bit for
+  bit;
 - orbital-diagonal, orbital-independent G: the entries with all four labels
   equal are the single-band values, bit for bit; entries with b1 = b2 and
   b3 = b4 but b2 != b3 keep only the direct term, those with b2 = b3 and
@@ -131,3 +133,16 @@ def test_orbital_diagonal_g_factorises(channel):
     d = mo[:, :, 1, 1, :, 0, 0]          # b1 = b2 = 0, b3 = b4 = 1: direct term
     x = mo[:, :, 0, 1, :, 1, 0]          # b2 = b3 = 0, b1 = b4 = 1: exchange term
     assert np.abs(d + x - single).max() <= 1e-13 * np.abs(single).max()
+
+
+@pytest.mark.parametrize("channel", CH)
+def test_entries_equal_whole_slice(channel):
+    w = Workload("mo-ent", lx=2, ly=2, nw=4, nwex=2, nq=4, q_list=(3, 1, 0, 2), q_begin=1, q_end=6, beta=5.0)
+    nb = 2
+    rng = np.random.default_rng(9 + channel)
+    ngb = w.ng * nb
+    gu, gd = rand_g(rng, (3, ngb, ngb)), rand_g(rng, (3, ngb, ngb))
+    s = np.array([1.0, -1.0, 1.0])
+    full = ref.accumulate_mo(w, nb, channel, gu, gd, s).reshape(-1)
+    idx = rng.integers(0, full.shape[0], size=200)
+    assert np.array_equal(ref.entries_mo(w, nb, channel, gu, gd, s, idx), full[idx])
