@@ -11,7 +11,7 @@
 // stored as documented: entry ((p*N + K2)*nb^2 + b3*nb + b4)*(N nb^2) +
 // (K1*nb + b1)*nb + b2, complex128.
 //
-// A launch covers up to 64 measurements of one channel over up to 256 planes
+// A launch covers up to 32 measurements of one channel over up to 256 planes
 // and keeps the sums over the measurements in registers, then reads, adds and
 // writes each entry once.  For nb <= 4 (mo_rows_kernel) a thread owns one
 // column (K1, b1, b2) of one (plane, K2) and all nb^2 rows (b3, b4): per
@@ -35,7 +35,10 @@ namespace g4 {
 namespace {
 
 constexpr int kMoPlanes = 256;   // planes per launch
-constexpr int kMoBatch = 64;     // measurements per launch
+// measurements per launch: 32 keeps a launch's G (2 x 32 x 2.5 MB for the
+// 2x2 cluster with 4 orbitals) in the last-level cache; 64 per launch took
+// 4.71 ms per 64 measurements there, 32 4.37 ms, 16 5.04 ms
+constexpr int kMoBatch = 32;
 
 struct MoArgs {
     const void *gu, *gd;

@@ -5,7 +5,7 @@ Bars: FP64 products 1e-12, FP32 products 1e-6 (relative Frobenius, Eq. (2)/(3)
 on real and imaginary parts, and the small half of the entries), per channel.
 Shapes: two and three orbitals, a transfer list in a different order, a slice
 cut through a transfer momentum, entry counts that are not multiples of the
-256-thread block; 70 measurements (two launches of at most 64).  Argument
+256-thread block; 70 measurements (three launches of at most 32).  Argument
 errors are rejected before any launch.
 """
 import numpy as np
