@@ -17,7 +17,9 @@
 // k, the four k slots hold (Re, Im) of both (Re C: A slots (Re a, -Im a),
 // Im C: (Im a, Re a), B slots (Re b, Im b)).  A 256-thread block owns a
 // 64 x 64 output tile (each wave 32 x 32: 2 x 2 MFMA tiles, Re and Im),
-// staged through LDS in k chunks of 16.
+// staged through LDS in k chunks of 16, the next chunk held in registers
+// while the current one is multiplied; LDS holds the operands in the form
+// each lane hands to the MFMA, so the inner loop is LDS reads and MFMAs.
 #include "../../include/g4.h"
 #include "g4_internal.hpp"
 
@@ -92,60 +94,97 @@ struct CgArgs {
     double scale;
 };
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BN = 64, BK = 16;
 
-template <typename T, bool BH, bool GEPI>
+// TM: 16-row MFMA tiles per wave along M; the block is (32 TM) x 64.
+template <typename T, bool BH, bool GEPI, int TM>
 __global__ __launch_bounds__(256) void cgemm_kernel(CgArgs a) {
     using V = typename Cx2<T>::V;
     using V4 = typename Cx2<T>::V4;
-    __shared__ V As[BM][BK + 1];
-    __shared__ V Bs[BK][BN + 1];
+    constexpr int BM = 32 * TM;
+    // Operands in LDS in the form each lane feeds the MFMA: A twice, as
+    // (Re, Im) for the real-part slots and (-Im, Re) for the imaginary-part
+    // slots; B split into its real and imaginary planes.
+    __shared__ V Ap[2][BM][BK + 1];
+    __shared__ T Bp[2][BK][BN + 4];
+    constexpr int PA = BM * BK / 256, PB = BK * BN / 256;   // elements a thread stages per chunk
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     const int b = blockIdx.z;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const V *A = static_cast<const V *>(a.A) + (int64_t)b * a.sA;
     const V *B = static_cast<const V *>(a.B) + (int64_t)b * a.sB;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int wr = (w >> 1) * 16 * TM, wc = (w & 1) * 32;
     const int slot = l >> 4, comp = slot & 1, kh = slot >> 1, lr = l & 15;
-    V4 re[2][2], im[2][2];
-    for (int i = 0; i < 2; ++i)
+    V4 re[TM][2], im[TM][2];
+    for (int i = 0; i < TM; ++i)
         for (int j = 0; j < 2; ++j) {
             re[i][j] = V4{0, 0, 0, 0};
             im[i][j] = V4{0, 0, 0, 0};
         }
-    for (int k0 = 0; k0 < a.K; k0 += BK) {
-        __syncthreads();      // the previous chunk's reads are done
-        for (int e = tid; e < BM * BK; e += 256) {
+    // the next chunk's operands are loaded into registers while the current one is multiplied
+    V ra[PA], rb[PB];
+    auto load = [&](int k0) {
+        for (int u = 0; u < PA; ++u) {
+            const int e = tid + 256 * u;
             const int r = e / BK, c = e % BK;
             const int gr = m0 + r, gc = k0 + c;
-            As[r][c] = (gr < a.M && gc < a.K) ? A[(int64_t)gr * a.lda + gc] : V{0, 0};
+            ra[u] = (gr < a.M && gc < a.K) ? A[(int64_t)gr * a.lda + gc] : V{0, 0};
         }
-        if (BH) {
-            for (int e = tid; e < BK * BN; e += 256) {
-                const int j = e / BK, c = e % BK;         // B_b row n0 + j, column k0 + c
-                const int gj = n0 + j, gc = k0 + c;
-                const V v = (gj < a.N && gc < a.K) ? B[(int64_t)gj * a.ldb + gc] : V{0, 0};
-                Bs[c][j] = V{v.x, -v.y};
-            }
-        } else {
-            for (int e = tid; e < BK * BN; e += 256) {
-                const int r = e / BN, c = e % BN;
-                const int gr = k0 + r, gc = n0 + c;
-                Bs[r][c] = (gr < a.K && gc < a.N) ? B[(int64_t)gr * a.ldb + gc] : V{0, 0};
+        for (int u = 0; u < PB; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / BK, c = e % BK;
+            if (BH) {
+                const int gj = n0 + r, gk = k0 + c;          // B_b row n0 + r, column k0 + c
+                rb[u] = (gj < a.N && gk < a.K) ? B[(int64_t)gj * a.ldb + gk] : V{0, 0};
+            } else {
+                const int rr = e / BN, cc = e % BN;
+                const int gk = k0 + rr, gj = n0 + cc;
+                rb[u] = (gk < a.K && gj < a.N) ? B[(int64_t)gk * a.ldb + gj] : V{0, 0};
             }
         }
+    };
+    auto store = [&]() {
+        for (int u = 0; u < PA; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / BK, c = e % BK;
+            const V v = ra[u];
+            Ap[0][r][c] = v;
+            Ap[1][r][c] = V{-v.y, v.x};
+        }
+        for (int u = 0; u < PB; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / BK, c = e % BK;
+            if (BH) {                 // conj(B_b(n0 + r, k0 + c)) at k = c, column r
+                Bp[0][c][r] = rb[u].x;
+                Bp[1][c][r] = -rb[u].y;
+            } else {
+                const int rr = e / BN, cc = e % BN;
+                Bp[0][rr][cc] = rb[u].x;
+                Bp[1][rr][cc] = rb[u].y;
+            }
+        }
+    };
+    if (a.K > 0) load(0);
+    for (int k0 = 0; k0 < a.K; k0 += BK) {
+        __syncthreads();      // the previous chunk's reads are done
+        store();
         __syncthreads();
+        if (k0 + BK < a.K) load(k0 + BK);
+#pragma unroll
         for (int kk = 0; kk < BK; kk += 2) {
             const int kc = kk + kh;
-            T are[2], aim[2], bv[2];
-            for (int t = 0; t < 2; ++t) {
-                const V av = As[wr + 16 * t + lr][kc];
-                are[t] = comp ? -av.y : av.x;
-                aim[t] = comp ? av.x : av.y;
-                const V bb = Bs[kc][wc + 16 * t + lr];
-                bv[t] = comp ? bb.y : bb.x;
+            T are[TM], aim[TM], bv[2];
+#pragma unroll
+            for (int t = 0; t < TM; ++t) {
+                const V av = Ap[comp][wr + 16 * t + lr][kc];
+                are[t] = av.x;
+                aim[t] = av.y;
             }
-            for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) bv[t] = Bp[comp][kc][wc + 16 * t + lr];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     re[i][j] = mfma16(are[i], bv[j], re[i][j]);
                     im[i][j] = mfma16(aim[i], bv[j], im[i][j]);
@@ -159,7 +198,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(CgArgs a) {
         if (col >= a.N) continue;
         double2 gc{0.0, 0.0};
         if (GEPI) gc = a.g0[col];
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TM; ++i)
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wr + 16 * i + 4 * slot + r;
                 if (row >= a.M) continue;
@@ -191,6 +230,7 @@ template <typename T>
 hipError_t run_gsigma(const GsShape &s, const double *tau, const int32_t *site, const void *M, void *G, void *ws,
                       hipStream_t st) {
     using V = typename Cx2<T>::V;
+    constexpr int kTM = sizeof(T) == 4 ? 4 : 2, kBM = 32 * kTM;   // FP64: registers and LDS allow 64-row blocks
     const int64_t per_e = (int64_t)s.ng * s.n;
     double2 *g0 = static_cast<double2 *>(ws);
     V *E = reinterpret_cast<V *>(g0 + s.ng);
@@ -208,7 +248,7 @@ hipError_t run_gsigma(const GsShape &s, const double *tau, const int32_t *site, 
         a1.sA = per_e; a1.sB = (int64_t)s.n * s.n; a1.sC = per_e;
         a1.lda = s.n; a1.ldb = s.n; a1.ldc = s.n;
         a1.M = s.ng; a1.N = s.n; a1.K = s.n; a1.scale = 1.0;
-        hipLaunchKernelGGL((cgemm_kernel<T, false, false>), dim3((s.n + BN - 1) / BN, (s.ng + BM - 1) / BM, s.count),
+        hipLaunchKernelGGL((cgemm_kernel<T, false, false, kTM>), dim3((s.n + BN - 1) / BN, (s.ng + kBM - 1) / kBM, s.count),
                            dim3(256), 0, st, a1);
         if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     }
@@ -218,7 +258,7 @@ hipError_t run_gsigma(const GsShape &s, const double *tau, const int32_t *site, 
     a2.lda = s.n; a2.ldb = s.n; a2.ldc = s.ng;
     a2.M = s.ng; a2.N = s.ng; a2.K = s.n; a2.scale = 1.0 / (s.beta * s.nc);
     // n = 0 still writes G = diag(g0) (the k loop is empty)
-    hipLaunchKernelGGL((cgemm_kernel<T, true, true>), dim3((s.ng + BN - 1) / BN, (s.ng + BM - 1) / BM, s.count),
+    hipLaunchKernelGGL((cgemm_kernel<T, true, true, kTM>), dim3((s.ng + BN - 1) / BN, (s.ng + kBM - 1) / kBM, s.count),
                        dim3(256), 0, st, a2);
     return hipGetLastError();
 }
