@@ -448,7 +448,13 @@ int g4_accumulate_mo(int32_t lx, int32_t ly, int32_t nw, int32_t nwex, int32_t n
  * the run). */
 void g4_destroy(g4_slice *h);
 
-/* Message of the last failing call on this host thread ("" if none).
+/* Environment: G4_LOG=1 prints one line on stderr whenever a slice installs
+ * a plan (init, g4_set_plan, g4_autotune); G4_AUTOTUNE_CACHE names the
+ * autotuner's cache file; each pass of g4_accumulate is a roctx range
+ * ("g4 pass: ...", seen by rocprofv3 --marker-trace) when the roctx library
+ * is present, G4_ROCTX=0 turns the ranges off.
+ *
+ * Message of the last failing call on this host thread ("" if none).
  * Paper: no passage (error reporting of this interface only). */
 const char *g4_last_error(void);
 

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -32,6 +34,37 @@ int fail(int code, const char *fmt, ...) {
     va_end(ap);
     return code;
 }
+
+// Named ranges for rocprofv3 --marker-trace: the roctx library is opened at
+// the first pass (dlopen, so the library does not depend on it); absent, or
+// with G4_ROCTX=0, the ranges cost nothing.
+struct RoctxApi {
+    int (*push)(const char *);
+    int (*pop)();
+};
+const RoctxApi &roctx_api() {
+    static const RoctxApi api = [] {
+        RoctxApi a{nullptr, nullptr};
+        const char *e = std::getenv("G4_ROCTX");
+        if (e && e[0] == '0') return a;
+        if (void *lib = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL)) {
+            a.push = reinterpret_cast<int (*)(const char *)>(dlsym(lib, "roctxRangePushA"));
+            a.pop = reinterpret_cast<int (*)()>(dlsym(lib, "roctxRangePop"));
+            if (!a.push || !a.pop) a = RoctxApi{nullptr, nullptr};
+        }
+        return a;
+    }();
+    return api;
+}
+struct RoctxRange {
+    bool on;
+    explicit RoctxRange(const char *name) : on(roctx_api().push != nullptr) {
+        if (on) roctx_api().push(name);
+    }
+    ~RoctxRange() {
+        if (on) roctx_api().pop();
+    }
+};
 
 constexpr int kMaxNw = 256;      // one K1 row per lane group of a 256-thread block
 constexpr int kMaxBatch = 256;
@@ -473,6 +506,20 @@ int channel_slot(uint32_t channel) {
     }
 }
 
+// G4_LOG=1: one line on stderr whenever a plan is installed.
+void log_plan(const g4_slice *h, const char *why) {
+    const char *e = std::getenv("G4_LOG");
+    if (!e || !e[0] || e[0] == '0') return;
+    const Plan &P = h->P;
+    static const char *names[] = {"valu", "mfma-direct", "packed", "packed-deep", "packed-mfma-direct"};
+    std::fprintf(stderr,
+                 "g4: %s: channels 0x%x, %llu entries per channel, kind %d, variant %s, tile %d, pass %d, "
+                 "rows/thread %d, plane group %d, %d work tiles, %llu device bytes\n",
+                 why, h->cfg.channels, (unsigned long long)P.entries, P.kind,
+                 P.variant >= 0 && P.variant <= 4 ? names[P.variant] : "?", P.tile, P.batch, P.ept, P.mgroup,
+                 h->nitems, (unsigned long long)P.total_bytes);
+}
+
 void drop_graphs(g4_slice *h) {
     for (auto &g : h->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -728,6 +775,9 @@ int graph_entry(g4_slice *h, const void *pu, const void *pd, int nb, g4_slice::G
 // directly, the second records); the weights are uploaded before the launch.
 int run_pass(g4_slice *h, const char *gu, const char *gd, const double *sign, int b0, int nb) {
     const Plan &P = h->P;
+    char range[96];
+    std::snprintf(range, sizeof(range), "g4 pass: %d measurements, variant %d, tile %d", nb, P.variant, P.tile);
+    const RoctxRange rr(range);
     const size_t in_el = h->cfg.g_in == G4_IN_C128 ? 16 : 8;
     const int64_t per = (int64_t)P.d.ng * P.d.ng;
     const void *pu = gu + (size_t)b0 * per * in_el;
@@ -1061,6 +1111,7 @@ int g4_init_slice(const g4_config *cfg, g4_slice **out) {
     }
     *out = h;
     g_err[0] = 0;
+    log_plan(h, "init");
     return G4_OK;
 }
 
@@ -1243,7 +1294,9 @@ int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     h->P.batch = batch ? batch : keep_batch;
     h->cfg.tile = c.tile;
     h->cfg.flags = c.flags;
-    return rebuild_work(h);
+    rc = rebuild_work(h);
+    if (rc == G4_OK) log_plan(h, "set_plan");
+    return rc;
 }
 
 }  // extern "C"
@@ -1511,6 +1564,7 @@ int g4_autotune(g4_slice *h, const void *G_up, const void *G_dn, const double *s
           << res.ms_per_measurement << "\n";
     }
     if (out) *out = res;
+    log_plan(h, from_cache ? "autotune (cached choice)" : "autotune");
     return G4_OK;
 }
 
