@@ -9,10 +9,11 @@ definition
 (PH magnetic/charge: direct minus exchange Wick terms; the spin-resolved PH
 channels: longitudinal up-up, longitudinal up-down, transverse; PP: the
 paper's Eq. (1) with K3 -> Q, and its singlet and triplet projections), the G elements being regenerated one by one from their
-Philox counters by the seeded input generator.  Index arithmetic is done on
-cluster coordinates and integer Matsubara labels, as in the C oracle: momenta
-add coordinate-wise modulo the cluster, w_n + nu_m = w_{n+m},
-nu_m - w_n = w_{m-n-1}.  Measurements are summed in order.
+Philox counters by the seeded input generator (a chunk of measurements at a
+time).  Index arithmetic is done on cluster coordinates and integer Matsubara
+labels, as in the C oracle: momenta add coordinate-wise modulo the cluster,
+w_n + nu_m = w_{n+m}, nu_m - w_n = w_{m-n-1}.  Measurements are summed in
+order.
 """
 from __future__ import annotations
 
@@ -72,53 +73,46 @@ def entries(w: Workload, channel: int, idx, b0: int = 0, count: int = None,
     r_k1 = _g_index(w, k1, n1)
     r_k2 = _g_index(w, k2, n2)
     out = np.zeros(len(iQ), dtype=np.complex128)
-    if channel in (PH_MAGNETIC, PH_CHARGE):
+    if channel in (PH_MAGNETIC, PH_CHARGE, PH_LONG_UPUP, PH_LONG_UPDOWN, PH_TRANSVERSE):
         r_k1q = _g_index(w, _mom_add(w, k1, q), n1 + m)
         r_k2q = _g_index(w, _mom_add(w, k2, q), n2 + m)
-        pm = -1.0 if channel == PH_MAGNETIC else 1.0
-        for j in range(count):
-            b = b0 + j
-            u1, d1 = g_elements(w, b, 0, r_k1q, r_k1), g_elements(w, b, 1, r_k1q, r_k1)
-            u2, d2 = g_elements(w, b, 0, r_k2, r_k2q), g_elements(w, b, 1, r_k2, r_k2q)
-            direct = (u1 + pm * d1) * (u2 + pm * d2)
-            ex = (g_elements(w, b, 0, r_k2, r_k1) * g_elements(w, b, 0, r_k1q, r_k2q)
-                  + g_elements(w, b, 1, r_k2, r_k1) * g_elements(w, b, 1, r_k1q, r_k2q))
-            out += sign[j] * (direct - ex)
-    elif channel in (PH_LONG_UPUP, PH_LONG_UPDOWN, PH_TRANSVERSE):
-        r_k1q = _g_index(w, _mom_add(w, k1, q), n1 + m)
-        r_k2q = _g_index(w, _mom_add(w, k2, q), n2 + m)
-        for j in range(count):
-            b = b0 + j
-            if channel == PH_LONG_UPUP:
-                t = (g_elements(w, b, 0, r_k1q, r_k1) * g_elements(w, b, 0, r_k2, r_k2q)
-                     - g_elements(w, b, 0, r_k2, r_k1) * g_elements(w, b, 0, r_k1q, r_k2q))
-            elif channel == PH_LONG_UPDOWN:
-                t = g_elements(w, b, 0, r_k1q, r_k1) * g_elements(w, b, 1, r_k2, r_k2q)
-            else:
-                t = -(g_elements(w, b, 1, r_k2, r_k1) * g_elements(w, b, 0, r_k1q, r_k2q)
-                      + g_elements(w, b, 0, r_k2, r_k1) * g_elements(w, b, 1, r_k1q, r_k2q))
-            out += sign[j] * t
-    elif channel == PP_UPDOWN:
+    elif channel in (PP_UPDOWN, PP_SINGLET, PP_TRIPLET):
         r_qk1 = _g_index(w, _mom_sub(w, q, k1), m - n1 - 1)
         r_qk2 = _g_index(w, _mom_sub(w, q, k2), m - n2 - 1)
-        for j in range(count):
-            b = b0 + j
-            t = (g_elements(w, b, 0, r_qk2, r_qk1) * g_elements(w, b, 1, r_k2, r_k1)
-                 + g_elements(w, b, 1, r_qk2, r_qk1) * g_elements(w, b, 0, r_k2, r_k1))
-            out += sign[j] * t
-    elif channel in (PP_SINGLET, PP_TRIPLET):
-        r_qk1 = _g_index(w, _mom_sub(w, q, k1), m - n1 - 1)
-        r_qk2 = _g_index(w, _mom_sub(w, q, k2), m - n2 - 1)
-        pm = 1.0 if channel == PP_SINGLET else -1.0
-        for j in range(count):
-            b = b0 + j
-            same = (g_elements(w, b, 0, r_qk2, r_qk1) * g_elements(w, b, 1, r_k2, r_k1)
-                    + g_elements(w, b, 1, r_qk2, r_qk1) * g_elements(w, b, 0, r_k2, r_k1))
-            crossed = (g_elements(w, b, 0, r_qk2, r_k1) * g_elements(w, b, 1, r_k2, r_qk1)
-                       + g_elements(w, b, 1, r_qk2, r_k1) * g_elements(w, b, 0, r_k2, r_qk1))
-            out += sign[j] * 0.5 * (same + pm * crossed)
     else:
         raise ValueError("unknown channel")
+
+    def terms(b):
+        """T_channel of measurements b (column) at every sampled entry (row
+        vectors of indices): one row per measurement."""
+        G = lambda spin, r, c: g_elements(w, b, spin, r[None, :], c[None, :])
+        if channel in (PH_MAGNETIC, PH_CHARGE):
+            pm = -1.0 if channel == PH_MAGNETIC else 1.0
+            u1, d1 = G(0, r_k1q, r_k1), G(1, r_k1q, r_k1)
+            u2, d2 = G(0, r_k2, r_k2q), G(1, r_k2, r_k2q)
+            direct = (u1 + pm * d1) * (u2 + pm * d2)
+            ex = G(0, r_k2, r_k1) * G(0, r_k1q, r_k2q) + G(1, r_k2, r_k1) * G(1, r_k1q, r_k2q)
+            return direct - ex
+        if channel == PH_LONG_UPUP:
+            return G(0, r_k1q, r_k1) * G(0, r_k2, r_k2q) - G(0, r_k2, r_k1) * G(0, r_k1q, r_k2q)
+        if channel == PH_LONG_UPDOWN:
+            return G(0, r_k1q, r_k1) * G(1, r_k2, r_k2q)
+        if channel == PH_TRANSVERSE:
+            return -(G(1, r_k2, r_k1) * G(0, r_k1q, r_k2q) + G(0, r_k2, r_k1) * G(1, r_k1q, r_k2q))
+        same = G(0, r_qk2, r_qk1) * G(1, r_k2, r_k1) + G(1, r_qk2, r_qk1) * G(0, r_k2, r_k1)
+        if channel == PP_UPDOWN:
+            return same
+        pm = 1.0 if channel == PP_SINGLET else -1.0
+        crossed = G(0, r_qk2, r_k1) * G(1, r_k2, r_qk1) + G(1, r_qk2, r_k1) * G(0, r_k2, r_qk1)
+        return 0.5 * (same + pm * crossed)
+
+    # measurements regenerated in chunks (vectorised), summed one by one in order
+    chunk = max(1, min(count, (1 << 20) // max(1, len(iQ))))
+    for j0 in range(0, count, chunk):
+        nb = min(chunk, count - j0)
+        t = terms(np.arange(b0 + j0, b0 + j0 + nb, dtype=np.int64)[:, None])
+        for j in range(nb):
+            out += sign[j0 + j] * t[j]
     return out
 
 

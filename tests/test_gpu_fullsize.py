@@ -147,11 +147,12 @@ def test_three_channel_quarter_slice(prod, bar):
 
 
 def test_long_run_stability():
-    """30,000 measurements at the tiny shapes, one per pass: the compensated float
-    accumulator stays at the FP32 product error while the plain float one drifts."""
+    """100,000 measurements at the tiny shapes, one per pass: the compensated
+    float accumulator stays at the FP32 product error while the plain float one
+    drifts."""
     g4 = g4mod()
     w = C1_TINY
-    M = 30000
+    M = 100000
     gu, gd = device_g(w, 1, 0, M)
     s = signs(w, 0, M)
     idx = sampled.sample_indices(w, 48, seed=5)
