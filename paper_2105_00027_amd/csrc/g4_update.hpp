@@ -493,16 +493,29 @@ __global__ __launch_bounds__(NT, KindInfo<KIND>::waves) void update_kernel(Updat
             } else if (CI::ph) {
                 V yu, yd;
                 t.y_at(i2l, i1, m, yu, yd);
-                if (CI::mag) {
+                if constexpr (CI::mag && CI::chg) {
+                    // both PH channels share the exchange sum: computed once
+                    V ex = cmul(xu[j], yu);
+                    cmac(ex, xd[j], yd);
                     cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
-                    cmac(acc[0][j][m], xu[j], yu);
-                    cmac(acc[0][j][m], xd[j], yd);
-                }
-                if (CI::chg) {
+                    acc[0][j][m].x += ex.x;
+                    acc[0][j][m].y += ex.y;
                     const int sm = CI::slot_chg * M + m;
                     cmac(acc[CI::slot_chg][j][m], ld(At + sm * nw + i1), ld(Bt + sm * T2 + i2l));
-                    cmac(acc[CI::slot_chg][j][m], xu[j], yu);
-                    cmac(acc[CI::slot_chg][j][m], xd[j], yd);
+                    acc[CI::slot_chg][j][m].x += ex.x;
+                    acc[CI::slot_chg][j][m].y += ex.y;
+                } else {
+                    if (CI::mag) {
+                        cmac(acc[0][j][m], ld(At + m * nw + i1), ld(Bt + m * T2 + i2l));
+                        cmac(acc[0][j][m], xu[j], yu);
+                        cmac(acc[0][j][m], xd[j], yd);
+                    }
+                    if (CI::chg) {
+                        const int sm = CI::slot_chg * M + m;
+                        cmac(acc[CI::slot_chg][j][m], ld(At + sm * nw + i1), ld(Bt + sm * T2 + i2l));
+                        cmac(acc[CI::slot_chg][j][m], xu[j], yu);
+                        cmac(acc[CI::slot_chg][j][m], xd[j], yd);
+                    }
                 }
             }
             if (CI::pp) {

@@ -345,15 +345,25 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
                         if (!F && !(m < M && r0 + j * RP < T2)) return;
                         if (CI::ph) {
                             const V yu{o.y[j].x, o.y[j].y}, yd{o.y[j].z, o.y[j].w};
-                            static_for<0, CI::nph>([&](auto c) {
-                                V &r = acc[c][j][m];
+                            if constexpr (CI::nph == 1) {
+                                V &r = acc[0][j][m];
                                 V av;
                                 if constexpr (AR) av = ar[m];
-                                else av = o.a[c];
-                                cmac(r, av, o.bb[c][j]);
+                                else av = o.a[0];
+                                cmac(r, av, o.bb[0][j]);
                                 cmac(r, xu[j], yu);
                                 cmac(r, xd[j], yd);
-                            });
+                            } else {
+                                // magnetic and charge share the exchange sum: computed once
+                                V ex = cmul(xu[j], yu);
+                                cmac(ex, xd[j], yd);
+                                static_for<0, CI::nph>([&](auto c) {
+                                    V &r = acc[c][j][m];
+                                    cmac(r, o.a[c], o.bb[c][j]);
+                                    r.x += ex.x;
+                                    r.y += ex.y;
+                                });
+                            }
                         }
                         if (CI::pp) {
                             const V zu{o.z[j].x, o.z[j].y}, zd{o.z[j].z, o.z[j].w};
