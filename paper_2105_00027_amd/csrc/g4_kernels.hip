@@ -84,8 +84,13 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
 __global__ __launch_bounds__(256) void pack_gather_kernel(PackArgs pa) {
     const GatherArgs &a = pa.g;
     const int64_t b = blockIdx.y;
-    const int R = blockIdx.x;
     const int ng = a.d.ng, nwg = a.d.nwg, nw = a.d.nw, nwex = a.d.nwex, nc = a.d.nc, n = a.d.n;
+    // Blocks are dealt to the 8 XCDs in turn; each XCD takes a contiguous run of
+    // rows, so the direct-vector elements that consecutive rows write into one
+    // cache line meet in the same L2 instead of leaving it as partial lines.
+    const int per = (ng + 7) / 8;
+    const int R = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (R >= ng) return;
     const float2 *su = static_cast<const float2 *>(a.gu) + b * a.g_stride + (int64_t)R * ng;
     const float2 *sd = static_cast<const float2 *>(a.gd) + b * a.g_stride + (int64_t)R * ng;
     float4 *d = static_cast<float4 *>(pa.pack) + b * pa.pack_stride16 + (int64_t)R * pa.ldp;
@@ -438,7 +443,7 @@ hipError_t launch_pack_gather(const PackArgs &a, hipStream_t s) {
     if (a.pcb < a.g.d.nwg || a.pcb % 8 || a.ldp < a.g.d.nc * a.pcb + 1 || a.pack_stride16 < (int64_t)ng * a.ldp ||
         count > 65535)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(pack_gather_kernel, dim3(ng, count), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pack_gather_kernel, dim3(8 * ((ng + 7) / 8), count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
