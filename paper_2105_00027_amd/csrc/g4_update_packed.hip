@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
         // two-buffer form: this thread's G(K2,K1) values straight from the packed
         // block into registers, one measurement ahead (the loop waits for every
         // outstanding load before its barrier, so these add no wait)
-        float4 xr[EPT], xn[EPT];
+        float4 xr[EPT];
         // a block base common to the wave plus this lane's fixed byte offsets
         unsigned xoff[EPT];
         static_for<0, EPT>([&](auto j) {
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
             const char *blk = static_cast<const char *>(a.pack) + (int64_t)jb * a.pack_stride;
             static_for<0, EPT>([&](auto j) { dst[j] = *reinterpret_cast<const float4 *>(blk + xoff[j]); });
         };
-        static_for<0, EPT>([&](auto j) { xr[j] = xn[j] = float4{0.f, 0.f, 0.f, 0.f}; });
+        static_for<0, EPT>([&](auto j) { xr[j] = float4{0.f, 0.f, 0.f, 0.f}; });
         // AR: this thread's a(Q, K1) for the group's planes (clamped to the
         // group's last plane, whose values the partial path does not use)
         V ar[AR ? MG : 1], an[AR ? MG : 1];
@@ -287,6 +287,14 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
                                                       (int64_t)jb * a.pack_stride) + k1 * nw + i1;
             static_for<0, MG>([&](auto m) { dst[m] = pa[(int64_t)(p0 + min((int)m, M - 1)) * n]; });
         };
+        // a full tile's operands: this thread's byte offsets within a buffer;
+        // plane and row then add constants (compile-time when nw is), so each
+        // measurement costs one address add per operand
+        const int zcf = nw + MG - 1;
+        const unsigned fy = (unsigned)((i1 * pgf.ycs + r0) * 16);
+        const unsigned fz = (unsigned)((pgf.nY + (tile - 1 - r0) * zcf + nw - 1 - i1) * 16);
+        const unsigned fa = (unsigned)(pgf.nG * 16 + i1 * 8);
+        const unsigned fb = (unsigned)(pgf.nG * 16 + pgf.nA * 16 + r0 * 8);
         for (int b = 0; b < NB - 1 && b < a.batch; ++b) issue(b);
         if (!XL && act && a.batch > 0) load_x(0, xr);
         if constexpr (AR) {
@@ -297,7 +305,6 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
             wait_vm(S * (min(b + NB - 2, a.batch - 1) - b));
             __syncthreads();                 // b's copies landed everywhere; b-1's buffer is free
             if (b + NB - 1 < a.batch) issue(b + NB - 1);
-            if (!XL && act && b + 1 < a.batch) load_x(b + 1, xn);
             if constexpr (AR) {
                 if (act && b + 1 < a.batch) load_a(b + 1, an);
             }
@@ -313,6 +320,13 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
                 xu[j] = V{x.x * f, x.y * f};
                 xd[j] = V{x.z * f, x.w * f};
             });
+            // xr is consumed: the next measurement's G(K2,K1) goes straight into
+            // it (the last step reloads its own, in bounds, so that the load is
+            // unconditional and its registers stay the loop's)
+            if constexpr (!XL) {
+                __builtin_amdgcn_sched_barrier(0);
+                load_x(min(b + 1, a.batch - 1), xr);
+            }
             // The plane loop is software-pipelined by hand: the LDS operands of
             // plane m+1 are read into registers before the arithmetic of plane m,
             // so the LDS latency is covered by that arithmetic even at two
@@ -331,6 +345,24 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
                 const V *At = reinterpret_cast<const V *>(L + g.nG);
                 const V *Bt = At + 2 * g.nA;
                 auto load = [&](int m, Ops &o) __attribute__((always_inline)) {
+                    if constexpr (F) {
+                        const unsigned char *lb = smem_raw + (b % NB) * bufb;
+                        static_for<0, EPT>([&](auto j) {
+                            const int rj = NWC ? j * (NTH / (NWC ? NWC : NTH)) : j * RP;
+                            if (CI::ph)
+                                o.y[j] = *reinterpret_cast<const float4 *>(lb + fy + (m * (g.ycs + 1) + rj) * 16);
+                            if (CI::pp)
+                                o.z[j] = *reinterpret_cast<const float4 *>(lb + fz + (m * (zcx + 1) - rj * zcx) * 16);
+                            static_for<0, CI::nph>([&](auto c) {
+                                o.bb[c][j] = ld(reinterpret_cast<const V *>(lb + fb + ((c * MG + m) * tile + rj) * 8));
+                            });
+                        });
+                        if constexpr (!AR)
+                            static_for<0, CI::nph>([&](auto c) {
+                                o.a[c] = ld(reinterpret_cast<const V *>(lb + fa + (c * MG + m) * nw * 8));
+                            });
+                        return;
+                    }
                     const int mm = F ? m : min(m, M - 1);
                     static_for<0, EPT>([&](auto j) {
                         const int i2l = F ? r0 + j * RP : min(r0 + j * RP, T2 - 1);
@@ -392,7 +424,6 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
             };
             if (full && r0 + (EPT - 1) * RP < T2) run(std::true_type{});
             else run(std::false_type{});
-            if (!XL) static_for<0, EPT>([&](auto j) { xr[j] = xn[j]; });
             if constexpr (AR) static_for<0, MG>([&](auto m) { ar[m] = an[m]; });
         }
         if (!act) continue;
