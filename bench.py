@@ -101,6 +101,9 @@ def roofline(E, ng, B, g_bytes, acc_bytes, channels, launch_s, variant=0, direct
         a = fl_direct / launch_s / 1e12
         out["mfma_direct"] = {"achieved": a, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s",
                               "frac": a / (MFMA_F32_PEAK / 1e12), "flops_per_launch": fl_direct}
+        # every term's flops against the vector peak: the figure a plan with the
+        # direct term on the VALU reports as its frac, for comparison
+        out["all_flops_vs_valu_peak"] = fl / launch_s / ALU_PEAK
     return out
 
 

@@ -446,43 +446,47 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
 // Packed operands with the PH direct term on the matrix cores: nw = 64, 8-row
 // tiles, plane groups of MG = 4 or 8, PH channels.  Same copies into LDS as
 // the packed kernel (buffer layout, copy-slot table, G(K2,K1) read into
-// registers one measurement ahead, three blocks per CU), different thread
-// mapping: wave w owns K1 columns 16w..16w+15 of the tile; in lane l (group
-// g = l/16, column cc = l%16) it holds K2 rows 4(g%2)..4(g%2)+3 of plane
-// 2p + g/2 for every plane pair p, which is the output layout of
-// v_mfma_f32_16x16x4f32 when its 16 rows are (8 K2 rows) x (2 planes of a
-// pair).  Per pair and measurement two MFMAs add the complex rank-1 update
-// D(K2, K1) += b(Q, K2) a(Q, K1) of both planes (sign folded into a):
-//   k slot (member, component) of A row (row, member'): b_component(plane of
-//   member, row) when member == member', else 0 (block diagonal);
-//   Re: B = (Re a, -Im a) by component, Im: B = (Im a, Re a);
-// so no k slot holds padding and the VALU only does the exchange Hadamard
-// sum, added into the same registers.  With both PH channels the exchange is
-// computed once and added to each.
+// registers one measurement ahead, three blocks per CU) and the same vector
+// mapping for the exchange term: lane l owns K1 column l of the tile, wave w
+// K2 rows w and w + 4, every plane.  The vector units only do the exchange
+// Hadamard sum, once for both PH channels.  The direct term
+// D(K2, K1) += b(Q, K2) a(Q, K1) (sign folded into a) of each channel runs on
+// v_mfma_f32_4x4x1_16b_f32: sixteen 4x4 rank-1 updates per instruction, block
+// l/4 holding K1 columns 4(l/4)..4(l/4)+3, so that lane l again owns column l,
+// here of K2 rows 4(w%2)..4(w%2)+3 (its four result registers) and of planes
+// (MG/2)(w/2)..(MG/2)(w/2)+MG/2-1.  A complex update is four real ones:
+//   Re D += Re b Re a, Re D += (-Im b) Im a, Im D += Re b Im a, Im D += Im b Re a.
+// After the pass's last measurement the matrix-core sums go through LDS (the
+// staging buffers are free then) into the exchange layout and each channel's
+// accumulator entry is read, updated and written once.
 template <int MG, int CH>
 __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kernel(UpdateArgs a) {
     using V = float2;
     using CI = ChanInfo<CH>;
     static_assert(CI::ph && !CI::pp, "PH channels only");
-    static_assert(MG == 4 || MG == 8, "plane pairs");
+    static_assert(MG == 4 || MG == 8, "plane groups of 4 or 8");
     typedef float f4 __attribute__((ext_vector_type(4)));
-    constexpr int NTH = 256, NB = 2, TR = 8, NW = 64, NP = MG / 2;
+    constexpr int NTH = 256, NB = 2, TR = 8, NW = 64, EPT = 2, RP = 4, PW = MG / 2, NPH = CI::nph;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int l = tid & 63, g = l >> 4, cc = l & 15;
+    const int l = tid & 63;
+    const int r0 = wave;                                   // exchange: K2 rows r0, r0 + RP
+    const int rg = 4 * (wave & 1), pw0 = PW * (wave >> 1); // direct: K2 rows rg.., planes pw0..
     const int nwg = a.d.nwg, nc = a.d.nc, n = a.d.n;
-    const int i1 = 16 * wave + cc;        // K1 column of this lane (local frequency)
-    const int h = g >> 1;                 // pair member of this lane's outputs
-    const int rb = 4 * (g & 1);           // first of its four K2 rows
-    const int a_row = cc & 7, a_mem = cc >> 3;   // MFMA A row (cc): K2 row, pair member
-    const int k_mem = g >> 1, k_c = g & 1;       // MFMA k slot (g): pair member, component
     constexpr PackedGeom pgf = packed_geom(NW, TR, MG, CH, false);
     constexpr int S = (pgf.nbuf + NTH - 1) / NTH;
     static_assert(S <= kPackedSlots, "staging slots");
-    float *sg = reinterpret_cast<float *>(smem_raw + NB * S * NTH * 16);
+    constexpr int bufb = S * NTH * 16;
+    static_assert(TR * MG * NW * 8 <= NB * bufb, "the direct sums' transpose fits the staging buffers");
+    float *sg = reinterpret_cast<float *>(smem_raw + NB * bufb);
     if (tid < a.batch) sg[tid] = (float)a.sign[tid];
-    const float bsign = k_c ? -1.f : 1.f;
+    // this lane's byte offsets within a buffer: exchange block (plane m adds
+    // m (ycs + 1) chunks, row j adds RP), a(Q, K1) at column l and b(Q, K2) at
+    // row rg + l%4 of plane pw0 (channel c and plane p add (c MG + p) rows)
+    const unsigned fy = (unsigned)((l * pgf.ycs + r0) * 16);
+    const unsigned fa = (unsigned)(pgf.nG * 16 + (pw0 * NW + l) * 8);
+    const unsigned fb = (unsigned)(pgf.nG * 16 + pgf.nA * 16 + (pw0 * TR + rg + (l & 3)) * 8);
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         __syncthreads();   // a previous tile's LDS reads are done (the launch uses one block per tile)
@@ -494,129 +498,120 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
         const int rowX = k2 * nwg + c0, colX = k1 * a.pcb;
         unsigned off[S];
         packed_offsets_full<NTH, CH, S>(a, pgf, tid, q, k1, k2, c0, TR, M, MG, m_lo, p0, off);
-        const int bufb = S * NTH * 16;
         const unsigned lds0 = (unsigned)(uintptr_t)(lds_t *)smem_raw + wave * 64 * 16;
         auto issue = [&](int j) __attribute__((always_inline)) {
             const char *base = static_cast<const char *>(a.pack) + (int64_t)j * a.pack_stride;
             const unsigned buf = lds0 + (j % NB) * bufb;
             static_for<0, S>([&](auto k) { dma16(base, off[k], buf + k * NTH * 16); });
         };
-        f4 re[CI::nph][NP], im[CI::nph][NP];
-        static_for<0, CI::nph>([&](auto c) {
-            static_for<0, NP>([&](auto p) {
-                re[c][p] = f4{0.f, 0.f, 0.f, 0.f};
-                im[c][p] = f4{0.f, 0.f, 0.f, 0.f};
+        V ex[EPT][MG];
+        f4 dre[NPH][PW], dim[NPH][PW];
+        static_for<0, EPT>([&](auto j) { static_for<0, MG>([&](auto m) { ex[j][m] = V{0.f, 0.f}; }); });
+        static_for<0, NPH>([&](auto c) {
+            static_for<0, PW>([&](auto p) {
+                dre[c][p] = f4{0.f, 0.f, 0.f, 0.f};
+                dim[c][p] = f4{0.f, 0.f, 0.f, 0.f};
             });
         });
-        // G(K2,K1) at this lane's four rows, one measurement ahead: a block base
-        // common to the wave plus this lane's fixed byte offsets
-        float4 xr[4], xn[4];
-        unsigned xoff[4];
-        static_for<0, 4>([&](auto t) { xoff[t] = (unsigned)(((rowX + rb + t) * ldp + colX + i1) * 16); });
+        // G(K2,K1) at this lane's two rows, one measurement ahead
+        float4 xr[EPT];
+        unsigned xoff[EPT];
+        static_for<0, EPT>([&](auto j) { xoff[j] = (unsigned)(((rowX + r0 + j * RP) * ldp + colX + l) * 16); });
         auto load_x = [&](int jb, float4 *dst) __attribute__((always_inline)) {
             const char *blk = static_cast<const char *>(a.pack) + (int64_t)jb * a.pack_stride;
-            static_for<0, 4>([&](auto t) { dst[t] = *reinterpret_cast<const float4 *>(blk + xoff[t]); });
+            static_for<0, EPT>([&](auto j) { dst[j] = *reinterpret_cast<const float4 *>(blk + xoff[j]); });
         };
+        static_for<0, EPT>([&](auto j) { xr[j] = float4{0.f, 0.f, 0.f, 0.f}; });
         if (a.batch > 0) {
             issue(0);
             load_x(0, xr);
         }
-        // one measurement: its X values in cur, the next one's loaded into nxt
-        auto step = [&](int j, float4 (&cur)[4], float4 (&nxt)[4]) __attribute__((always_inline)) {
+        for (int b = 0; b < a.batch; ++b) {
             wait_vm(0);
-            __syncthreads();                 // j's copies landed everywhere; j-1's buffer is free
-            if (j + 1 < a.batch) {
-                issue(j + 1);
-                load_x(j + 1, nxt);
-            }
-            const float s = sg[j];
-            const unsigned char *L = smem_raw + (j % NB) * bufb;
-            // G(K2,K1) times -s_b in place (the PH exchange's minus folded in)
-            static_for<0, 4>([&](auto t) {
-                cur[t].x *= -s;
-                cur[t].y *= -s;
-                cur[t].z *= -s;
-                cur[t].w *= -s;
+            __syncthreads();                 // b's copies landed everywhere; b-1's buffer is free
+            if (b + 1 < a.batch) issue(b + 1);
+            const float s = sg[b];
+            // G(K2,K1) times -s_b (the PH exchange's minus folded in)
+            V xu[EPT], xd[EPT];
+            static_for<0, EPT>([&](auto j) {
+                xu[j] = V{xr[j].x * -s, xr[j].y * -s};
+                xd[j] = V{xr[j].z * -s, xr[j].w * -s};
             });
-            // a partial group was staged in the full layout (see packed_offsets_full)
-            const float4 *Ly = reinterpret_cast<const float4 *>(L);
-            const float *Af = reinterpret_cast<const float *>(L + pgf.nG * 16);   // a: [slot][plane][K1] complex
-            const float *Bf = Af + 4 * pgf.nA;                                     // b: [slot][plane][row] complex
-            struct Ops {
-                float4 y[4];
-                float av[CI::nph], br[CI::nph], bi[CI::nph];
+            // xr is consumed: the next measurement's G(K2,K1) goes straight into
+            // it (the last step reloads its own, in bounds)
+            __builtin_amdgcn_sched_barrier(0);
+            load_x(min(b + 1, a.batch - 1), xr);
+            const unsigned char *lb = smem_raw + (b & 1) * bufb;
+            struct MOps {
+                float ar[NPH], ai[NPH], br[NPH], bi[NPH];
             };
-            auto load = [&](int p, Ops &o) __attribute__((always_inline)) {
-                const int m = 2 * p + h;                 // this lane's output plane
-                static_for<0, 4>([&](auto t) { o.y[t] = Ly[(i1 + m) * pgf.ycs + rb + t + m]; });
-                static_for<0, CI::nph>([&](auto c) {
-                    const float *pbv = Bf + ((c * MG + 2 * p + a_mem) * TR + a_row) * 2 + k_c;
-                    o.av[c] = k_mem == a_mem ? *pbv : 0.f;     // block-diagonal A
-                    const float *pav = Af + ((c * MG + 2 * p + k_mem) * NW + i1) * 2;
-                    o.br[c] = pav[k_c];
-                    o.bi[c] = pav[1 - k_c];
+            auto load_m = [&](int p, MOps &o) __attribute__((always_inline)) {
+                static_for<0, NPH>([&](auto c) {
+                    const V av = ld(reinterpret_cast<const V *>(lb + fa + (c * MG + p) * NW * 8));
+                    const V bv = ld(reinterpret_cast<const V *>(lb + fb + (c * MG + p) * TR * 8));
+                    o.ar[c] = av.x;
+                    o.ai[c] = av.y;
+                    o.br[c] = bv.x;
+                    o.bi[c] = bv.y;
                 });
             };
-            auto exchange = [&](auto p, const Ops &o) __attribute__((always_inline)) {
-                // exchange: sum over spins of G(K2,K1) G(K1+Q,K2+Q), on the VALU;
-                // straight into the accumulator of one channel, or once for both
-                static_for<0, 4>([&](auto t) {
-                    const V xu{cur[t].x, cur[t].y}, xd{cur[t].z, cur[t].w};
-                    if constexpr (CI::nph == 1) {
-                        V acc{re[0][p][t()], im[0][p][t()]};
-                        cmac(acc, xu, V{o.y[t].x, o.y[t].y});
-                        cmac(acc, xd, V{o.y[t].z, o.y[t].w});
-                        re[0][p][t()] = acc.x;
-                        im[0][p][t()] = acc.y;
+            auto load_y = [&](int m, float4 (&y)[EPT]) __attribute__((always_inline)) {
+                static_for<0, EPT>([&](auto j) {
+                    y[j] = *reinterpret_cast<const float4 *>(lb + fy + (m * (pgf.ycs + 1) + j * RP) * 16);
+                });
+            };
+            // plane m+1's exchange operands, and plane group p+1's matrix-core
+            // operands, are read before plane m's arithmetic
+            float4 y[2][EPT];
+            MOps mo[2];
+            load_m(0, mo[0]);
+            load_y(0, y[0]);
+            static_for<0, MG>([&](auto m) {
+                constexpr int p = m / 2;
+                if constexpr (m + 1 < MG) load_y(m + 1, y[(m + 1) & 1]);
+                if constexpr (m % 2 == 0 && p + 1 < PW) load_m(p + 1, mo[(p + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                static_for<0, EPT>([&](auto j) {
+                    const float4 &yv = y[m & 1][j];
+                    cmac(ex[j][m], xu[j], V{yv.x, yv.y});
+                    cmac(ex[j][m], xd[j], V{yv.z, yv.w});
+                });
+                const MOps &o = mo[p & 1];
+                static_for<0, NPH>([&](auto c) {
+                    if constexpr (m % 2 == 0) {
+                        dre[c][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.br[c], o.ar[c], dre[c][p], 0, 0, 0);
+                        dim[c][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.br[c], o.ai[c], dim[c][p], 0, 0, 0);
                     } else {
-                        V ex = cmul(xu, V{o.y[t].x, o.y[t].y});
-                        cmac(ex, xd, V{o.y[t].z, o.y[t].w});
-                        static_for<0, CI::nph>([&](auto c) {
-                            re[c][p][t()] += ex.x;
-                            im[c][p][t()] += ex.y;
-                        });
+                        dre[c][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(-o.bi[c], o.ai[c], dre[c][p], 0, 0, 0);
+                        dim[c][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.bi[c], o.ar[c], dim[c][p], 0, 0, 0);
                     }
                 });
-            };
-            auto direct = [&](auto p, const Ops &o) __attribute__((always_inline)) {
-                // direct: b(Q,K2) a(Q,K1) of both planes of the pair on the matrix cores
-                static_for<0, CI::nph>([&](auto c) {
-                    re[c][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.av[c], bsign * o.br[c], re[c][p], 0, 0, 0);
-                    im[c][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.av[c], o.bi[c], im[c][p], 0, 0, 0);
-                });
-            };
-            // pair p+1's LDS operands are read before pair p's arithmetic
-            Ops o[2];
-            load(0, o[0]);
-            static_for<0, NP>([&](auto p) {
-                if constexpr (p + 1 < NP) load(p + 1, o[(p + 1) & 1]);
-                __builtin_amdgcn_sched_barrier(0);
-                exchange(p, o[p & 1]);
-                direct(p, o[p & 1]);
                 __builtin_amdgcn_sched_barrier(0);
             });
-        };
-        // X registers alternate between xr and xn (no copies between steps)
-        int j = 0;
-        for (; j + 1 < a.batch; j += 2) {
-            step(j, xr, xn);
-            step(j + 1, xn, xr);
         }
-        if (j < a.batch) step(j, xr, xn);
+        // the direct sums into the exchange layout through LDS, one channel at a
+        // time: T[K2 row][plane][K1 column]
         const int64_t nn = (int64_t)n * n;
-        const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * NW * NW + (int64_t)(c0 + rb) * NW + i1;
-        // one pair at a time, so that the accumulator reads in flight stay few
-        static_for<0, NP>([&](auto p) {
-            const int m = 2 * p + h;
-            if (m < M) {
-                static_for<0, 4>([&](auto t) {
-                    const int64_t e = ebase + m * nn + (int64_t)t * NW;
-                    if (CI::mag) acc_update(a.acc[0], a.acc_kind, e, V{re[0][p][t()], im[0][p][t()]});
-                    if (CI::chg)
-                        acc_update(a.acc[1], a.acc_kind, e, V{re[CI::slot_chg][p][t()], im[CI::slot_chg][p][t()]});
+        const int64_t ebase = (((int64_t)p0 * nc + k2) * nc + k1) * NW * NW + (int64_t)(c0 + r0) * NW + l;
+        V *T = reinterpret_cast<V *>(smem_raw);
+        static_for<0, NPH>([&](auto c) {
+            __syncthreads();                 // the buffers (or the previous channel's T) are free
+            static_for<0, PW>([&](auto p) {
+                static_for<0, 4>([&](auto r) {
+                    T[((rg + r) * MG + pw0 + p) * NW + l] = V{dre[c][p][r()], dim[c][p][r()]};
                 });
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            });
+            __syncthreads();
+            static_for<0, EPT>([&](auto j) {
+                static_for<0, MG>([&](auto m) {
+                    if (m < M) {
+                        const V d = T[((r0 + j * RP) * MG + m) * NW + l];
+                        const int64_t e = ebase + m * nn + (int64_t)j * RP * NW;
+                        const V v{ex[j][m].x + d.x, ex[j][m].y + d.y};
+                        acc_update(a.acc[(c == 0 && CI::mag) ? 0 : 1], a.acc_kind, e, v);
+                    }
+                });
+            });
         });
     }
 }
