@@ -15,12 +15,13 @@
 // and keeps the sums over the measurements in registers, then reads, adds and
 // writes each entry once.  For nb <= 4 (mo_rows_kernel) a thread owns one
 // column (K1, b1, b2) of one (plane, K2) and all nb^2 rows (b3, b4): per
-// measurement it loads the column's a = G(K1+Q b1, K1 b2) once, the nb
+// measurement it loads the column's a = G(K1+Q b1, K1 b2) once and the nb
 // exchange operands of each side (G(K2 b3, K1 b2) and G(K1+Q b1, K2+Q b4):
-// one per b3, one per b4), and the nb^2 values b = G(K2 b3, K2+Q b4) that are
-// the same for every lane of the block, so about one vector load per entry
-// and measurement instead of eight; lanes run along the column, so each of
-// the nb^2 output rows is written as one contiguous run.  Larger nb takes the
+// one per b3, one per b4), about a quarter of a vector load per entry and
+// measurement instead of eight; the nb^2 values b = G(K2 b3, K2+Q b4) are
+// the same for the whole block (a block covers one (plane, K2) row), which
+// forms them once per launch into LDS.  Lanes run along the column, so each
+// of the nb^2 output rows is written as one contiguous run.  Larger nb takes the
 // one-thread-per-entry kernel (mo_kernel).  G elements come straight from
 // global memory (L2-resident across a plane's rows).  Momenta are added on
 // the lattice coordinates in the kernel (no tables).
@@ -37,7 +38,7 @@ namespace {
 constexpr int kMoPlanes = 256;   // planes per launch
 // measurements per launch: 32 keeps a launch's G (2 x 32 x 2.5 MB for the
 // 2x2 cluster with 4 orbitals) in the last-level cache; 64 per launch took
-// 4.71 ms per 64 measurements there, 32 4.37 ms, 16 5.04 ms
+// 3.27 ms per 64 measurements there, 32 3.18 ms
 constexpr int kMoBatch = 32;
 
 struct MoArgs {
@@ -123,20 +124,28 @@ __global__ __launch_bounds__(256) void mo_kernel(MoArgs a) {
     *pa = v;
 }
 
-// Thread (plane p, K2, column (K1, b1, b2)) for all (b3, b4); NB = nb.
+// Thread (plane p, K2, column (K1, b1, b2)) for all (b3, b4); NB = nb.  A
+// block covers up to 256 columns of one (plane, K2) row, so the row-side
+// direct operand b(Q; K2 b3, K2+Q b4) of every measurement is the same for
+// the whole block: the block forms it once per launch, weight and spin
+// combination folded in, into LDS, and the loop reads it from there.  The
+// weight of the exchange term is folded into G(K2 b3, K1 b2) as it arrives,
+// so each entry update is the twelve FMAs of its three complex products.
 template <typename R, int NB>
 __global__ __launch_bounds__(256) void mo_rows_kernel(MoArgs a) {
     using V = typename MoCx<R>::V;
+    __shared__ V bsh[kMoBatch][NB * NB];
     const int64_t side = a.side;                       // N NB^2
     const int64_t n = side / (NB * NB);
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t cols_per_row = side;
-    if (t >= (int64_t)a.planes * n * cols_per_row) return;
-    const int64_t col = t % cols_per_row, pk = t / cols_per_row;
-    const int K2 = (int)(pk % n), p = (int)(pk / n);
+    const int64_t bpr = (side + 255) / 256;            // blocks per (plane, K2) row
+    const int64_t rowi = blockIdx.x / bpr;
+    const int64_t col = (blockIdx.x % bpr) * 256 + threadIdx.x;
+    const bool act = col < side;
+    const int K2 = (int)(rowi % n), p = (int)(rowi / n);
     const int nw = a.nw, nwg = a.nwg, lx = a.lx, ly = a.ly;
     const int64_t ngb = a.ngb;
-    const int K1 = (int)(col / (NB * NB)), b1 = (int)((col / NB) % NB), b2 = (int)(col % NB);
+    const int64_t cl = act ? col : 0;
+    const int K1 = (int)(cl / (NB * NB)), b1 = (int)((cl / NB) % NB), b2 = (int)(cl % NB);
     const int q = a.qm[p].x, m = a.qm[p].y;
     const int k1 = K1 / nw, i1 = K1 % nw, k2 = K2 / nw, i2 = K2 % nw;
     const int qx = q % lx, qy = q / lx;
@@ -146,73 +155,145 @@ __global__ __launch_bounds__(256) void mo_rows_kernel(MoArgs a) {
     const V *gu = static_cast<const V *>(a.gu);
     const V *gd = static_cast<const V *>(a.gd);
     R sr[NB][NB], si[NB][NB];
+#pragma unroll
     for (int i = 0; i < NB; ++i)
+#pragma unroll
         for (int j = 0; j < NB; ++j) sr[i][j] = si[i][j] = 0;
+    // Operands of one measurement, loaded one measurement ahead into the other
+    // of two register sets (the loop alternates them, so nothing is copied).
+    // Every product is added by a plain FMA: imaginary parts that enter with a
+    // minus sign are negated once per measurement.
+    struct Ops {
+        V au, ad;
+        V xu[NB], xd[NB], yu[NB], yd[NB];
+    };
+    auto run = [&](auto load, auto compute) __attribute__((always_inline)) {
+        if (!act || a.batch == 0) return;
+        Ops o0, o1;
+        load(0, o0);
+        int b = 0;
+        for (; b + 1 < a.batch; b += 2) {
+            load(b + 1, o1);
+            compute(b, o0);
+            load(min(b + 2, a.batch - 1), o0);
+            compute(b + 1, o1);
+        }
+        if (b < a.batch) compute(b, o0);
+    };
     if (a.channel == CH_PP) {
         const int w_qk1 = ksub(k1) * nwg + (m + nw - 1 - i1), w_qk2 = ksub(k2) * nwg + (m + nw - 1 - i2);
         const int w_k1 = k1 * nwg + i1, w_k2 = k2 * nwg + i2;
-        for (int b = 0; b < a.batch; ++b) {
-            const int64_t o = (int64_t)b * a.g_stride;
-            const R s = (R)a.sign[b];
-            V zu[NB], zd[NB], xu[NB], xd[NB];
+        const int64_t iz0 = gi(w_qk2, 0) * ngb + gi(w_qk1, b2);   // G(Q-K2 b4, Q-K1 b2) at b4 = 0 (yu, yd)
+        const int64_t ix0 = gi(w_k2, 0) * ngb + gi(w_k1, b1);     // G(K2 b3, K1 b1) at b3 = 0 (xu, xd)
+        auto load = [&](int b, Ops &o) __attribute__((always_inline)) {
+            const V *pu = gu + (int64_t)b * a.g_stride, *pd = gd + (int64_t)b * a.g_stride;
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {   // G(Q-K2 b4, Q-K1 b2), b4 = j
-                const int64_t i = o + gi(w_qk2, j) * ngb + gi(w_qk1, b2);
-                zu[j] = gu[i];
-                zd[j] = gd[i];
+            for (int j = 0; j < NB; ++j) {
+                o.yu[j] = pu[iz0 + j * ngb];
+                o.yd[j] = pd[iz0 + j * ngb];
+                o.xu[j] = pu[ix0 + j * ngb];
+                o.xd[j] = pd[ix0 + j * ngb];
             }
+        };
+        auto compute = [&](int b, const Ops &o) __attribute__((always_inline)) {
+            const R s = (R)a.sign[b];
+            // s G(Q-K2 b4, Q-K1 b2) and its negated imaginary part
+            R zur[NB], zui[NB], zun[NB], zdr[NB], zdi[NB], zdn[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {   // G(K2 b3, K1 b1), b3 = j
-                const int64_t i = o + gi(w_k2, j) * ngb + gi(w_k1, b1);
-                xu[j] = gu[i];
-                xd[j] = gd[i];
+            for (int j = 0; j < NB; ++j) {
+                zur[j] = s * o.yu[j].x;
+                zui[j] = s * o.yu[j].y;
+                zun[j] = -zui[j];
+                zdr[j] = s * o.yd[j].x;
+                zdi[j] = s * o.yd[j].y;
+                zdn[j] = -zdi[j];
             }
 #pragma unroll
             for (int b3 = 0; b3 < NB; ++b3)
 #pragma unroll
                 for (int b4 = 0; b4 < NB; ++b4) {
-                    const R tr = zu[b4].x * xd[b3].x - zu[b4].y * xd[b3].y + zd[b4].x * xu[b3].x - zd[b4].y * xu[b3].y;
-                    const R ti = zu[b4].x * xd[b3].y + zu[b4].y * xd[b3].x + zd[b4].x * xu[b3].y + zd[b4].y * xu[b3].x;
-                    sr[b3][b4] += s * tr;
-                    si[b3][b4] += s * ti;
+                    R r = sr[b3][b4], i = si[b3][b4];
+                    r += zur[b4] * o.xd[b3].x;
+                    r += zun[b4] * o.xd[b3].y;
+                    r += zdr[b4] * o.xu[b3].x;
+                    r += zdn[b4] * o.xu[b3].y;
+                    i += zur[b4] * o.xd[b3].y;
+                    i += zui[b4] * o.xd[b3].x;
+                    i += zdr[b4] * o.xu[b3].y;
+                    i += zdi[b4] * o.xu[b3].x;
+                    sr[b3][b4] = r;
+                    si[b3][b4] = i;
                 }
-        }
+        };
+        run(load, compute);
     } else {
         const R sg = a.channel == CH_MAG ? (R)-1 : (R)1;
         const int w_k1 = k1 * nwg + i1, w_k2 = k2 * nwg + i2;
         const int w_k1q = kadd(k1) * nwg + i1 + m, w_k2q = kadd(k2) * nwg + i2 + m;
-        for (int b = 0; b < a.batch; ++b) {
-            const int64_t o = (int64_t)b * a.g_stride;
+        // s_b (Gu -/+ Gd)(K2 b3, K2+Q b4) of every measurement of the launch
+        for (int t = threadIdx.x; t < a.batch * NB * NB; t += 256) {
+            const int b = t / (NB * NB), j = t % (NB * NB);
+            const int64_t ib = (int64_t)b * a.g_stride + gi(w_k2, j / NB) * ngb + gi(w_k2q, j % NB);
+            const V u = gu[ib], d = gd[ib];
             const R s = (R)a.sign[b];
-            const int64_t ia = o + gi(w_k1q, b1) * ngb + gi(w_k1, b2);          // G(K1+Q b1, K1 b2)
-            const V au = gu[ia], ad = gd[ia];
-            const R ar = au.x + sg * ad.x, ai = au.y + sg * ad.y;
-            V xu[NB], xd[NB], yu[NB], yd[NB];
+            bsh[b][j] = V{s * (u.x + sg * d.x), s * (u.y + sg * d.y)};
+        }
+        __syncthreads();
+        const int64_t ia = gi(w_k1q, b1) * ngb + gi(w_k1, b2);    // G(K1+Q b1, K1 b2)
+        const int64_t ix0 = gi(w_k2, 0) * ngb + gi(w_k1, b2);     // G(K2 b3, K1 b2) at b3 = 0
+        const int64_t iy0 = gi(w_k1q, b1) * ngb + gi(w_k2q, 0);   // G(K1+Q b1, K2+Q b4) at b4 = 0
+        auto load = [&](int b, Ops &o) __attribute__((always_inline)) {
+            const V *pu = gu + (int64_t)b * a.g_stride, *pd = gd + (int64_t)b * a.g_stride;
+            o.au = pu[ia];
+            o.ad = pd[ia];
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const int64_t ix = o + gi(w_k2, j) * ngb + gi(w_k1, b2);       // G(K2 b3, K1 b2), b3 = j
-                const int64_t iy = o + gi(w_k1q, b1) * ngb + gi(w_k2q, j);     // G(K1+Q b1, K2+Q b4), b4 = j
-                xu[j] = gu[ix];
-                xd[j] = gd[ix];
-                yu[j] = gu[iy];
-                yd[j] = gd[iy];
+                o.xu[j] = pu[ix0 + j * ngb];
+                o.xd[j] = pd[ix0 + j * ngb];
+                o.yu[j] = pu[iy0 + j];
+                o.yd[j] = pd[iy0 + j];
+            }
+        };
+        auto compute = [&](int b, const Ops &o) __attribute__((always_inline)) {
+            const R s = (R)a.sign[b];
+            const R ar = o.au.x + sg * o.ad.x, ai = o.au.y + sg * o.ad.y, an = -ai;
+            // -s G(K2 b3, K1 b2) (the exchange's minus and weight), and G(K1+Q b1,
+            // K2+Q b4) with its negated imaginary part
+            R xur[NB], xui[NB], xdr[NB], xdi[NB], yun[NB], ydn[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                xur[j] = -s * o.xu[j].x;
+                xui[j] = -s * o.xu[j].y;
+                xdr[j] = -s * o.xd[j].x;
+                xdi[j] = -s * o.xd[j].y;
+                yun[j] = -o.yu[j].y;
+                ydn[j] = -o.yd[j].y;
             }
 #pragma unroll
             for (int b3 = 0; b3 < NB; ++b3)
 #pragma unroll
                 for (int b4 = 0; b4 < NB; ++b4) {
-                    const int64_t ib = o + gi(w_k2, b3) * ngb + gi(w_k2q, b4);   // G(K2 b3, K2+Q b4): block-uniform
-                    const V bu = gu[ib], bd = gd[ib];
-                    const R br = bu.x + sg * bd.x, bi = bu.y + sg * bd.y;
-                    const R tr = ar * br - ai * bi - (xu[b3].x * yu[b4].x - xu[b3].y * yu[b4].y) -
-                                 (xd[b3].x * yd[b4].x - xd[b3].y * yd[b4].y);
-                    const R ti = ar * bi + ai * br - (xu[b3].x * yu[b4].y + xu[b3].y * yu[b4].x) -
-                                 (xd[b3].x * yd[b4].y + xd[b3].y * yd[b4].x);
-                    sr[b3][b4] += s * tr;
-                    si[b3][b4] += s * ti;
+                    const V bb = bsh[b][b3 * NB + b4];
+                    R r = sr[b3][b4], i = si[b3][b4];
+                    r += ar * bb.x;
+                    r += an * bb.y;
+                    r += xur[b3] * o.yu[b4].x;
+                    r += xui[b3] * yun[b4];
+                    r += xdr[b3] * o.yd[b4].x;
+                    r += xdi[b3] * ydn[b4];
+                    i += ar * bb.y;
+                    i += ai * bb.x;
+                    i += xur[b3] * o.yu[b4].y;
+                    i += xui[b3] * o.yu[b4].x;
+                    i += xdr[b3] * o.yd[b4].y;
+                    i += xdi[b3] * o.yd[b4].x;
+                    sr[b3][b4] = r;
+                    si[b3][b4] = i;
                 }
-        }
+        };
+        run(load, compute);
     }
+    if (!act) return;
     // entry ((p*N + K2)*NB^2 + b3*NB + b4)*side + col
 #pragma unroll
     for (int b3 = 0; b3 < NB; ++b3)
@@ -229,8 +310,8 @@ __global__ __launch_bounds__(256) void mo_rows_kernel(MoArgs a) {
 template <typename R>
 hipError_t launch_mo(const MoArgs &a, hipStream_t st) {
     const int64_t n = a.side / ((int64_t)a.nb * a.nb);
-    const int64_t threads = a.nb <= 4 ? (int64_t)a.planes * n * a.side : a.total;
-    const int64_t blocks = (threads + 255) / 256;
+    // rows kernel: whole blocks per (plane, K2) row; entry kernel: one thread per entry
+    const int64_t blocks = a.nb <= 4 ? (int64_t)a.planes * n * ((a.side + 255) / 256) : (a.total + 255) / 256;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
     const dim3 g((unsigned)blocks), b(256);
     switch (a.nb) {
