@@ -539,6 +539,8 @@ def main():
                     help="packed operands copied straight into LDS (the autotuner may switch)")
     ap.add_argument("--deep", action="store_true",
                     help="packed operands, 512-thread blocks, three LDS buffers")
+    ap.add_argument("--persistent", action="store_true",
+                    help="packed plans launch a persistent grid walking the tiles (G4_F_PERSISTENT)")
     ap.add_argument("--graph", action="store_true",
                     help="replay recorded HIP graphs of the passes (warm-up covers the recording)")
     ap.add_argument("--plain-measurements", type=int, default=64)
@@ -585,7 +587,8 @@ def main():
     ring = args.workload == "ring6x6"
     acc = g4.G4_ACC_C128 if args.acc == "c128" else g4.G4_ACC_C64_KAHAN
     vflags = ((g4.G4_F_GRAPH if args.graph else 0) | (g4.G4_F_MFMA if args.mfma else 0) |
-              (g4.G4_F_PACKED if args.packed else 0) | (g4.G4_F_PACKED_DEEP if args.deep else 0))
+              (g4.G4_F_PACKED if args.packed else 0) | (g4.G4_F_PACKED_DEEP if args.deep else 0) |
+              (g4.G4_F_PERSISTENT if args.persistent else 0))
     ring_w = C4_RING.with_(channels=g4.G4_PH_MAGNETIC, q_begin=3 * 72, q_end=4 * 72)
     ring_runs = [((3 - s) % 8 * 16, 16) for s in range(8)]   # rank 3's order: own, then from the left
 

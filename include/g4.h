@@ -152,9 +152,18 @@ enum {
                                  * 16 + direct vectors) more device bytes, ldp = Nc * pcb + 1
                                  rounded up to 8, pcb = Nwg rounded up to 8.  Combines with
                                  G4_F_MFMA only (see there). */
-    G4_F_PACKED_DEEP = 32u    /* as G4_F_PACKED, with 512-thread blocks and three LDS buffers
+    G4_F_PACKED_DEEP = 32u,   /* as G4_F_PACKED, with 512-thread blocks and three LDS buffers
                                  (copies run two measurements ahead); one or two K2 rows per
                                  thread, tile = 512/nw or 1024/nw.  Exclusive with the others. */
+    G4_F_PERSISTENT = 64u     /* packed plans (G4_F_PACKED, with or without G4_F_MFMA, and
+                                 G4_F_PACKED_DEEP) launch a persistent grid: as many blocks as
+                                 the device holds at once (the occupancy calculator's blocks per
+                                 CU times the CU count, rounded down to a multiple of 8), each
+                                 walking the pass's work tiles with a grid stride, in place of
+                                 one block per tile; every pass still fuses all its measurements
+                                 in one launch.  Other plans ignore the flag.  Slower than one
+                                 block per tile on MI355X (tiles advance in a fixed stride instead
+                                 of being handed to whichever block finishes first). */
 };
 
 /* slice-update kernel variants (g4_stats, g4_set_plan, g4_tune_result) */

@@ -83,6 +83,7 @@ struct Plan {
     int variant;       // 0 VALU kernel, 1 MFMA direct term, 2 packed operands, 3 deep packed,
                        // 4 packed with the direct term on MFMA (G4_VARIANT_*)
     int split;         // direct term from split operands on MFMA: 0 no, 1 bf16 hi+lo, 2 fp16 hi+lo
+    int persistent;    // packed variants under G4_F_PERSISTENT: a persistent grid
     int batch;         // measurements per pass
     int mgroup;        // transfer planes per work tile (compile-time bound)
     int tile;          // K2 rows per work tile
@@ -149,7 +150,7 @@ int validate(const g4_config *c, Plan *p) {
     if (c->acc < G4_ACC_C128 || c->acc > G4_ACC_C64) return fail(G4_E_ARG, "acc=%d", c->acc);
     if (c->mode != G4_MODE_PLAIN && c->mode != G4_MODE_BATCHED) return fail(G4_E_ARG, "mode=%d", c->mode);
     if (c->flags & ~(uint32_t)(G4_F_CHECK_FINITE | G4_F_KERNEL_TIMING | G4_F_GRAPH | G4_F_MFMA | G4_F_PACKED |
-                               G4_F_PACKED_DEEP))
+                               G4_F_PACKED_DEEP | G4_F_PERSISTENT))
         return fail(G4_E_ARG, "unknown flags 0x%x", c->flags);
     if (c->device < 0) return fail(G4_E_ARG, "device=%d", c->device);
     if (c->mode == G4_MODE_PLAIN) {
@@ -206,6 +207,7 @@ int validate(const g4_config *c, Plan *p) {
     // read as zeros there, with no test in the arithmetic loop)
     if (P.split && P.variant == G4_VARIANT_VALU) P.variant = G4_VARIANT_PACKED;
     const bool packed = uses_pack(P.variant);
+    P.persistent = packed && (c->flags & G4_F_PERSISTENT) ? 1 : 0;
     if (packed && P.kind != 2) return fail(G4_E_UNSUPPORTED, "packed operands need batched FP32 products");
     if (P.variant == G4_VARIANT_PACKED_MFMA) {
         // MFMA accumulator layout: per plane pair, 8 K2 rows x 2 planes x 64 columns
@@ -514,10 +516,10 @@ void log_plan(const g4_slice *h, const char *why) {
     static const char *names[] = {"valu", "mfma-direct", "packed", "packed-deep", "packed-mfma-direct"};
     std::fprintf(stderr,
                  "g4: %s: channels 0x%x, %llu entries per channel, kind %d, variant %s, tile %d, pass %d, "
-                 "rows/thread %d, plane group %d, %d work tiles, %llu device bytes\n",
+                 "rows/thread %d, plane group %d, %d work tiles%s, %llu device bytes\n",
                  why, h->cfg.channels, (unsigned long long)P.entries, P.kind,
                  P.variant >= 0 && P.variant <= 4 ? names[P.variant] : "?", P.tile, P.batch, P.ept, P.mgroup,
-                 h->nitems, (unsigned long long)P.total_bytes);
+                 h->nitems, P.persistent ? " (persistent grid)" : "", (unsigned long long)P.total_bytes);
 }
 
 void drop_graphs(g4_slice *h) {
@@ -711,6 +713,7 @@ int enqueue_pass(g4_slice *h, const void *pu, const void *pd, const double *ds, 
     ua.acc[2] = h->acc[2];
     ua.acc_kind = h->cfg.acc;
     ua.tile = P.tile;
+    ua.persistent = P.persistent;
     ua.d = P.d;
     ua.t = tables_of(h);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -966,6 +969,7 @@ int noalloc_accumulate(const g4_config *cfg, void *const acc[3], const void *G_u
         ua.acc[2] = acc[2];
         ua.acc_kind = cfg->acc;
         ua.tile = P.tile;
+        ua.persistent = P.persistent;
         ua.d = P.d;
         ua.t = t;
         G4_NA(launch_update(P.kind, (int)cfg->channels, P.ept, P.mgroup, (int)items.size(), P.variant, ua, st));
@@ -1291,6 +1295,7 @@ int g4_set_plan(g4_slice *h, int32_t tile, int32_t batch, int32_t variant) {
     h->P.ept = P.ept;
     h->P.tile = P.tile;
     h->P.variant = P.variant;
+    h->P.persistent = P.persistent;
     h->P.batch = batch ? batch : keep_batch;
     h->cfg.tile = c.tile;
     h->cfg.flags = c.flags;
@@ -1441,6 +1446,7 @@ int install_plan(g4_slice *h, const g4_config &base, const std::vector<int32_t> 
     h->P.ept = P.ept;
     h->P.tile = P.tile;
     h->P.variant = P.variant;
+    h->P.persistent = P.persistent;
     h->P.batch = batch;
     h->cfg.flags = (h->cfg.flags & G4_F_GRAPH) | (cc.flags & ~(uint32_t)G4_F_GRAPH);
     h->cfg.tile = cc.tile;

@@ -94,6 +94,8 @@ struct UpdateArgs {
     int nitems;               // work tiles in the list (one block per tile)
     int skip_direct;          // packed kernel: 1 = the PH direct term is added by
                               // direct_split_kernel; the tile's direct vectors read as zeros
+    int persistent;           // packed kernels: 1 = a grid of co-resident blocks walks the tiles
+                              // with a grid stride, 0 = one block per tile
     Dims d;
     Tables t;
 };

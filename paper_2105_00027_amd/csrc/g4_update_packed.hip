@@ -31,6 +31,8 @@
 //      (complex64 pairs).
 #include "g4_update.hpp"
 
+#include <algorithm>
+
 #if !defined(G4_EPT)
 #error "G4_EPT must be defined"
 #endif
@@ -72,14 +74,29 @@ __device__ __forceinline__ void wait_vm(int n) {
     }
 }
 
-// One block per tile.
+// One block per tile, or (a.persistent) as many blocks as the device holds at
+// once, each walking the tile list with a grid stride.  The persistent grid
+// is a multiple of 8, so that block i (dispatched to XCD i % 8) still takes
+// the tiles the list's order put on that XCD.
 hipError_t launch_block_per_tile(const void *fn, int nitems, int nth, size_t lds, const UpdateArgs &a,
                                  hipStream_t s) {
     if (hipError_t e = ensure_lds_limit(fn, lds); e != hipSuccess) return e;
     UpdateArgs arg = a;
     arg.nitems = nitems;
     void *params[] = {&arg};
-    return hipLaunchKernel(fn, dim3(nitems), dim3(nth), params, lds, s);
+    int grid = nitems;
+    if (a.persistent) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) return e;
+        if (hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            e != hipSuccess)
+            return e;
+        if (hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nth, lds); e != hipSuccess)
+            return e;
+        const int resident = std::max(8, per_cu * cus / 8 * 8);
+        grid = std::max(1, std::min(nitems, resident));
+    }
+    return hipLaunchKernel(fn, dim3(grid), dim3(nth), params, lds, s);
 }
 
 // Geometry of a tile's staging buffer, known at run time (GeoRt) or, for

@@ -30,8 +30,8 @@ G4_IN_C128, G4_IN_C64 = 0, 1
 G4_PROD_F64, G4_PROD_F32, G4_PROD_BF16X2, G4_PROD_F16X2 = 0, 1, 2, 3
 G4_ACC_C128, G4_ACC_C64_KAHAN, G4_ACC_C64 = 0, 1, 2
 G4_MODE_PLAIN, G4_MODE_BATCHED = 0, 1
-G4_F_CHECK_FINITE, G4_F_KERNEL_TIMING, G4_F_GRAPH, G4_F_MFMA, G4_F_PACKED, G4_F_PACKED_DEEP = \
-    1, 2, 4, 8, 16, 32
+G4_F_CHECK_FINITE, G4_F_KERNEL_TIMING, G4_F_GRAPH, G4_F_MFMA, G4_F_PACKED, G4_F_PACKED_DEEP, G4_F_PERSISTENT = \
+    1, 2, 4, 8, 16, 32, 64
 G4_VARIANT_VALU, G4_VARIANT_MFMA, G4_VARIANT_PACKED, G4_VARIANT_PACKED_DEEP, G4_VARIANT_PACKED_MFMA = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {0: "G4_OK", -1: "G4_E_ARG", -2: "G4_E_OOM", -3: "G4_E_HIP", -4: "G4_E_STATE",

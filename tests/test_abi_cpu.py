@@ -57,7 +57,7 @@ BAD = [
     dict(q_list=[0, 1, 1] + list(range(3, 16))), dict(q_list=[0] * 15 + [16]),
     dict(q_begin=5, q_end=5), dict(q_end=129), dict(q_begin=-1), dict(channels=0),
     dict(channels=256), dict(channels=9), dict(channels=7 | 56), dict(channels=4 | 64), dict(channels=32 | 128),
-    dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9), dict(flags=64),
+    dict(g_in=2), dict(prod=9), dict(acc=3), dict(mode=2), dict(flags=1 << 9), dict(flags=128),
     dict(device=-1), dict(mode=1, max_batch=0), dict(mode=1, max_batch=257),
     dict(mode=0, prod=1), dict(mode=0, acc=1), dict(mode=1, max_batch=8, prod=0, g_in=1),
     dict(tile=-1),
@@ -210,6 +210,16 @@ def test_index_maps_bit_exact(w):
     iQ = np.arange(w.q0, w.q1)
     assert np.array_equal(pq, np.asarray(w.qs)[iQ // w.nwex])
     assert np.array_equal(pm, iQ % w.nwex)
+
+
+def test_persistent_flag_accepted_everywhere():
+    """G4_F_PERSISTENT changes only how the packed plans launch (a persistent
+    grid instead of one block per tile): accepted with every plan, no device
+    memory of its own."""
+    for f in (g4.G4_F_PACKED, g4.G4_F_PACKED | g4.G4_F_MFMA, g4.G4_F_PACKED_DEEP, 0, g4.G4_F_MFMA):
+        a = base(mode=1, max_batch=16, prod=1, g_in=1, flags=f)
+        b = base(mode=1, max_batch=16, prod=1, g_in=1, flags=f | g4.G4_F_PERSISTENT)
+        assert g4.g4_slice_size(b) == g4.g4_slice_size(a), f
 
 
 def test_packed_mfma_plan_accepted_and_bounded():

@@ -164,6 +164,34 @@ def test_batched_fp32_packed_mfma(w, count, B, g_in, acc):
     check(got, oracle_out(w, count, w.channels), 1e-6)
 
 
+# 4x2 cluster, all 64 planes of Nwex = 8: 4096 work tiles of 8 rows, more than
+# the device holds blocks at once, so a persistent grid walks several each
+W8_BIG = Workload("w8-big", lx=4, ly=2, nw=64, nwex=8, nq=8, q_begin=0, q_end=64, beta=6.0, seed=28, wid=28,
+                  channels=PH_MAGNETIC)
+
+
+@pytest.mark.parametrize("acc", [0, 1], ids=["acc-c128", "acc-kahan"])
+@pytest.mark.parametrize("w,flags,variant", [
+    (W8_BIG, "packed", 2), (W8_BIG.with_(channels=PH_MAGNETIC | PH_CHARGE), "packed-mfma", 4),
+    (W8_BIG, "packed-mfma", 4), (MULTI, "packed", 2), (MULTI.with_(channels=PH_MAGNETIC), "deep", 3)],
+    ids=["w8big-packed", "w8big-mfma-mag+chg", "w8big-mfma", "multi-packed-all", "multi-deep"])
+def test_persistent_grid(w, flags, variant, acc):
+    """G4_F_PERSISTENT: the packed kernels on a persistent grid walking more
+    work tiles than it has blocks (every tile of a block after its first
+    reuses the block's LDS), passes with a ragged last one."""
+    g4 = g4mod()
+    f = {"packed": g4.G4_F_PACKED, "packed-mfma": g4.G4_F_PACKED | g4.G4_F_MFMA,
+         "deep": g4.G4_F_PACKED_DEEP}[flags] | g4.G4_F_PERSISTENT
+    count, B = 5, 2
+    print(f"\ncase {w.name} {flags} channels={w.channels} acc={acc}", flush=True)
+    gu, gd, s = host_inputs(w, count)
+    cfg = config_for(w, mode=1, prod=1, g_in=1, acc=acc, batch=B, flags=f)
+    got, st = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
+    assert st["variant"] == variant
+    assert st["launches"] == -(-count // B)
+    check(got, oracle_out(w, count, w.channels), 1e-6)
+
+
 @pytest.mark.parametrize("g_in", [0, 1], ids=["c128-in", "c64-in"])
 @pytest.mark.parametrize("acc", [0, 1, 2], ids=["acc-c128", "acc-kahan", "acc-c64"])
 @pytest.mark.parametrize("channels", [PH_MAGNETIC, PH_CHARGE, PH_MAGNETIC | PH_CHARGE],
