@@ -3,9 +3,11 @@ with the FP64 oracle.
 
 Bars: FP64 products 1e-12, FP32 products 1e-6 (relative Frobenius, Eq. (2)/(3)
 on real and imaginary parts, and the small half of the entries), per channel.
-Shapes: two and three orbitals, a transfer list in a different order, a slice
-cut through a transfer momentum, entry counts that are not multiples of the
-256-thread block; 70 measurements (three launches of at most 32).  Argument
+Shapes: one to five orbitals (four: rows of 384 columns, a full and a partial
+block each; five: the one-thread-per-entry kernel), a transfer list in a
+different order, a slice cut through a transfer momentum, entry counts that
+are not multiples of the 256-thread block; 70 measurements (three launches of
+at most 32).  Argument
 errors are rejected before any launch.
 """
 import numpy as np
@@ -45,8 +47,8 @@ def run(w, nb, channels, prod, gu, gd, s):
 
 
 @pytest.mark.parametrize("prod", [0, 1], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("w,nb,count", [(W2, 2, 5), (W3, 3, 3), (W2, 1, 70)],
-                         ids=["3x1-nb2", "2x2-nb3", "3x1-nb1-70meas"])
+@pytest.mark.parametrize("w,nb,count", [(W2, 2, 5), (W3, 3, 3), (W2, 1, 70), (W3, 4, 3), (W2, 5, 2)],
+                         ids=["3x1-nb2", "2x2-nb3", "3x1-nb1-70meas", "2x2-nb4", "3x1-nb5-entry-kernel"])
 def test_matches_oracle(w, nb, count, prod):
     print("\ncase %s nb=%d count=%d prod=%d" % (w.name, nb, count, prod), flush=True)
     gu, gd, s = inputs(w, nb, count, 10 * nb + count)
