@@ -252,15 +252,16 @@ def test_split_precision_direct_term(w, count, B, flags, prod):
         assert e_split < 10 * e32 + 1e-7
 
 
-@pytest.mark.parametrize("flags", [0, 16], ids=["valu", "packed"])
+@pytest.mark.parametrize("flags", [0, 16, 24, 16 | 64], ids=["valu", "packed", "packed-mfma", "packed-persistent"])
 def test_graph_replay_matches_direct_passes(flags):
     """G4_F_GRAPH: passes on known inputs replay a recorded graph.  Every replay
     is checked, bit for bit, against a slice running the same passes directly,
     with eager work, input changes, new weights and synchronizations between
-    replays, and across a plan change (which drops the recordings)."""
+    replays, and across a plan change (which drops the recordings).  The
+    packed MFMA plan takes the PH channels only."""
     import torch
     g4 = g4mod()
-    w = MULTI
+    w = MULTI.with_(channels=PH_MAGNETIC | PH_CHARGE) if flags & 8 else MULTI
     gu, gd, s = host_inputs(w, 6)
     du, dd = to_dev(gu, 1), to_dev(gd, 1)
     base = dict(mode=1, prod=1, g_in=1, acc=1, batch=3)
@@ -281,7 +282,7 @@ def test_graph_replay_matches_direct_passes(flags):
                 g4.g4_accumulate(h, du[half], dd[half], sg)
             torch.cuda.synchronize()
             _ = (du.abs().sum() + dd.abs().sum()).item()    # eager work between replays
-            for ch in (1, 2, 4):
+            for ch in (c for c in (1, 2, 4) if w.channels & c):
                 a = g4.g4_readback(hd, ch)
                 b = g4.g4_readback(hg, ch)
                 assert np.array_equal(a, b), (it, ch)
