@@ -34,19 +34,37 @@ def _meta(h: g4.Slice) -> dict:
 
 
 def save_slice(h: g4.Slice, path: str, chunk: int = 1 << 22) -> None:
-    """Write every channel of slice h to the directory `path` (created)."""
+    """Write every channel of slice h to the directory `path` (created).
+
+    The device-to-host readback of one range overlaps the file write of the
+    previous one (a writer thread; the readback and the copy into the mapped
+    file both run outside the interpreter lock), so at most two ranges are
+    held in host memory."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(path, exist_ok=True)
     meta = _meta(h)
-    for ch, name in CHANNELS.items():
-        if not meta["channels"] & ch:
-            continue
-        out = np.lib.format.open_memmap(os.path.join(path, name + ".npy"), mode="w+",
-                                        dtype=np.complex128, shape=(h.entries,))
-        for first in range(0, h.entries, chunk):
-            count = min(chunk, h.entries - first)
-            out[first:first + count] = g4.g4_readback(h, ch, first, count)
-        out.flush()
-        del out
+
+    def put(out, first, data):
+        out[first:first + data.shape[0]] = data
+
+    with ThreadPoolExecutor(max_workers=1) as writer:
+        for ch, name in CHANNELS.items():
+            if not meta["channels"] & ch:
+                continue
+            out = np.lib.format.open_memmap(os.path.join(path, name + ".npy"), mode="w+",
+                                            dtype=np.complex128, shape=(h.entries,))
+            pending = None
+            for first in range(0, h.entries, chunk):
+                count = min(chunk, h.entries - first)
+                data = g4.g4_readback(h, ch, first, count)
+                if pending is not None:
+                    pending.result()
+                pending = writer.submit(put, out, first, data)
+            if pending is not None:
+                pending.result()
+            out.flush()
+            del out
     with open(os.path.join(path, "meta.json"), "w") as f:
         json.dump(meta, f, indent=1)
 
