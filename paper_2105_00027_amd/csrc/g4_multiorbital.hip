@@ -13,7 +13,7 @@
 //
 // A launch covers up to 32 measurements of one channel over up to 256 planes
 // and keeps the sums over the measurements in registers, then reads, adds and
-// writes each entry once.  For nb <= 4 (mo_rows_kernel) a thread owns one
+// writes each entry once.  For nb <= 8 (mo_rows_kernel) a thread owns one
 // column (K1, b1, b2) of one (plane, K2) and all nb^2 rows (b3, b4): per
 // measurement it loads the column's a = G(K1+Q b1, K1 b2) once and the nb
 // exchange operands of each side (G(K2 b3, K1 b2) and G(K1+Q b1, K2+Q b4):
@@ -311,7 +311,7 @@ template <typename R>
 hipError_t launch_mo(const MoArgs &a, hipStream_t st) {
     const int64_t n = a.side / ((int64_t)a.nb * a.nb);
     // rows kernel: whole blocks per (plane, K2) row; entry kernel: one thread per entry
-    const int64_t blocks = a.nb <= 4 ? (int64_t)a.planes * n * ((a.side + 255) / 256) : (a.total + 255) / 256;
+    const int64_t blocks = a.nb <= 8 ? (int64_t)a.planes * n * ((a.side + 255) / 256) : (a.total + 255) / 256;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
     const dim3 g((unsigned)blocks), b(256);
     switch (a.nb) {
@@ -319,6 +319,10 @@ hipError_t launch_mo(const MoArgs &a, hipStream_t st) {
         case 2: hipLaunchKernelGGL((mo_rows_kernel<R, 2>), g, b, 0, st, a); break;
         case 3: hipLaunchKernelGGL((mo_rows_kernel<R, 3>), g, b, 0, st, a); break;
         case 4: hipLaunchKernelGGL((mo_rows_kernel<R, 4>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((mo_rows_kernel<R, 5>), g, b, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((mo_rows_kernel<R, 6>), g, b, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((mo_rows_kernel<R, 7>), g, b, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((mo_rows_kernel<R, 8>), g, b, 0, st, a); break;
         default: hipLaunchKernelGGL(mo_kernel<R>, g, b, 0, st, a); break;
     }
     return hipGetLastError();

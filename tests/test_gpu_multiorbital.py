@@ -3,8 +3,9 @@ with the FP64 oracle.
 
 Bars: FP64 products 1e-12, FP32 products 1e-6 (relative Frobenius, Eq. (2)/(3)
 on real and imaginary parts, and the small half of the entries), per channel.
-Shapes: one to five orbitals (four: rows of 384 columns, a full and a partial
-block each; five: the one-thread-per-entry kernel), a transfer list in a
+Shapes: one to nine orbitals (four: rows of 384 columns, a full and a partial
+block each; six: rows of 864 columns; nine: the one-thread-per-entry
+kernel), a transfer list in a
 different order, a slice cut through a transfer momentum, entry counts that
 are not multiples of the 256-thread block; 70 measurements (three launches of
 at most 32).  Argument
@@ -47,8 +48,10 @@ def run(w, nb, channels, prod, gu, gd, s):
 
 
 @pytest.mark.parametrize("prod", [0, 1], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("w,nb,count", [(W2, 2, 5), (W3, 3, 3), (W2, 1, 70), (W3, 4, 3), (W2, 5, 2)],
-                         ids=["3x1-nb2", "2x2-nb3", "3x1-nb1-70meas", "2x2-nb4", "3x1-nb5-entry-kernel"])
+@pytest.mark.parametrize("w,nb,count", [(W2, 2, 5), (W3, 3, 3), (W2, 1, 70), (W3, 4, 3), (W2, 5, 2), (W3, 6, 2),
+                                         (W2, 7, 2), (W2, 8, 2), (W2, 9, 1)],
+                         ids=["3x1-nb2", "2x2-nb3", "3x1-nb1-70meas", "2x2-nb4", "3x1-nb5", "2x2-nb6",
+                              "3x1-nb7", "3x1-nb8", "3x1-nb9-entry-kernel"])
 def test_matches_oracle(w, nb, count, prod):
     print("\ncase %s nb=%d count=%d prod=%d" % (w.name, nb, count, prod), flush=True)
     gu, gd, s = inputs(w, nb, count, 10 * nb + count)
