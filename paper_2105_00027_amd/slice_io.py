@@ -78,10 +78,16 @@ def load_slice(h: g4.Slice, path: str, chunk: int = 1 << 22) -> None:
     for k in ("lx", "ly", "nw", "nwex", "nq", "q_list", "q_begin", "q_end", "channels", "entries"):
         if meta[k] != mine[k]:
             raise ValueError("slice file %s: %s is %r, the slice has %r" % (path, k, meta[k], mine[k]))
+    # the device load reads each range straight from the mapped file (no
+    # host copy of its own; a reader thread that copied the next range out
+    # ahead took 0.21 s against 0.08 s for a 2.15 GB channel in page cache)
     for ch, name in CHANNELS.items():
         if not meta["channels"] & ch:
             continue
         src = np.load(os.path.join(path, name + ".npy"), mmap_mode="r")
+        if src.shape != (h.entries,):
+            raise ValueError("slice file %s: %s holds %r entries, the slice has %d"
+                             % (path, name, src.shape, h.entries))
         for first in range(0, h.entries, chunk):
             count = min(chunk, h.entries - first)
             g4.g4_load(h, ch, first, np.asarray(src[first:first + count]))
