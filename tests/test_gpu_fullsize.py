@@ -61,13 +61,15 @@ def test_plain_slice_full_size():
 
 FULL_PLANS = [(0, 0, 16, 0), (1, 0, 16, 0), (0, 8, 16, 0), (0, 16, 16, 0), (1, 16, 16, 0), (0, 32, 16, 0),
               (0, 24, 16, 0), (1, 24, 16, 0),
-              # the benchmark's plan: packed operands, 8-row tiles, passes of 64
-              (0, 16, 64, 8), (1, 16, 64, 8)]
+              # the benchmark's plans (the autotuner picks one of the two): packed
+              # operands, 8-row tiles, passes of 64, direct term on the VALU or on MFMA
+              (0, 16, 64, 8), (1, 16, 64, 8), (0, 24, 64, 8), (1, 24, 64, 8)]
 
 
 @pytest.mark.parametrize("acc,flags,B,tile", FULL_PLANS,
                          ids=["acc-c128", "acc-kahan", "mfma", "packed", "packed-kahan", "deep",
-                              "packed-mfma", "packed-mfma-kahan", "bench-plan", "bench-plan-kahan"])
+                              "packed-mfma", "packed-mfma-kahan", "bench-plan", "bench-plan-kahan",
+                              "bench-plan-mfma", "bench-plan-mfma-kahan"])
 def test_batched_full_size(acc, flags, B, tile):
     """The same slice, 4096 measurements in passes of B, complex64 G, FP32 products."""
     g4 = g4mod()
