@@ -461,7 +461,9 @@ void g4_destroy(g4_slice *h);
  * a plan (init, g4_set_plan, g4_autotune); G4_AUTOTUNE_CACHE names the
  * autotuner's cache file; each pass of g4_accumulate is a roctx range
  * ("g4 pass: ...", seen by rocprofv3 --marker-trace) when the roctx library
- * is present, G4_ROCTX=0 turns the ranges off.
+ * is present, G4_ROCTX=0 turns the ranges off.  For measurements,
+ * G4_TILE_ORDER=0..3 sets the order of the work tiles and G4_PLANE_GROUP=1|4|8
+ * the transfer planes per tile (defaults: by variant; 8, 4 or 1 by Nwex).
  *
  * Message of the last failing call on this host thread ("" if none).
  * Paper: no passage (error reporting of this interface only). */

@@ -104,7 +104,17 @@ bool uses_pack(int variant) {
     return variant == G4_VARIANT_PACKED || variant == G4_VARIANT_PACKED_DEEP || variant == G4_VARIANT_PACKED_MFMA;
 }
 
-int choose_mgroup(int nwex) { return nwex == 1 ? 1 : (nwex <= 4 ? 4 : 8); }
+// Transfer planes per work tile: 8 when Nwex allows, else 4, else 1.
+// G4_PLANE_GROUP=1|4|8 in the environment sets it instead, for measurements
+// (a group larger than Nwex is always partial; the packed MFMA plans, which
+// need plane pairs, reject 1).
+int choose_mgroup(int nwex) {
+    if (const char *e = std::getenv("G4_PLANE_GROUP")) {
+        const int g = std::atoi(e);
+        if (g == 1 || g == 4 || g == 8) return g;
+    }
+    return nwex == 1 ? 1 : (nwex <= 4 ? 4 : 8);
+}
 
 // Largest K2-rows-per-thread count keeping the register accumulators and the
 // LDS tiles modest; tile = ept * (256 / nw).

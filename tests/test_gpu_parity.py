@@ -454,6 +454,21 @@ def test_one_hot_support_nw64(flags, tile, channels):
         assert np.array_equal(got[channels] != 0, want != 0), (spin, r, c)
 
 
+@pytest.mark.parametrize("group,flags", [(4, 16), (4, 24), (1, 0), (8, 16)],
+                         ids=["g4-packed", "g4-packed-mfma", "g1-valu", "g8-packed-nwex3"])
+def test_plane_group_override(group, flags, monkeypatch):
+    """G4_PLANE_GROUP sets the transfer planes per work tile (a measurement
+    aid): groups of 4 or 1 on Nwex = 8, groups of 8 on Nwex = 3 (always
+    partial), against the oracle."""
+    monkeypatch.setenv("G4_PLANE_GROUP", str(group))
+    g4 = g4mod()
+    w = MULTI.with_(channels=PH_MAGNETIC | PH_CHARGE) if group == 8 else W8.with_(channels=PH_MAGNETIC | PH_CHARGE)
+    gu, gd, s = host_inputs(w, 5)
+    cfg = config_for(w, mode=1, prod=1, g_in=1, acc=0, batch=2, flags=flags)
+    got, st = run_slice(cfg, to_dev(gu, 1), to_dev(gd, 1), s)
+    check(got, oracle_out(w, 5, w.channels), 1e-6)
+
+
 def test_determinism_bitwise():
     """Every slice entry is written by one thread, no atomics: two runs agree
     bit for bit (also a race check of the LDS staging)."""
