@@ -234,7 +234,7 @@ __global__ __launch_bounds__(NTH, AR ? 3 : 2) void update_packed_kernel(UpdateAr
     if (tid < a.batch) sg[tid] = (float)a.sign[tid];
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        __syncthreads();   // a previous tile's LDS reads are done (the launch uses one block per tile)
+        __syncthreads();   // the previous tile's LDS reads are done (a persistent grid walks several)
         // ---- decode the tile -------------------------------------------------
         const int4 it = a.t.items[item];
         const int4 gr = a.t.groups[it.x];
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(256, CH == 3 ? 2 : 3) void update_packed_mfma_kerne
     const unsigned fb = (unsigned)(pgf.nG * 16 + pgf.nA * 16 + (pw0 * TR + rg + (l & 3)) * 8);
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        __syncthreads();   // a previous tile's LDS reads are done (the launch uses one block per tile)
+        __syncthreads();   // the previous tile's LDS reads are done (a persistent grid walks several)
         const int4 it = a.t.items[item];
         const int4 gr = a.t.groups[it.x];
         const int q = gr.x, m_lo = gr.y, M = gr.z, p0 = gr.w;
