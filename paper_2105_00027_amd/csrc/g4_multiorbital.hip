@@ -17,8 +17,9 @@
 // column (K1, b1, b2) of one (plane, K2) and all nb^2 rows (b3, b4): per
 // measurement it loads the column's a = G(K1+Q b1, K1 b2) once and the nb
 // exchange operands of each side (G(K2 b3, K1 b2) and G(K1+Q b1, K2+Q b4):
-// one per b3, one per b4), about a quarter of a vector load per entry and
-// measurement instead of eight; the nb^2 values b = G(K2 b3, K2+Q b4) are
+// one per b3, one per b4), both spins: 2 + 4 nb vector loads for nb^2 entry
+// updates (18 for 16 at nb = 4) instead of eight per entry update; the nb^2
+// values b = G(K2 b3, K2+Q b4) are
 // the same for the whole block (a block covers one (plane, K2) row), which
 // forms them once per launch into LDS.  Lanes run along the column, so each
 // of the nb^2 output rows is written as one contiguous run.  Larger nb takes the
