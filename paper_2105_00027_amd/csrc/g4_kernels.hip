@@ -97,20 +97,13 @@ __global__ __launch_bounds__(256) void pack_gather_kernel(PackArgs pa) {
     const int pcb = pa.pcb, pad = pcb - nwg;
     // source column c = k*nwg + i -> packed column k*pcb + i
     auto dcol = [&](int c) { const int k = c / nwg; return c + k * pad; };
-    if ((ng & 1) == 0) {
-        // rows start on an even element: pairs are 16-byte aligned
-        const float4 *pu = reinterpret_cast<const float4 *>(su);
-        const float4 *pd = reinterpret_cast<const float4 *>(sd);
-        for (int j = threadIdx.x; j < ng / 2; j += 256) {
-            const float4 u = pu[j], w = pd[j];
-            d[dcol(2 * j)] = float4{u.x, u.y, w.x, w.y};
-            d[dcol(2 * j + 1)] = float4{u.z, u.w, w.z, w.w};
-        }
-    } else {
-        for (int c = threadIdx.x; c < ng; c += 256) {
-            const float2 u = su[c], w = sd[c];
-            d[dcol(c)] = float4{u.x, u.y, w.x, w.y};
-        }
+    // lane c: source column c of both spins (8-byte loads, contiguous across
+    // the wave) into packed column dcol(c), so that each store instruction
+    // writes one contiguous run (16-byte loads of two columns, whose stores
+    // then alternate between chunks, took 0.71 against 0.66 ms per pass)
+    for (int c = threadIdx.x; c < ng; c += 256) {
+        const float2 u = su[c], w = sd[c];
+        d[dcol(c)] = float4{u.x, u.y, w.x, w.y};
     }
     // zeros: each block's padding columns, then the row's tail [nc*pcb, ldp)
     for (int e = threadIdx.x; e < nc * pad; e += 256) {
