@@ -491,11 +491,13 @@ def leg_line(w, res, B, steps, g_bytes, acc_bytes, plan_acc, direct_elsewhere=Fa
             "pass_batch": st["batch"], "tile": st["tile"], "kernel_variant": VARIANTS[st["variant"]],
             "kernel": {"name": KERNELS[st["variant"]], "avg_launch_ms": launch_s * 1e3,
                        "launches": st["timed_launches"]}}
-    line["roofline"] = roofline(w.entries, w.ng, st["batch"], g_bytes, acc_bytes, w.channels, launch_s,
-                                st["variant"], direct_elsewhere)
-    line["roofline"]["traffic"] = measured_traffic(
-        {"mode": 1, "acc": plan_acc, "batch": st["batch"], "tile": st["tile"], "variant": st["variant"],
-         "channels": w.channels, "entries": w.entries})
+    line["roofline"] = None
+    if launch_s > 0:     # no timed launch (--no-batched): no kernel time to put against a roof
+        line["roofline"] = roofline(w.entries, w.ng, st["batch"], g_bytes, acc_bytes, w.channels, launch_s,
+                                    st["variant"], direct_elsewhere)
+        line["roofline"]["traffic"] = measured_traffic(
+            {"mode": 1, "acc": plan_acc, "batch": st["batch"], "tile": st["tile"], "variant": st["variant"],
+             "channels": w.channels, "entries": w.entries})
     if "errors" in res:
         line["error"] = res["errors"][1] if list(res["errors"]) == [1] else \
             {"channel_%d" % ch: e for ch, e in res["errors"].items()}
